@@ -1,0 +1,198 @@
+/*
+ * sg.h -- C interface of the MI355X stochastic Galerkin (SG) solver library.
+ *
+ * Problem (Section 2 of Sousedik, Ghanem, Phipps, "Hierarchical Schur
+ * complement preconditioner for the stochastic Galerkin finite element
+ * methods"): -div(a(x, xi) grad u) = f on the unit square, u = 0 on the
+ * boundary, with a linear Karhunen-Loeve coefficient
+ *     a(x, xi) = theta0 + sigma * sum_{k=1..M} s_k phi_k(x) xi_k,
+ * xi_k i.i.d. standard Gaussian, Q1 elements on an n_e x n_e grid and a
+ * normalised Hermite chaos of total degree <= p (P = (M+p)!/(M! p!)
+ * functions). The discrete system is sum_k (G_k (x) K_k) vec(U) = vec(F)
+ * (eq. (global-system), eq. (global-matrix)).
+ *
+ * Layout conventions used by every call
+ *   n = (n_e - 1)^2 interior nodes, node (ix, iy), 1 <= ix, iy <= n_e - 1,
+ *   has index (iy - 1)(n_e - 1) + (ix - 1) (x1 fastest).
+ *   A block of chaos coefficients is an n x P column-major FP64 array in
+ *   device memory, leading dimension n: column j holds chaos coefficient j.
+ *   Chaos functions are graded by total degree; within one degree they are
+ *   in descending lexicographic order of their multi-indices ((d,0,..,0)
+ *   first). Level l (degree l) occupies columns level_off[l]..level_off[l+1]-1.
+ *   Element arrays are indexed [ey][ex] (x1 fastest).
+ *
+ * Memory and streams
+ *   The caller owns every array. The library allocates no device memory: it
+ *   works inside a caller-provided device workspace whose size is returned
+ *   by sg_workspace_bytes. Host inputs are copied during the call; no
+ *   pointer is retained after a call returns except the workspace. All
+ *   device work is issued on the stream given to sg_setup. Calls that return
+ *   host scalars (sg_solve, sg_adjoint_grad, sg_inner_solve, sg_qoi)
+ *   synchronise that stream; the others are asynchronous.
+ *   A handle is not thread-safe; use one handle per stream.
+ *
+ * Status codes
+ *   SG_OK (0); negative: the call was rejected and did nothing
+ *   (SG_EINVAL invalid argument, SG_EDEVICE HIP runtime error,
+ *   SG_ENOMEM workspace too small); positive: a solver outcome with the
+ *   outputs filled (SG_NOT_CONVERGED: the last iterate is returned;
+ *   SG_BREAKDOWN: a non-positive or non-finite curvature p^T A p was met,
+ *   the last finite iterate is returned). sg_last_error() describes the
+ *   most recent failure of the calling thread.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SG_OK = 0,
+  SG_EINVAL = -1,
+  SG_EDEVICE = -2,
+  SG_ENOMEM = -3,
+  SG_NOT_CONVERGED = 1,
+  SG_BREAKDOWN = 2
+};
+
+enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_HSC = 2 };
+
+typedef struct sg_ctx* sg_handle;
+
+/* Problem description (Section 2; eq. (KL-expansion) with k_i = sqrt(lambda_i) v_i).
+ * theta0 > 0 is the mean coefficient, sigma >= 0 the standard-deviation
+ * scale, s[M] the KL amplitudes sqrt(lambda_k) and phi[M][n_e][n_e] the
+ * element values of the KL modes (both host arrays, copied by sg_setup).
+ * The element coefficient of KL term k is a_k(e) = sigma * s[k] * phi[k][e];
+ * coefficients are constant per element. Requires n_e >= 3, M >= 0, p >= 0,
+ * P <= 2^20. */
+typedef struct sg_problem {
+  int32_t n_e;
+  int32_t M;
+  int32_t p;
+  int32_t reserved;
+  double theta0;
+  double sigma;
+  const double* s;
+  const double* phi;
+} sg_problem;
+
+/* Solver options.
+ *   inner_precision   64 or 32: arithmetic of the inner K_0 solves and the
+ *                     coupling products of the preconditioner (the outer
+ *                     CG and the SG matvec are always FP64).
+ *   cheb_degree       d >= 1: updates of the Chebyshev polynomial
+ *                     preconditioner of the inner PCG (d - 1 products with
+ *                     K_0 per application).
+ *   inner_maxit       cap on inner PCG iterations per solve (>= 1).
+ *   precond           SG_PC_NONE, SG_PC_MEAN or SG_PC_HSC for sg_solve.
+ *   tile              spatial tile edge of the inner solver (16 or 32; 0 = auto).
+ *   inner_rtol        relative residual at which an inner solve stops
+ *                     (recursive residual, Euclidean norm); <= 0 runs
+ *                     exactly inner_maxit iterations. */
+typedef struct sg_opts {
+  int32_t inner_precision;
+  int32_t cheb_degree;
+  int32_t inner_maxit;
+  int32_t precond;
+  int32_t tile;
+  int32_t reserved;
+  double inner_rtol;
+} sg_opts;
+
+/* Statistics of a solve. Counters are totals over the call. */
+typedef struct sg_stats {
+  int32_t outer_it;           /* outer FCG iterations */
+  int32_t status;             /* same code as returned */
+  int64_t inner_it_total;     /* inner PCG iterations summed over all solves */
+  int64_t n_blockmv;          /* block products in preconditioner actions (n_m per HSC action) */
+  int64_t n_blocksolve;       /* block solves in preconditioner actions (n_ds per HSC action) */
+  int32_t inner_it_max[16];   /* max inner iterations per level (level l < 16) */
+  double relres;              /* final recursive relative residual ||r||_2 / ||f||_2 */
+  double true_relres;         /* ||f - A u||_2 / ||f||_2 recomputed at exit */
+  double kappa_est;           /* Lanczos condition estimate from the FCG coefficients */
+  double ms;                  /* wall time of the call in milliseconds */
+  double ms_precond;          /* time in preconditioner actions */
+  double ms_matvec;           /* time in SG matvecs */
+} sg_stats;
+
+/* Device workspace needed by sg_setup for this problem and options. */
+int sg_workspace_bytes(const sg_problem* prob, const sg_opts* opts, size_t* bytes);
+
+/* Validate, build the chaos tables and upload the coefficients into the
+ * workspace (device pointer, at least sg_workspace_bytes long, 256-byte
+ * aligned). `stream` is a hipStream_t (NULL = default stream). */
+int sg_setup(const sg_problem* prob, const sg_opts* opts, void* workspace, size_t workspace_bytes,
+             void* stream, sg_handle* out);
+
+/* Sizes: n, P, level offsets level_off[p+2] and, if alpha is not NULL, the
+ * multi-indices alpha[P][M] (host arrays). */
+int sg_sizes(sg_handle h, int64_t* n, int32_t* P, int32_t* level_off, int32_t* alpha);
+
+/* Replace the options of a handle (same inner precision as at setup). */
+int sg_set_opts(sg_handle h, const sg_opts* opts);
+
+/* Y = sum_k K_k U G_k^T (the MAT-VEC of the Remark after eq.
+ * (global-matrix-block)); U and Y are distinct n x P device blocks. FP64. */
+int sg_matvec(sg_handle h, const double* U, double* Y);
+
+/* Z = M_P R: one action of the hierarchical Schur complement preconditioner
+ * (Algorithm 1) with inexact diagonal-block solves by inner PCG (Section 5).
+ * R and Z are distinct n x P device blocks. */
+int sg_apply_hsc(sg_handle h, const double* R, double* Z);
+
+/* Z = (I (x) K_0^-1) R approximately: the mean-based preconditioner (Section 6),
+ * one inner PCG solve per column. */
+int sg_apply_mean(sg_handle h, const double* R, double* Z);
+
+/* Inner solves on the diagonal blocks (Section 5): for columns c = 0..ncols-1,
+ * PCG on K_0 x_c = b_c with the Jacobi-scaled Chebyshev preconditioner, in
+ * the handle's inner precision (FP64 data in and out). B and X are
+ * n x ncols device blocks (ld = n). iters[ncols] (host, may be NULL)
+ * receives the iteration count of each column. */
+int sg_inner_solve(sg_handle h, const double* B, double* X, int32_t ncols, int32_t* iters);
+
+/* Coupling products of Algorithm 1 on level l (1 <= l <= p), FP64:
+ *   dir = 0 (pre-correction):  R[:, level l-1] -= (B_l Y)[:, level l-1]
+ *            with Y read from the level-l columns of Y;
+ *   dir = 1 (post-correction): R[:, level l] -= (C_l Z)[:, level l]
+ *            with Z read from the level-(l-1) columns of Z.
+ * R, Y/Z are n x P device blocks. */
+int sg_coupling(sg_handle h, int32_t level, int32_t dir, double* R, const double* V);
+
+/* Solve A U = F by flexible CG (Section 5) preconditioned as opts.precond,
+ * to ||f - A u||_2 <= rtol ||f||_2 (recursive residual) or maxit outer
+ * iterations. use_x0 != 0 starts from the contents of U, else from zero.
+ * stats (host, may be NULL) is filled. */
+int sg_solve(sg_handle h, const double* F, double* U, double rtol, int32_t maxit, int32_t use_x0,
+             sg_stats* stats);
+
+/* Quantity of interest Q = w_mean . U[:,0] + sum_{j>=1} w_var . U[:,j]^2
+ * (w_mean, w_var: n-vectors on the device); result to *Q (host). */
+int sg_qoi(sg_handle h, const double* U, const double* w_mean, const double* w_var, double* Q);
+
+/* Gradient of Q with respect to theta = (theta0, s_1..s_M) at the solution U
+ * of A U = F: solves the adjoint system A Lambda = dQ/dU with the same
+ * preconditioned FCG (A is symmetric) to rtol, then contracts
+ * dQ/dtheta_i = -<Lambda, (dA/dtheta_i) U>. Q (host) and grad[1+M] (host)
+ * receive the results; Lambda (device n x P, may be NULL) receives the
+ * adjoint solution. */
+int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const double* w_var,
+                    double rtol, int32_t maxit, double* Q, double* grad, double* Lambda,
+                    sg_stats* stats);
+
+/* Release the handle (the workspace stays with the caller). */
+void sg_destroy(sg_handle h);
+
+/* Thread-local description of the last failure (never NULL). */
+const char* sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_H */

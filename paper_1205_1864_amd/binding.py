@@ -1,0 +1,261 @@
+"""ctypes binding of libsgpc.so (the C interface declared in include/sg.h).
+
+Argument marshalling only: every computation runs in the HIP library. Device
+blocks are torch tensors of shape (P, n), float64, contiguous, on the CUDA
+(HIP) device -- i.e. n x P column-major blocks with leading dimension n. The
+library allocates no device memory; the workspace is a torch uint8 tensor.
+If the library is not built this module raises on import.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgpc.so")
+
+SG_OK, SG_EINVAL, SG_EDEVICE, SG_ENOMEM, SG_NOT_CONVERGED, SG_BREAKDOWN = 0, -1, -2, -3, 1, 2
+SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC = 0, 1, 2
+_PC = {"none": SG_PC_NONE, "mean": SG_PC_MEAN, "hsc": SG_PC_HSC}
+
+
+class SgProblem(ctypes.Structure):
+    _fields_ = [("n_e", ctypes.c_int32), ("M", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("theta0", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("s", ctypes.POINTER(ctypes.c_double)), ("phi", ctypes.POINTER(ctypes.c_double))]
+
+
+class SgOpts(ctypes.Structure):
+    _fields_ = [("inner_precision", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
+                ("inner_maxit", ctypes.c_int32), ("precond", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+
+
+class SgStats(ctypes.Structure):
+    _fields_ = [("outer_it", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("inner_it_total", ctypes.c_int64), ("n_blockmv", ctypes.c_int64),
+                ("n_blocksolve", ctypes.c_int64), ("inner_it_max", ctypes.c_int32 * 16),
+                ("relres", ctypes.c_double), ("true_relres", ctypes.c_double),
+                ("kappa_est", ctypes.c_double), ("ms", ctypes.c_double),
+                ("ms_precond", ctypes.c_double), ("ms_matvec", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["inner_it_max"] = list(self.inner_it_max)
+        return d
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, VP, I32, I64, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "sg_workspace_bytes": [P(SgProblem), P(SgOpts), P(ctypes.c_size_t)],
+        "sg_setup": [P(SgProblem), P(SgOpts), VP, ctypes.c_size_t, VP, P(VP)],
+        "sg_sizes": [VP, P(I64), P(I32), P(I32), P(I32)],
+        "sg_set_opts": [VP, P(SgOpts)],
+        "sg_matvec": [VP, VP, VP],
+        "sg_apply_hsc": [VP, VP, VP],
+        "sg_apply_mean": [VP, VP, VP],
+        "sg_inner_solve": [VP, VP, VP, I32, P(I32)],
+        "sg_coupling": [VP, I32, I32, VP, VP],
+        "sg_solve": [VP, VP, VP, D, I32, I32, P(SgStats)],
+        "sg_qoi": [VP, VP, VP, VP, P(D)],
+        "sg_adjoint_grad": [VP, VP, VP, VP, D, I32, P(D), P(D), VP, P(SgStats)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.sg_destroy.argtypes = [VP]
+    lib.sg_destroy.restype = None
+    lib.sg_last_error.argtypes = []
+    lib.sg_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+class SGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc, allow_positive=False):
+    if rc < 0 or (rc > 0 and not allow_positive):
+        raise SGError(rc, lib.sg_last_error().decode())
+    return rc
+
+
+def last_error() -> str:
+    return lib.sg_last_error().decode()
+
+
+@dataclass
+class Options:
+    inner_precision: int = 64
+    cheb_degree: int = 4
+    inner_maxit: int = 1000
+    precond: str = "hsc"
+    tile: int = 0
+    inner_rtol: float = 1e-4
+
+    def to_c(self) -> SgOpts:
+        return SgOpts(self.inner_precision, self.cheb_degree, self.inner_maxit, _PC[self.precond],
+                      self.tile, 0, float(self.inner_rtol))
+
+
+def _dptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+def make_c_problem(problem):
+    """(SgProblem, keep-alive arrays) from any object with n_e, M, p, theta0, sigma, s, phi."""
+    s = np.ascontiguousarray(np.asarray(problem.s, dtype=np.float64).reshape(-1))
+    phi = np.ascontiguousarray(np.asarray(problem.phi, dtype=np.float64).reshape(-1))
+    dp = ctypes.POINTER(ctypes.c_double)
+    cp = SgProblem(int(problem.n_e), int(problem.M), int(problem.p), 0, float(problem.theta0),
+                   float(problem.sigma), s.ctypes.data_as(dp) if s.size else None,
+                   phi.ctypes.data_as(dp) if phi.size else None)
+    return cp, (s, phi)
+
+
+def workspace_bytes(problem, opts: Options) -> int:
+    cp, keep = make_c_problem(problem)
+    co = opts.to_c()
+    nb = ctypes.c_size_t(0)
+    _check(lib.sg_workspace_bytes(ctypes.byref(cp), ctypes.byref(co), ctypes.byref(nb)))
+    return int(nb.value)
+
+
+class SGSolver:
+    """A configured SG problem on one device (a handle plus its workspace)."""
+
+    def __init__(self, problem, opts: Options = None, device="cuda", stream=None):
+        self.opts = opts or Options()
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        cp, keep = make_c_problem(problem)
+        co = self.opts.to_c()
+        nb = ctypes.c_size_t(0)
+        _check(lib.sg_workspace_bytes(ctypes.byref(cp), ctypes.byref(co), ctypes.byref(nb)))
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.sg_setup(ctypes.byref(cp), ctypes.byref(co), ctypes.c_void_p(self.workspace.data_ptr()),
+                            ctypes.c_size_t(int(nb.value)), ctypes.c_void_p(self.stream.cuda_stream),
+                            ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int64()
+        P = ctypes.c_int32()
+        self.M, self.p = int(problem.M), int(problem.p)
+        off = (ctypes.c_int32 * (self.p + 2))()
+        alpha = (ctypes.c_int32 * max(1, 0))()
+        _check(lib.sg_sizes(h, ctypes.byref(n), ctypes.byref(P), off, None))
+        self.n, self.P = int(n.value), int(P.value)
+        self.level_off = list(off)
+        al = (ctypes.c_int32 * max(1, self.P * self.M))()
+        _check(lib.sg_sizes(h, None, None, None, al))
+        self.alpha = np.array(al[: self.P * self.M], dtype=np.int64).reshape(self.P, self.M)
+        del alpha
+
+    # -- helpers ---------------------------------------------------------
+    def _block(self, t: torch.Tensor, ncols=None) -> torch.Tensor:
+        ncols = self.P if ncols is None else ncols
+        if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous() or \
+                tuple(t.shape) != (ncols, self.n):
+            raise ValueError(f"expected a contiguous float64 ({ncols}, {self.n}) tensor on {self.device}")
+        return t
+
+    def empty(self, ncols=None) -> torch.Tensor:
+        return torch.empty((self.P if ncols is None else ncols, self.n), dtype=torch.float64, device=self.device)
+
+    def set_opts(self, opts: Options):
+        co = opts.to_c()
+        _check(lib.sg_set_opts(self.handle, ctypes.byref(co)))
+        self.opts = opts
+
+    # -- entry points (same names as the C interface) ----------------------
+    def sg_matvec(self, U, Y=None):
+        Y = self.empty() if Y is None else Y
+        _check(lib.sg_matvec(self.handle, _dptr(self._block(U)), _dptr(self._block(Y))))
+        return Y
+
+    def sg_apply_hsc(self, R, Z=None):
+        Z = self.empty() if Z is None else Z
+        _check(lib.sg_apply_hsc(self.handle, _dptr(self._block(R)), _dptr(self._block(Z))))
+        return Z
+
+    def sg_apply_mean(self, R, Z=None):
+        Z = self.empty() if Z is None else Z
+        _check(lib.sg_apply_mean(self.handle, _dptr(self._block(R)), _dptr(self._block(Z))))
+        return Z
+
+    def sg_inner_solve(self, B, X=None):
+        ncols = B.shape[0]
+        X = self.empty(ncols) if X is None else X
+        its = (ctypes.c_int32 * max(1, ncols))()
+        _check(lib.sg_inner_solve(self.handle, _dptr(self._block(B, ncols)), _dptr(self._block(X, ncols)),
+                                  ncols, its))
+        return X, np.array(its[:ncols])
+
+    def sg_coupling(self, level, direction, R, V):
+        _check(lib.sg_coupling(self.handle, int(level), int(direction), _dptr(self._block(R)),
+                               _dptr(self._block(V))))
+        return R
+
+    def sg_solve(self, F, U=None, rtol=1e-8, maxit=200, use_x0=False):
+        U = self.empty() if U is None else U
+        st = SgStats()
+        rc = _check(lib.sg_solve(self.handle, _dptr(self._block(F)), _dptr(self._block(U)), float(rtol),
+                                 int(maxit), int(bool(use_x0)), ctypes.byref(st)), allow_positive=True)
+        d = st.as_dict()
+        d["rc"] = rc
+        return U, d
+
+    def sg_qoi(self, U, w_mean, w_var):
+        Q = ctypes.c_double()
+        _check(lib.sg_qoi(self.handle, _dptr(self._block(U)), _dptr(w_mean), _dptr(w_var), ctypes.byref(Q)))
+        return Q.value
+
+    def sg_adjoint_grad(self, U, w_mean, w_var, rtol=1e-8, maxit=200, Lambda=None):
+        Q = ctypes.c_double()
+        grad = (ctypes.c_double * (1 + self.M))()
+        st = SgStats()
+        lam_ptr = _dptr(self._block(Lambda)) if Lambda is not None else None
+        rc = _check(lib.sg_adjoint_grad(self.handle, _dptr(self._block(U)), _dptr(w_mean), _dptr(w_var),
+                                        float(rtol), int(maxit), ctypes.byref(Q), grad, lam_ptr,
+                                        ctypes.byref(st)), allow_positive=True)
+        d = st.as_dict()
+        d["rc"] = rc
+        return Q.value, np.array(grad[:]), d
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.sg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_device_block(A: np.ndarray, device="cuda") -> torch.Tensor:
+    """(P, n) numpy array -> contiguous float64 device tensor."""
+    return torch.from_numpy(np.ascontiguousarray(A, dtype=np.float64)).to(device)
+
+
+def to_device_vec(v: np.ndarray, device="cuda") -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).to(device)

@@ -1,0 +1,881 @@
+// C interface of the SG solver library: setup of the chaos tables and the
+// workspace, and the host drivers of the flexible CG (Section 5), the
+// hierarchical Schur complement preconditioner (Algorithm 1), the mean-based
+// preconditioner (Section 6) and the adjoint gradient.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define SG_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(SG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+long binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Multi-indices of total degree <= p, graded, descending lexicographic within a degree.
+void multi_indices(int M, int p, std::vector<int>& out, std::vector<int>& off) {
+  out.clear();
+  off.assign(1, 0);
+  std::vector<int> cur(M, 0);
+  for (int d = 0; d <= p; ++d) {
+    long count = 0;
+    if (M == 0) {
+      if (d == 0) count = 1;
+    } else {
+      // iterative enumeration: fill positions left to right with the largest value first
+      std::vector<int> rem(M + 1, 0);
+      std::function<void(int, int)> rec = [&](int k, int remaining) {
+        if (k == M - 1) {
+          cur[k] = remaining;
+          out.insert(out.end(), cur.begin(), cur.end());
+          ++count;
+          return;
+        }
+        for (int v = remaining; v >= 0; --v) {
+          cur[k] = v;
+          rec(k + 1, remaining - v);
+        }
+      };
+      rec(0, d);
+    }
+    off.push_back(off.back() + (int)count);
+  }
+}
+
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    size_t o = total;
+    total += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
+
+struct Plan {
+  int P, nx;
+  long n;
+  int nlo, nup, npairs;
+  int maxcols, ntiles_max;
+  size_t o_a64, o_a32, o_c64;
+  size_t o_lo_ptr, o_lo_ent, o_lo_g64, o_lo_g32, o_up_ptr, o_up_ent, o_up_g64, o_up_g32;
+  size_t o_pair_ptr, o_pair_a, o_pair_b, o_pair_g;
+  size_t o_vec[7];
+  size_t o_rw, o_zw;
+  size_t o_pcg[6];
+  size_t o_part, o_done, o_iters, o_ndone, o_status;
+  size_t o_red_part, o_red_out;
+  size_t total;
+};
+
+int validate(const sg_problem* pr, const sg_opts* op) {
+  if (!pr || !op) return fail(SG_EINVAL, "null problem or options");
+  if (pr->n_e < 3) return fail(SG_EINVAL, "n_e must be >= 3");
+  if (pr->n_e > 8192) return fail(SG_EINVAL, "n_e must be <= 8192");
+  if (pr->M < 0 || pr->p < 0) return fail(SG_EINVAL, "M and p must be >= 0");
+  if (pr->p + 1 > sgk::kMaxLevels) return fail(SG_EINVAL, "p must be < 16");
+  if (binom(pr->M + pr->p, pr->p) > (1L << 20)) return fail(SG_EINVAL, "P = C(M+p, p) exceeds 2^20");
+  if (pr->M > 2047) return fail(SG_EINVAL, "M must be < 2048");
+  if (!(pr->theta0 > 0.0) || !std::isfinite(pr->theta0)) return fail(SG_EINVAL, "theta0 must be positive");
+  if (!(pr->sigma >= 0.0) || !std::isfinite(pr->sigma)) return fail(SG_EINVAL, "sigma must be >= 0");
+  if (pr->M > 0 && (!pr->s || !pr->phi)) return fail(SG_EINVAL, "null s or phi");
+  if (op->inner_precision != 32 && op->inner_precision != 64)
+    return fail(SG_EINVAL, "inner_precision must be 32 or 64");
+  if (op->cheb_degree < 1 || op->cheb_degree > sgk::kMaxCheb) return fail(SG_EINVAL, "cheb_degree must be 1..16");
+  if (op->inner_maxit < 1) return fail(SG_EINVAL, "inner_maxit must be >= 1");
+  if (op->precond < SG_PC_NONE || op->precond > SG_PC_HSC) return fail(SG_EINVAL, "unknown preconditioner");
+  if (op->tile != 0 && op->tile != 16 && op->tile != 32) return fail(SG_EINVAL, "tile must be 0, 16 or 32");
+  if (!(op->inner_rtol < 1.0) || std::isnan(op->inner_rtol)) return fail(SG_EINVAL, "inner_rtol must be < 1");
+  return SG_OK;
+}
+
+void make_plan(const sg_problem* pr, const sg_opts* op, Plan& pl) {
+  const int M = pr->M, p = pr->p;
+  pl.P = (int)binom(M + p, p);
+  pl.nx = pr->n_e - 1;
+  pl.n = (long)pl.nx * pl.nx;
+  const long ne2 = (long)pr->n_e * pr->n_e;
+  // each row has at most M lower and M upper neighbours; exact counts from the level sizes
+  long nlo = 0;
+  std::vector<int> al, off;
+  multi_indices(M, p, al, off);
+  for (int a = 0; a < pl.P; ++a)
+    for (int k = 0; k < M; ++k)
+      if (al[(long)a * M + k] > 0) ++nlo;
+  pl.nlo = (int)nlo;
+  pl.nup = (int)nlo;  // every lower entry (a, a - e_k) is an upper entry of a - e_k
+  pl.npairs = 2 * (int)nlo;
+  pl.maxcols = pl.P;
+  pl.ntiles_max = (int)(((pl.nx + 15) / 16) * ((pl.nx + 15) / 16));
+  const size_t isz = op->inner_precision == 32 ? 4 : 8;
+  const long nP = pl.n * (long)pl.P;
+  Layout L;
+  pl.o_a64 = L.take(sizeof(double) * M * ne2);
+  pl.o_a32 = L.take(sizeof(float) * M * ne2);
+  pl.o_c64 = L.take(sizeof(double) * M * ne2);
+  pl.o_lo_ptr = L.take(sizeof(int) * (pl.P + 1));
+  pl.o_lo_ent = L.take(sizeof(int) * std::max(1, pl.nlo));
+  pl.o_lo_g64 = L.take(sizeof(double) * std::max(1, pl.nlo));
+  pl.o_lo_g32 = L.take(sizeof(float) * std::max(1, pl.nlo));
+  pl.o_up_ptr = L.take(sizeof(int) * (pl.P + 1));
+  pl.o_up_ent = L.take(sizeof(int) * std::max(1, pl.nup));
+  pl.o_up_g64 = L.take(sizeof(double) * std::max(1, pl.nup));
+  pl.o_up_g32 = L.take(sizeof(float) * std::max(1, pl.nup));
+  pl.o_pair_ptr = L.take(sizeof(int) * (M + 1));
+  pl.o_pair_a = L.take(sizeof(int) * std::max(1, pl.npairs));
+  pl.o_pair_b = L.take(sizeof(int) * std::max(1, pl.npairs));
+  pl.o_pair_g = L.take(sizeof(double) * std::max(1, pl.npairs));
+  for (int i = 0; i < 7; ++i) pl.o_vec[i] = L.take(sizeof(double) * nP);
+  pl.o_rw = L.take(isz * nP);
+  pl.o_zw = L.take(op->inner_precision == 32 ? isz * nP : 0);
+  for (int i = 0; i < 6; ++i) pl.o_pcg[i] = L.take(isz * pl.n * (long)pl.maxcols);
+  pl.o_part = L.take(sizeof(double) * 6 * (long)pl.maxcols * pl.ntiles_max);
+  pl.o_done = L.take(sizeof(int) * pl.maxcols);
+  pl.o_iters = L.take(sizeof(int) * pl.maxcols);
+  pl.o_ndone = L.take(sizeof(unsigned));
+  pl.o_status = L.take(sizeof(int));
+  const long nb_contract = (ne2 + 255) / 256;
+  pl.o_red_part = L.take(sizeof(double) * std::max<long>(4L * sgk::kRedBlocks, nb_contract * (M + 1)));
+  pl.o_red_out = L.take(sizeof(double) * std::max(64, M + 1));
+  pl.total = L.total;
+}
+
+// Spectrum of D^-1 K_0 for the Q1 stencil: (8 - 2 c_i - 2 c_j - 4 c_i c_j) / 8, c_i = cos(i pi / n_e).
+void cheb_interval(int n_e, double& lmin, double& lmax) {
+  lmin = 1e300;
+  lmax = -1e300;
+  std::vector<double> c(n_e - 1);
+  for (int i = 1; i < n_e; ++i) c[i - 1] = std::cos(i * M_PI / n_e);
+  for (int i = 0; i < n_e - 1; ++i)
+    for (int j = 0; j < n_e - 1; ++j) {
+      const double l = (8.0 - 2.0 * c[i] - 2.0 * c[j] - 4.0 * c[i] * c[j]) / 8.0;
+      lmin = std::min(lmin, l);
+      lmax = std::max(lmax, l);
+    }
+}
+
+template <typename T>
+void fill_pcg_consts(const sg_ctx* h, sgk::PcgArgs<T>& a) {
+  const double lmin = h->lmin, lmax = h->lmax;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double diag = h->theta0 * 8.0 / 3.0;
+  a.c0 = (T)diag;
+  a.c1 = (T)(-h->theta0 / 3.0);
+  a.inv_diag = (T)(1.0 / diag);
+  a.inv_theta = (T)(1.0 / theta);
+  for (int j = 0; j < sgk::kMaxCheb; ++j) {
+    a.chebA[j] = T(0);
+    a.chebB[j] = T(0);
+  }
+  if (delta > 0.0) {
+    const double sigma1 = theta / delta;
+    double rho = 1.0 / sigma1;
+    for (int j = 1; j < h->opts.cheb_degree; ++j) {
+      const double rn = 1.0 / (2.0 * sigma1 - rho);
+      a.chebA[j] = (T)(rn * rho);
+      a.chebB[j] = (T)(2.0 * rn / delta);
+      rho = rn;
+    }
+  }
+}
+
+int effective_degree(const sg_ctx* h) { return h->lmax - h->lmin > 0.0 ? h->opts.cheb_degree : 1; }
+
+size_t pcg_lds_bytes(int tile, int degree, size_t tsz) {
+  const int H = degree - 1;
+  const int RS = tile + 2 * (H > 1 ? H : 1);
+  return tsz * (3 * RS * RS + 2 * tile * tile);
+}
+
+int choose_tile(const sg_ctx* h, int ncols, size_t tsz, int degree) {
+  if (h->opts.tile == 16 || h->opts.tile == 32) {
+    if (h->opts.tile == 32 && pcg_lds_bytes(32, degree, tsz) > 64 * 1024) return 16;
+    return h->opts.tile;
+  }
+  if (pcg_lds_bytes(32, degree, tsz) > 64 * 1024) return 16;
+  const long t32 = (long)((h->nx + 31) / 32) * ((h->nx + 31) / 32);
+  if ((long)ncols * t32 >= 2L * h->num_cu) return 32;
+  return 16;
+}
+
+// Batched inner PCG on `ncols` contiguous columns (inner precision T).
+template <typename T>
+int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::vector<int>* iters_out = nullptr) {
+  if (ncols <= 0) return SG_OK;
+  if (ncols > h->pcg_maxcols) return fail(SG_EINVAL, "too many columns for the inner solver");
+  sgk::PcgArgs<T> a{};
+  const int degree = effective_degree(h);
+  const int tile = choose_tile(h, ncols, sizeof(T), degree);
+  a.nx = h->nx;
+  a.n = h->n;
+  a.ncols = ncols;
+  a.B = B;
+  a.X = X;
+  a.R0 = (T*)h->pR0;
+  a.R1 = (T*)h->pR1;
+  a.P0 = (T*)h->pP0;
+  a.P1 = (T*)h->pP1;
+  a.Q = (T*)h->pQ;
+  a.Z = (T*)h->pZ;
+  a.sc = h->pcgsc;
+  a.ntx = (h->nx + tile - 1) / tile;
+  a.ntiles = a.ntx * a.ntx;
+  a.degree = degree;
+  a.maxit = h->opts.inner_maxit;
+  a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;
+  fill_pcg_consts<T>(h, a);
+  a.degree = degree;
+  SG_HIP(sgk::launch_pcg<T>(a, tile, 0, h->stream));
+  std::vector<int> it(ncols);
+  SG_HIP(hipMemcpyAsync(it.data(), h->pcgsc.iters, sizeof(int) * ncols, hipMemcpyDeviceToHost, h->stream));
+  SG_HIP(hipStreamSynchronize(h->stream));
+  int mx = 0;
+  for (int v : it) {
+    h->inner_it_acc += v;
+    mx = std::max(mx, v);
+  }
+  if (level_for_stats >= 0 && level_for_stats < sgk::kMaxLevels)
+    h->inner_it_max[level_for_stats] = std::max(h->inner_it_max[level_for_stats], mx);
+  if (iters_out) *iters_out = it;
+  return SG_OK;
+}
+
+template <typename T>
+sgk::ChaosLists<T> lists(const sg_ctx* h);
+template <>
+sgk::ChaosLists<double> lists<double>(const sg_ctx* h) {
+  return {h->lo_ptr_d, h->lo_ent_d, h->lo_g64, h->up_ptr_d, h->up_ent_d, h->up_g64};
+}
+template <>
+sgk::ChaosLists<float> lists<float>(const sg_ctx* h) {
+  return {h->lo_ptr_d, h->lo_ent_d, h->lo_g32, h->up_ptr_d, h->up_ent_d, h->up_g32};
+}
+template <typename T>
+const T* coefs(const sg_ctx* h);
+template <>
+const double* coefs<double>(const sg_ctx* h) { return h->a64; }
+template <>
+const float* coefs<float>(const sg_ctx* h) { return h->a32; }
+
+// R[level l-1] -= B_l V[level l] (dir 0) or R[level l] -= C_l V[level l-1] (dir 1).
+template <typename T>
+void coupling(sg_ctx* h, int l, int dir, T* R, const T* V) {
+  sgk::SgOpArgs<T> a{};
+  a.n_e = h->n_e;
+  a.nx = h->nx;
+  a.n = h->n;
+  const int rl = dir == 0 ? l - 1 : l;
+  a.row0 = h->off[rl];
+  a.nrows = h->off[rl + 1] - h->off[rl];
+  a.use_lower = dir == 1;
+  a.use_upper = dir == 0;
+  a.diag = T(0);
+  a.rcoef = T(1);
+  a.sgn = T(-1);
+  a.in = V;
+  a.rsrc = R;
+  a.out = R;
+  a.a = coefs<T>(h);
+  a.lists = lists<T>(h);
+  sgk::launch_sgop<T>(a, h->stream);
+}
+
+long coupling_blocks(const sg_ctx* h, int l, int dir) {
+  const int rl = dir == 0 ? l - 1 : l;
+  const std::vector<int>& ptr = dir == 0 ? h->up_ptr : h->lo_ptr;
+  return ptr[h->off[rl + 1]] - ptr[h->off[rl]];
+}
+
+// Algorithm 1 in inner precision T: rw holds a copy of the residual, Zb receives M_P r.
+template <typename T>
+int hsc_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs) {
+  const long n = h->n;
+  for (int l = h->p; l >= 1; --l) {
+    const int lo = h->off[l], hi = h->off[l + 1];
+    int rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l);  // y_l = D_l^-1 r_l^l
+    if (rc) return rc;
+    coupling<T>(h, l, 0, rw, Zb);  // g_{l-1} = r_l^{l-1} - B_l y_l
+    *nbs += hi - lo;
+    *nbmv += coupling_blocks(h, l, 0);
+  }
+  int rc = run_pcg<T>(h, rw, Zb, 1, 0);  // A_0 u_0 = g_0
+  if (rc) return rc;
+  *nbs += 1;
+  for (int l = 1; l <= h->p; ++l) {
+    const int lo = h->off[l], hi = h->off[l + 1];
+    coupling<T>(h, l, 1, rw, Zb);  // w = r_l^l - C_l u_{l-1}
+    *nbmv += coupling_blocks(h, l, 1);
+    rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l);  // u_l^l = D_l^-1 w
+    if (rc) return rc;
+    *nbs += hi - lo;
+  }
+  return SG_OK;
+}
+
+int apply_hsc(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
+  const long N = h->n * (long)h->P;
+  if (h->opts.inner_precision == 64) {
+    double* rw = (double*)h->rw;
+    sgk::launch_copy_d2d(rw, R, N, h->stream);
+    return hsc_core<double>(h, rw, Z, nbmv, nbs);
+  }
+  float* rw = (float*)h->rw;
+  float* zw = (float*)h->zw;
+  sgk::launch_copy_d2f(rw, R, N, h->stream);
+  int rc = hsc_core<float>(h, rw, zw, nbmv, nbs);
+  if (rc) return rc;
+  sgk::launch_copy_f2d(Z, zw, N, h->stream);
+  return SG_OK;
+}
+
+int apply_mean(sg_ctx* h, const double* R, double* Z, long* nbs) {
+  const long N = h->n * (long)h->P;
+  *nbs += h->P;
+  if (h->opts.inner_precision == 64) return run_pcg<double>(h, R, Z, h->P, -1);
+  float* rw = (float*)h->rw;
+  float* zw = (float*)h->zw;
+  sgk::launch_copy_d2f(rw, R, N, h->stream);
+  int rc = run_pcg<float>(h, rw, zw, h->P, -1);
+  if (rc) return rc;
+  sgk::launch_copy_f2d(Z, zw, N, h->stream);
+  return SG_OK;
+}
+
+void matvec(sg_ctx* h, const double* U, double* Y) {
+  sgk::SgOpArgs<double> a{};
+  a.n_e = h->n_e;
+  a.nx = h->nx;
+  a.n = h->n;
+  a.row0 = 0;
+  a.nrows = h->P;
+  a.use_lower = 1;
+  a.use_upper = 1;
+  a.diag = h->theta0;
+  a.rcoef = 0.0;
+  a.sgn = 1.0;
+  a.in = U;
+  a.rsrc = nullptr;
+  a.out = Y;
+  a.a = h->a64;
+  a.lists = lists<double>(h);
+  sgk::launch_sgop<double>(a, h->stream);
+}
+
+int read_out(sg_ctx* h, int count) {
+  if ((int)h->host_out.size() < count) h->host_out.resize(count);
+  SG_HIP(hipMemcpyAsync(h->host_out.data(), h->red_out, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+  SG_HIP(hipStreamSynchronize(h->stream));
+  return SG_OK;
+}
+
+int dots(sg_ctx* h, int nd, const double* a0, const double* b0, const double* a1 = nullptr,
+         const double* b1 = nullptr, const double* a2 = nullptr, const double* b2 = nullptr) {
+  const double* A[3] = {a0, a1, a2};
+  const double* B[3] = {b0, b1, b2};
+  sgk::launch_dots(A, B, nd, h->n * (long)h->P, h->red_part, h->red_out, h->stream);
+  return read_out(h, nd);
+}
+
+double lanczos_kappa(const std::vector<double>& al, const std::vector<double>& be) {
+  const int m = (int)al.size();
+  if (m == 0) return 1.0;
+  // symmetric tridiagonal eigenvalues by bisection (Sturm sequences)
+  std::vector<double> d(m), e(m, 0.0);
+  d[0] = 1.0 / al[0];
+  for (int i = 1; i < m; ++i) {
+    const double b = std::fabs(be[i - 1]);
+    d[i] = 1.0 / al[i] + b / al[i - 1];
+    e[i] = std::sqrt(b) / al[i - 1];
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < m; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = d[i] - x - e[i] * e[i] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = std::fabs(e[i]) + (i + 1 < m ? std::fabs(e[i + 1]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto kth = [&](int k) {  // k-th smallest eigenvalue, 0-based
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (count_below(mid) > k) b = mid; else a = mid;
+    }
+    return 0.5 * (a + b);
+  };
+  const double emin = kth(0), emax = kth(m - 1);
+  return emax / emin;
+}
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+// Flexible CG with one stored direction; preconditioner kind pc.
+int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x0, int pc, sg_stats* st) {
+  Timer total;
+  const long N = h->n * (long)h->P;
+  sg_stats S{};
+  h->inner_it_acc = 0;
+  for (int l = 0; l < sgk::kMaxLevels; ++l) h->inner_it_max[l] = 0;
+  long nbmv = 0, nbs = 0;
+  double ms_pc = 0.0, ms_mv = 0.0;
+  int rc = dots(h, 1, F, F);
+  if (rc) return rc;
+  const double fn2 = h->host_out[0];
+  if (!std::isfinite(fn2)) return fail(SG_EINVAL, "right-hand side is not finite");
+  double* r = h->r;
+  double* z = h->z;
+  double* p = h->pv;
+  double* q = h->q;
+  if (use_x0) {
+    matvec(h, U, h->tmp);
+    sgk::launch_sub(r, F, h->tmp, N, h->stream);
+  } else {
+    sgk::launch_fill(U, 0.0, N, h->stream);
+    sgk::launch_copy_d2d(r, F, N, h->stream);
+  }
+  int status = SG_NOT_CONVERGED;
+  std::vector<double> alphas, betas;
+  double relres = 0.0;
+  int its = 0;
+  if (fn2 == 0.0) {
+    sgk::launch_fill(U, 0.0, N, h->stream);
+    status = SG_OK;
+  } else {
+    rc = dots(h, 1, r, r);
+    if (rc) return rc;
+    relres = std::sqrt(h->host_out[0] / fn2);
+    if (relres <= rtol) status = SG_OK;
+    double pq_prev = 0.0;
+    for (int it = 0; it < maxit && status == SG_NOT_CONVERGED; ++it) {
+      Timer tp;
+      if (pc == SG_PC_HSC) {
+        rc = apply_hsc(h, r, z, &nbmv, &nbs);
+      } else if (pc == SG_PC_MEAN) {
+        rc = apply_mean(h, r, z, &nbs);
+      } else {
+        sgk::launch_copy_d2d(z, r, N, h->stream);
+        rc = SG_OK;
+      }
+      if (rc) return rc;
+      if (it == 0) {
+        sgk::launch_copy_d2d(p, z, N, h->stream);
+      } else {
+        rc = dots(h, 1, z, q);
+        if (rc) return rc;
+        const double beta = -h->host_out[0] / pq_prev;
+        betas.push_back(beta);
+        sgk::launch_xpby(p, z, beta, N, h->stream);
+      }
+      SG_HIP(hipStreamSynchronize(h->stream));
+      ms_pc += tp.ms();
+      Timer tm;
+      matvec(h, p, q);
+      SG_HIP(hipStreamSynchronize(h->stream));
+      ms_mv += tm.ms();
+      rc = dots(h, 2, p, q, p, r);
+      if (rc) return rc;
+      const double pq = h->host_out[0], pr = h->host_out[1];
+      if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(pr)) {
+        status = SG_BREAKDOWN;
+        break;
+      }
+      const double alpha = pr / pq;
+      alphas.push_back(alpha);
+      sgk::launch_fcg_update(U, r, p, q, alpha, N, h->red_part, h->red_out, h->stream);
+      rc = read_out(h, 1);
+      if (rc) return rc;
+      pq_prev = pq;
+      its = it + 1;
+      relres = std::sqrt(h->host_out[0] / fn2);
+      if (!std::isfinite(relres)) {
+        status = SG_BREAKDOWN;
+        break;
+      }
+      if (relres <= rtol) status = SG_OK;
+    }
+  }
+  // true residual
+  double true_rel = 0.0;
+  if (fn2 > 0.0) {
+    matvec(h, U, h->tmp);
+    sgk::launch_sub(h->tmp, F, h->tmp, N, h->stream);
+    rc = dots(h, 1, h->tmp, h->tmp);
+    if (rc) return rc;
+    true_rel = std::sqrt(h->host_out[0] / fn2);
+  }
+  S.outer_it = its;
+  S.status = status;
+  S.inner_it_total = h->inner_it_acc;
+  S.n_blockmv = nbmv;
+  S.n_blocksolve = nbs;
+  for (int l = 0; l < 16; ++l) S.inner_it_max[l] = h->inner_it_max[l];
+  S.relres = relres;
+  S.true_relres = true_rel;
+  S.kappa_est = lanczos_kappa(alphas, betas);
+  S.ms_precond = ms_pc;
+  S.ms_matvec = ms_mv;
+  S.ms = total.ms();
+  if (st) *st = S;
+  if (status == SG_NOT_CONVERGED) g_last_error = "outer iteration did not converge";
+  if (status == SG_BREAKDOWN) g_last_error = "breakdown: non-positive or non-finite curvature";
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sg_workspace_bytes(const sg_problem* prob, const sg_opts* opts, size_t* bytes) {
+  int rc = validate(prob, opts);
+  if (rc) return rc;
+  if (!bytes) return fail(SG_EINVAL, "null bytes");
+  Plan pl;
+  make_plan(prob, opts, pl);
+  *bytes = pl.total;
+  return SG_OK;
+}
+
+int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t workspace_bytes, void* stream,
+             sg_handle* out) {
+  int rc = validate(pr, op);
+  if (rc) return rc;
+  if (!out || !workspace) return fail(SG_EINVAL, "null workspace or handle pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(SG_EINVAL, "workspace must be 256-byte aligned");
+  for (int k = 0; k < pr->M; ++k)
+    if (!std::isfinite(pr->s[k])) return fail(SG_EINVAL, "s is not finite");
+  Plan pl;
+  make_plan(pr, op, pl);
+  if (workspace_bytes < pl.total) return fail(SG_ENOMEM, "workspace too small");
+  sg_ctx* h = new (std::nothrow) sg_ctx();
+  if (!h) return fail(SG_ENOMEM, "host allocation failed");
+  h->n_e = pr->n_e;
+  h->M = pr->M;
+  h->p = pr->p;
+  h->P = pl.P;
+  h->nx = pl.nx;
+  h->n = pl.n;
+  h->theta0 = pr->theta0;
+  h->sigma = pr->sigma;
+  h->s.assign(pr->s, pr->s + pr->M);
+  h->opts = *op;
+  h->stream = (hipStream_t)stream;
+  h->ws = (char*)workspace;
+  h->ws_bytes = workspace_bytes;
+  multi_indices(h->M, h->p, h->alpha, h->off);
+  cheb_interval(h->n_e, h->lmin, h->lmax);
+  int dev = 0;
+  h->num_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    delete h;
+    return fail(SG_EDEVICE, "no HIP device");
+  }
+  const int M = h->M, P = h->P;
+  const long ne2 = (long)h->n_e * h->n_e;
+  // element coefficients
+  std::vector<double> a64((size_t)M * ne2), c64((size_t)M * ne2);
+  std::vector<float> a32((size_t)M * ne2);
+  for (int k = 0; k < M; ++k)
+    for (long e = 0; e < ne2; ++e) {
+      const double ph = pr->phi[(long)k * ne2 + e];
+      if (!std::isfinite(ph)) {
+        delete h;
+        return fail(SG_EINVAL, "phi is not finite");
+      }
+      c64[(size_t)k * ne2 + e] = pr->sigma * ph;
+      a64[(size_t)k * ne2 + e] = pr->sigma * pr->s[k] * ph;
+      a32[(size_t)k * ne2 + e] = (float)a64[(size_t)k * ne2 + e];
+    }
+  // chaos neighbour lists
+  std::map<std::vector<int>, int> index;
+  for (int a = 0; a < P; ++a)
+    index[std::vector<int>(h->alpha.begin() + (long)a * M, h->alpha.begin() + (long)(a + 1) * M)] = a;
+  std::vector<int> lo_ptr(P + 1, 0), up_ptr(P + 1, 0), lo_ent, up_ent;
+  std::vector<double> lo_g, up_g;
+  std::vector<std::vector<std::pair<int, int>>> pairs(M);  // per k: (a, b)
+  std::vector<std::vector<double>> pairg(M);
+  for (int a = 0; a < P; ++a) {
+    std::vector<int> al(h->alpha.begin() + (long)a * M, h->alpha.begin() + (long)(a + 1) * M);
+    int deg = 0;
+    for (int v : al) deg += v;
+    for (int k = 0; k < M; ++k) {
+      if (al[k] > 0) {
+        std::vector<int> b = al;
+        b[k] -= 1;
+        const int bi = index.at(b);
+        lo_ent.push_back(bi | ((k + 1) << 20));
+        lo_g.push_back(std::sqrt((double)al[k]));
+        pairs[k].push_back({a, bi});
+        pairg[k].push_back(std::sqrt((double)al[k]));
+      }
+    }
+    lo_ptr[a + 1] = (int)lo_ent.size();
+    for (int k = 0; k < M; ++k) {
+      if (deg < h->p) {
+        std::vector<int> b = al;
+        b[k] += 1;
+        const int bi = index.at(b);
+        up_ent.push_back(bi | ((k + 1) << 20));
+        up_g.push_back(std::sqrt((double)al[k] + 1.0));
+        pairs[k].push_back({a, bi});
+        pairg[k].push_back(std::sqrt((double)al[k] + 1.0));
+      }
+    }
+    up_ptr[a + 1] = (int)up_ent.size();
+  }
+  std::vector<float> lo_g32(lo_g.begin(), lo_g.end()), up_g32(up_g.begin(), up_g.end());
+  std::vector<int> pair_ptr(M + 1, 0), pair_a, pair_b;
+  std::vector<double> pair_g;
+  for (int k = 0; k < M; ++k) {
+    for (size_t i = 0; i < pairs[k].size(); ++i) {
+      pair_a.push_back(pairs[k][i].first);
+      pair_b.push_back(pairs[k][i].second);
+      pair_g.push_back(pairg[k][i]);
+    }
+    pair_ptr[k + 1] = (int)pair_a.size();
+  }
+  h->lo_ptr = lo_ptr;
+  h->up_ptr = up_ptr;
+  char* w = h->ws;
+  h->a64 = (double*)(w + pl.o_a64);
+  h->a32 = (float*)(w + pl.o_a32);
+  h->c64 = (double*)(w + pl.o_c64);
+  h->lo_ptr_d = (int*)(w + pl.o_lo_ptr);
+  h->lo_ent_d = (int*)(w + pl.o_lo_ent);
+  h->lo_g64 = (double*)(w + pl.o_lo_g64);
+  h->lo_g32 = (float*)(w + pl.o_lo_g32);
+  h->up_ptr_d = (int*)(w + pl.o_up_ptr);
+  h->up_ent_d = (int*)(w + pl.o_up_ent);
+  h->up_g64 = (double*)(w + pl.o_up_g64);
+  h->up_g32 = (float*)(w + pl.o_up_g32);
+  h->pair_ptr_d = (int*)(w + pl.o_pair_ptr);
+  h->pair_a_d = (int*)(w + pl.o_pair_a);
+  h->pair_b_d = (int*)(w + pl.o_pair_b);
+  h->pair_g_d = (double*)(w + pl.o_pair_g);
+  double** vecs[7] = {&h->r, &h->z, &h->pv, &h->q, &h->lam, &h->tmp, &h->rhs};
+  for (int i = 0; i < 7; ++i) *vecs[i] = (double*)(w + pl.o_vec[i]);
+  h->rw = w + pl.o_rw;
+  h->zw = op->inner_precision == 32 ? (void*)(w + pl.o_zw) : nullptr;
+  void** pcgv[6] = {&h->pR0, &h->pR1, &h->pP0, &h->pP1, &h->pQ, &h->pZ};
+  for (int i = 0; i < 6; ++i) *pcgv[i] = w + pl.o_pcg[i];
+  h->pcg_maxcols = pl.maxcols;
+  h->pcgsc.part = (double*)(w + pl.o_part);
+  h->pcgsc.done_at = (int*)(w + pl.o_done);
+  h->pcgsc.iters = (int*)(w + pl.o_iters);
+  h->pcgsc.ndone = (unsigned*)(w + pl.o_ndone);
+  h->pcgsc.status = (int*)(w + pl.o_status);
+  h->red_part = (double*)(w + pl.o_red_part);
+  h->red_out = (double*)(w + pl.o_red_out);
+  h->host_out.assign(std::max(64, M + 1), 0.0);
+  hipStream_t s = h->stream;
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(h->a64, a64.data(), sizeof(double) * a64.size());
+  if (e == hipSuccess) e = up(h->a32, a32.data(), sizeof(float) * a32.size());
+  if (e == hipSuccess) e = up(h->c64, c64.data(), sizeof(double) * c64.size());
+  if (e == hipSuccess) e = up(h->lo_ptr_d, lo_ptr.data(), sizeof(int) * lo_ptr.size());
+  if (e == hipSuccess) e = up(h->lo_ent_d, lo_ent.data(), sizeof(int) * lo_ent.size());
+  if (e == hipSuccess) e = up(h->lo_g64, lo_g.data(), sizeof(double) * lo_g.size());
+  if (e == hipSuccess) e = up(h->lo_g32, lo_g32.data(), sizeof(float) * lo_g32.size());
+  if (e == hipSuccess) e = up(h->up_ptr_d, up_ptr.data(), sizeof(int) * up_ptr.size());
+  if (e == hipSuccess) e = up(h->up_ent_d, up_ent.data(), sizeof(int) * up_ent.size());
+  if (e == hipSuccess) e = up(h->up_g64, up_g.data(), sizeof(double) * up_g.size());
+  if (e == hipSuccess) e = up(h->up_g32, up_g32.data(), sizeof(float) * up_g32.size());
+  if (e == hipSuccess) e = up(h->pair_ptr_d, pair_ptr.data(), sizeof(int) * pair_ptr.size());
+  if (e == hipSuccess) e = up(h->pair_a_d, pair_a.data(), sizeof(int) * pair_a.size());
+  if (e == hipSuccess) e = up(h->pair_b_d, pair_b.data(), sizeof(int) * pair_b.size());
+  if (e == hipSuccess) e = up(h->pair_g_d, pair_g.data(), sizeof(double) * pair_g.size());
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(SG_EDEVICE, std::string("upload failed: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return SG_OK;
+}
+
+int sg_sizes(sg_handle h, int64_t* n, int32_t* P, int32_t* level_off, int32_t* alpha) {
+  if (!h) return fail(SG_EINVAL, "null handle");
+  if (n) *n = h->n;
+  if (P) *P = h->P;
+  if (level_off)
+    for (int l = 0; l <= h->p + 1; ++l) level_off[l] = h->off[l];
+  if (alpha)
+    for (size_t i = 0; i < h->alpha.size(); ++i) alpha[i] = h->alpha[i];
+  return SG_OK;
+}
+
+int sg_set_opts(sg_handle h, const sg_opts* opts) {
+  if (!h || !opts) return fail(SG_EINVAL, "null handle or options");
+  sg_problem dummy{};
+  dummy.n_e = h->n_e;
+  dummy.M = 0;
+  dummy.p = h->p;
+  dummy.theta0 = h->theta0;
+  int rc = validate(&dummy, opts);
+  if (rc) return rc;
+  if (opts->inner_precision != h->opts.inner_precision)
+    return fail(SG_EINVAL, "inner precision is fixed at setup");
+  h->opts = *opts;
+  return SG_OK;
+}
+
+int sg_matvec(sg_handle h, const double* U, double* Y) {
+  if (!h || !U || !Y) return fail(SG_EINVAL, "null argument");
+  if (U == Y) return fail(SG_EINVAL, "U and Y must be distinct");
+  matvec(h, U, Y);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_apply_hsc(sg_handle h, const double* R, double* Z) {
+  if (!h || !R || !Z) return fail(SG_EINVAL, "null argument");
+  if (R == Z) return fail(SG_EINVAL, "R and Z must be distinct");
+  long a = 0, b = 0;
+  for (int l = 0; l < sgk::kMaxLevels; ++l) h->inner_it_max[l] = 0;
+  int rc = apply_hsc(h, R, Z, &a, &b);
+  if (rc) return rc;
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_apply_mean(sg_handle h, const double* R, double* Z) {
+  if (!h || !R || !Z) return fail(SG_EINVAL, "null argument");
+  if (R == Z) return fail(SG_EINVAL, "R and Z must be distinct");
+  long b = 0;
+  int rc = apply_mean(h, R, Z, &b);
+  if (rc) return rc;
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_inner_solve(sg_handle h, const double* B, double* X, int32_t ncols, int32_t* iters) {
+  if (!h || !B || !X) return fail(SG_EINVAL, "null argument");
+  if (ncols < 0 || ncols > h->P) return fail(SG_EINVAL, "ncols must be in 0..P");
+  if (ncols == 0) return SG_OK;
+  std::vector<int> it;
+  const long N = h->n * (long)ncols;
+  int rc;
+  if (h->opts.inner_precision == 64) {
+    rc = run_pcg<double>(h, B, X, ncols, -1, &it);
+  } else {
+    float* rw = (float*)h->rw;
+    float* zw = (float*)h->zw;
+    sgk::launch_copy_d2f(rw, B, N, h->stream);
+    rc = run_pcg<float>(h, rw, zw, ncols, -1, &it);
+    if (!rc) sgk::launch_copy_f2d(X, zw, N, h->stream);
+  }
+  if (rc) return rc;
+  SG_HIP(hipStreamSynchronize(h->stream));
+  if (iters)
+    for (int c = 0; c < ncols; ++c) iters[c] = it[c];
+  return SG_OK;
+}
+
+int sg_coupling(sg_handle h, int32_t level, int32_t dir, double* R, const double* V) {
+  if (!h || !R || !V) return fail(SG_EINVAL, "null argument");
+  if (level < 1 || level > h->p) return fail(SG_EINVAL, "level must be in 1..p");
+  if (dir != 0 && dir != 1) return fail(SG_EINVAL, "dir must be 0 or 1");
+  if ((const double*)R == V) return fail(SG_EINVAL, "R and V must be distinct");
+  coupling<double>(h, level, dir, R, V);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_solve(sg_handle h, const double* F, double* U, double rtol, int32_t maxit, int32_t use_x0, sg_stats* stats) {
+  if (!h || !F || !U) return fail(SG_EINVAL, "null argument");
+  if (F == U) return fail(SG_EINVAL, "F and U must be distinct");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(SG_EINVAL, "rtol must be >= 0 and maxit >= 0");
+  return fcg(h, F, U, rtol, maxit, use_x0, h->opts.precond, stats);
+}
+
+int sg_qoi(sg_handle h, const double* U, const double* w_mean, const double* w_var, double* Q) {
+  if (!h || !U || !w_mean || !w_var || !Q) return fail(SG_EINVAL, "null argument");
+  sgk::launch_qoi(U, w_mean, w_var, h->n, h->P, h->red_part, h->red_out, h->stream);
+  int rc = read_out(h, 1);
+  if (rc) return rc;
+  *Q = h->host_out[0];
+  return SG_OK;
+}
+
+int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const double* w_var, double rtol,
+                    int32_t maxit, double* Q, double* grad, double* Lambda, sg_stats* stats) {
+  if (!h || !U || !w_mean || !w_var || !Q || !grad) return fail(SG_EINVAL, "null argument");
+  int rc = sg_qoi(h, U, w_mean, w_var, Q);
+  if (rc) return rc;
+  sgk::launch_qoi_grad(U, w_mean, w_var, h->n, h->P, h->rhs, h->stream);
+  double* lam = Lambda ? Lambda : h->lam;
+  if (lam == U) return fail(SG_EINVAL, "Lambda must differ from U");
+  const int status = fcg(h, h->rhs, lam, rtol, maxit, 0, h->opts.precond, stats);
+  if (status < 0) return status;
+  sgk::ContractArgs c{};
+  c.n_e = h->n_e;
+  c.nx = h->nx;
+  c.n = h->n;
+  c.M = h->M;
+  c.P = h->P;
+  c.Lam = lam;
+  c.U = U;
+  c.c = h->c64;
+  c.pair_ptr = h->pair_ptr_d;
+  c.pair_a = h->pair_a_d;
+  c.pair_b = h->pair_b_d;
+  c.pair_g = h->pair_g_d;
+  c.partials = h->red_part;
+  c.out = h->red_out;
+  sgk::launch_contract(c, h->stream);
+  rc = read_out(h, h->M + 1);
+  if (rc) return rc;
+  for (int k = 0; k <= h->M; ++k) grad[k] = h->host_out[k];
+  return status;
+}
+
+void sg_destroy(sg_handle h) { delete h; }
+
+const char* sg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// Internal declarations shared by the host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sg.h"
+
+namespace sgk {
+
+constexpr int kMaxCheb = 16;     // largest supported Chebyshev degree
+constexpr int kMaxLevels = 16;   // largest supported chaos degree + 1
+constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
+
+// Chaos neighbour lists of the Hermite Galerkin matrices G_k (k >= 1): for
+// each chaos row a, the entries (k, b, g) with (G_k)_{ab} = g != 0 split into
+// lower neighbours (b = a - e_k, g = sqrt(a_k)) and upper neighbours
+// (b = a + e_k, g = sqrt(a_k + 1)). CSR over rows; an entry is packed as
+// b | (k << 20) with k in 1..M.
+template <typename T>
+struct ChaosLists {
+  const int* lo_ptr;
+  const int* lo_ent;
+  const T* lo_g;
+  const int* up_ptr;
+  const int* up_ent;
+  const T* up_g;
+};
+
+// out[a] = rcoef * rsrc[a] + diag * K_Lap in[a] + sgn * sum_{entries (k,b,g) of a} g * K_k in[b]
+// for chaos rows a in [row0, row0 + nrows). Columns live at base + col * n.
+template <typename T>
+struct SgOpArgs {
+  int n_e;
+  int nx;
+  long n;
+  int row0;
+  int nrows;
+  int use_lower;
+  int use_upper;
+  T diag;
+  T rcoef;
+  T sgn;
+  const T* in;
+  const T* rsrc;
+  T* out;
+  const T* a;  // [M][n_e * n_e] element coefficients of K_1..K_M
+  ChaosLists<T> lists;
+};
+
+template <typename T>
+void launch_sgop(const SgOpArgs<T>& args, hipStream_t s);
+
+// Persistent batched PCG on K_0 = theta0 * K_Lap (one independent solve per column).
+struct PcgScratch {
+  double* part;     // [6][ncols][ntiles] partial sums
+  int* done_at;     // [ncols]
+  int* iters;       // [ncols]
+  unsigned* ndone;  // [1]
+  int* status;      // [1]
+};
+
+template <typename T>
+struct PcgArgs {
+  int nx;
+  long n;
+  int ncols;
+  const T* B;
+  T* X;
+  T* R0;
+  T* R1;
+  T* P0;
+  T* P1;
+  T* Q;
+  T* Z;
+  PcgScratch sc;
+  int ntx;
+  int ntiles;
+  int degree;
+  int maxit;
+  double rtol;
+  T c0;        // centre weight of K_0: theta0 * 8/3
+  T c1;        // neighbour weight of K_0: -theta0 / 3
+  T inv_diag;  // 1 / (theta0 * 8/3)
+  T inv_theta; // 1 / centre of the Chebyshev interval
+  T chebA[kMaxCheb];
+  T chebB[kMaxCheb];
+};
+
+template <typename T>
+hipError_t launch_pcg(const PcgArgs<T>& args, int tile, int max_blocks, hipStream_t s);
+
+template <typename T>
+size_t pcg_scratch_bytes(int ncols, int ntiles);
+
+// FP64 BLAS-1 style kernels with deterministic two-stage reductions.
+void launch_dots(const double* const* a, const double* const* b, int ndots, long N, double* partials,
+                 double* out, hipStream_t s);
+void launch_fcg_update(double* x, double* r, const double* p, const double* q, double alpha, long N,
+                       double* partials, double* out, hipStream_t s);
+void launch_xpby(double* p, const double* z, double beta, long N, hipStream_t s);
+void launch_axpby(double* y, const double* x, double a, double b, long N, hipStream_t s);  // y = a x + b y
+void launch_fill(double* y, double v, long N, hipStream_t s);
+void launch_copy_d2f(float* dst, const double* src, long N, hipStream_t s);
+void launch_copy_f2d(double* dst, const float* src, long N, hipStream_t s);
+void launch_copy_d2d(double* dst, const double* src, long N, hipStream_t s);
+void launch_sub(double* r, const double* f, const double* y, long N, hipStream_t s);  // r = f - y
+
+// Adjoint support.
+void launch_qoi(const double* U, const double* wm, const double* wv, long n, int P, double* partials,
+                double* out, hipStream_t s);
+void launch_qoi_grad(const double* U, const double* wm, const double* wv, long n, int P, double* G,
+                     hipStream_t s);
+struct ContractArgs {
+  int n_e;
+  int nx;
+  long n;
+  int M;
+  int P;
+  const double* Lam;
+  const double* U;
+  const double* c;      // [M][n_e * n_e] sigma * phi_k(e)
+  const int* pair_ptr;  // [M + 1] start of the (a, b, g) pairs of G_k, k = 1..M
+  const int* pair_a;
+  const int* pair_b;
+  const double* pair_g;
+  double* partials;     // [nblocks][M + 1]
+  double* out;          // [M + 1]
+};
+void launch_contract(const ContractArgs& args, hipStream_t s);
+
+}  // namespace sgk
+
+// Host-side context behind sg_handle.
+struct sg_ctx {
+  int n_e, M, p, P, nx;
+  long n;
+  double theta0, sigma;
+  double lmin, lmax;  // spectrum of D^-1 K_0
+  std::vector<double> s;
+  std::vector<int> off;
+  std::vector<int> alpha;  // [P][M]
+  sg_opts opts;
+  hipStream_t stream;
+  int num_cu;
+  int tile;
+  // host copies of the chaos lists (for counters)
+  std::vector<int> lo_ptr, up_ptr;
+  // device arrays inside the workspace
+  char* ws;
+  size_t ws_bytes;
+  double* a64;
+  float* a32;
+  double* c64;
+  int *lo_ptr_d, *lo_ent_d, *up_ptr_d, *up_ent_d;
+  double *lo_g64, *up_g64;
+  float *lo_g32, *up_g32;
+  int *pair_ptr_d, *pair_a_d, *pair_b_d;
+  double* pair_g_d;
+  double *r, *z, *pv, *q, *lam, *tmp, *rhs;  // FP64 n x P blocks
+  void* rw;  // inner-precision working residual, n x P
+  void* zw;  // inner-precision output, n x P (FP32 only)
+  void *pR0, *pR1, *pP0, *pP1, *pQ, *pZ;  // inner PCG state, n x maxcols
+  int pcg_maxcols;
+  sgk::PcgScratch pcgsc;
+  double* red_part;  // reduction partials
+  double* red_out;   // reduction results (device)
+  std::vector<double> host_out;  // host mirror of red_out
+  long inner_it_acc;
+  int inner_it_max[sgk::kMaxLevels];
+};

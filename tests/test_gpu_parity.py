@@ -1,0 +1,191 @@
+"""GPU path (through the C-ABI) against the CPU oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import hsc, krylov, sg, solve  # noqa: E402
+from sg_inputs import named_problem, random_block  # noqa: E402
+
+
+def _b():
+    from paper_1205_1864_amd import binding
+    return binding
+
+
+def _sys(**kw):
+    prob = named_problem("small", **kw)
+    return prob, sg.build_system(prob)
+
+
+def _dev(A):
+    return _b().to_device_block(A)
+
+
+SHAPES = [dict(), dict(n_e=7, M=3, p=3), dict(n_e=33, M=5, p=2), dict(n_e=19, M=2, p=4),
+          dict(n_e=10, M=3, p=0), dict(n_e=9, M=0, p=2), dict(n_e=40, M=6, p=3, sigma=0.15)]
+
+
+@pytest.mark.parametrize("kw", SHAPES)
+def test_matvec_parity(kw):
+    b = _b()
+    prob, s = _sys(**kw)
+    print(f"matvec parity n_e={prob.n_e} M={prob.M} p={prob.p}", flush=True)
+    solver = b.SGSolver(prob)
+    U = random_block(prob.P, prob.n, seed=11)
+    Y = solver.sg_matvec(_dev(U)).cpu().numpy()
+    Yo = sg.matvec(s, U.T).T
+    assert np.linalg.norm(Y - Yo) <= 1e-12 * np.linalg.norm(Yo)
+
+
+def test_matvec_parity_scale():
+    b = _b()
+    prob = named_problem("scale")
+    print("matvec parity 256^2 M=10 p=3", flush=True)
+    s = sg.build_system(prob)
+    solver = b.SGSolver(prob)
+    U = random_block(prob.P, prob.n, seed=0)
+    Y = solver.sg_matvec(_dev(U)).cpu().numpy()
+    Yo = sg.matvec(s, U.T).T
+    assert np.linalg.norm(Y - Yo) <= 1e-12 * np.linalg.norm(Yo)
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-11), (32, 2e-5)])
+@pytest.mark.parametrize("degree,tile", [(4, 0), (1, 16), (6, 32)])
+def test_inner_solve_fixed_iterations(prec, tol, degree, tile):
+    b = _b()
+    prob, s = _sys(n_e=45, M=2, p=2)
+    print(f"inner solve prec={prec} degree={degree} tile={tile}", flush=True)
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=degree, inner_maxit=9,
+                                        inner_rtol=0.0, tile=tile))
+    B = random_block(5, prob.n, seed=3)
+    B[2] = 0.0
+    X, its = solver.sg_inner_solve(_dev(B))
+    X = X.cpu().numpy()
+    prec_o = krylov.make_chebyshev(s.K[0], prob.n_e, prob.theta0, degree)
+    st = krylov.InnerStats()
+    Xo = krylov.pcg_columns(s.K[0], B.T, prec_o, 0.0, 9, st).T
+    assert list(its) == list(st.iterations)
+    assert np.all(X[2] == 0.0)
+    for c in (0, 1, 3, 4):
+        assert np.linalg.norm(X[c] - Xo[c]) <= tol * np.linalg.norm(Xo[c])
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_inner_solve_to_tolerance(prec):
+    b = _b()
+    prob, s = _sys(n_e=64, M=2, p=3)
+    rtol = 1e-6 if prec == 64 else 1e-4
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=4, inner_maxit=500, inner_rtol=rtol))
+    B = random_block(7, prob.n, seed=4)
+    X, its = solver.sg_inner_solve(_dev(B))
+    X = X.cpu().numpy()
+    prec_o = krylov.make_chebyshev(s.K[0], prob.n_e, prob.theta0, 4)
+    st = krylov.InnerStats()
+    krylov.pcg_columns(s.K[0], B.T, prec_o, rtol, 500, st)
+    for c in range(7):
+        r = B[c] - s.K[0] @ X[c]
+        assert np.linalg.norm(r) <= rtol * 1.2 * np.linalg.norm(B[c])
+        assert abs(int(its[c]) - int(st.iterations[c])) <= 1
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(n_e=21, M=3, p=3), dict(n_e=12, M=5, p=2)])
+def test_coupling_parity(kw):
+    b = _b()
+    prob, s = _sys(**kw)
+    solver = b.SGSolver(prob)
+    rng = np.random.default_rng(7)
+    for l in range(1, prob.p + 1):
+        for d in (0, 1):
+            R = rng.standard_normal((prob.P, prob.n))
+            V = rng.standard_normal((prob.P, prob.n))
+            Rg = solver.sg_coupling(l, d, _dev(R), _dev(V)).cpu().numpy()
+            Ro = R.T.copy()
+            lo, hi = s.off[l], s.off[l + 1]
+            if d == 0:
+                Ro[:, :lo] -= sg.level_block(s, slice(0, lo), slice(lo, hi))(V.T[:, lo:hi])
+            else:
+                Ro[:, lo:hi] -= sg.level_block(s, slice(lo, hi), slice(0, lo))(V.T[:, :lo])
+            assert np.linalg.norm(Rg - Ro.T) <= 1e-13 * np.linalg.norm(Ro)
+
+
+@pytest.mark.parametrize("which", ["hsc", "mean"])
+def test_preconditioner_tight_parity(which):
+    b = _b()
+    prob, s = _sys(n_e=24, M=3, p=3)
+    solver = b.SGSolver(prob, b.Options(inner_precision=64, inner_rtol=1e-13, inner_maxit=2000))
+    R = random_block(prob.P, prob.n, seed=8)
+    Z = (solver.sg_apply_hsc if which == "hsc" else solver.sg_apply_mean)(_dev(R)).cpu().numpy()
+    ex = hsc.ExactMeanSolver(s)
+    Zo = (hsc.hsc_apply(s, R.T, ex) if which == "hsc" else hsc.mean_apply(s, R.T, ex)).T
+    assert np.linalg.norm(Z - Zo) <= 1e-9 * np.linalg.norm(Zo)
+
+
+@pytest.mark.parametrize("prec,pc", [(64, "hsc"), (32, "hsc"), (64, "mean"), (32, "mean")])
+def test_solve_small(prec, pc):
+    b = _b()
+    prob, s = _sys()
+    F = prob.load_block()
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, precond=pc, inner_rtol=1e-4))
+    U, st = solver.sg_solve(_dev(F), rtol=1e-8, maxit=100)
+    U = U.cpu().numpy()
+    assert st["rc"] == 0
+    Ud = solve.solve_direct(s, F.T.copy())
+    tr = solve.true_relres(s, F.T, U.T)
+    assert tr <= 1.05e-8
+    assert abs(st["true_relres"] - tr) <= 1e-3 * tr + 1e-15
+    A = sg.assemble(s).toarray()
+    ev = np.linalg.eigvalsh(A)
+    assert np.linalg.norm(U.T - Ud) / np.linalg.norm(Ud) <= ev.max() / ev.min() * 1e-8
+    if pc == "hsc":
+        P = prob.P
+        assert st["n_blocksolve"] == st["outer_it"] * (2 * (P - 1) + 1)
+        n_b = int(np.count_nonzero(sum(np.abs(G) for G in s.G)))
+        assert st["n_blockmv"] == st["outer_it"] * (n_b - P)
+
+
+def test_solve_tight_matches_oracle_iterates():
+    """With (nearly) exact inner solves the GPU FCG follows the oracle's FCG."""
+    b = _b()
+    prob, s = _sys()
+    F = prob.load_block()
+    solver = b.SGSolver(prob, b.Options(inner_precision=64, inner_rtol=1e-14, inner_maxit=3000))
+    U, st = solver.sg_solve(_dev(F), rtol=1e-10, maxit=50)
+    res, _, _ = solve.solve_fcg(s, F.T.copy(), "hsc", "exact", rtol=1e-10)
+    assert st["outer_it"] == res.iterations
+    assert np.linalg.norm(U.cpu().numpy().T - res.x) <= 1e-10 * np.linalg.norm(res.x)
+
+
+def test_solve_edge_cases():
+    b = _b()
+    prob, s = _sys(n_e=12, M=2, p=2)
+    solver = b.SGSolver(prob)
+    Z = np.zeros((prob.P, prob.n))
+    U, st = solver.sg_solve(_dev(Z))
+    assert st["rc"] == 0 and st["outer_it"] == 0 and float(U.abs().max()) == 0.0
+    F = prob.load_block()
+    U, st = solver.sg_solve(_dev(F), rtol=1e-12, maxit=1)
+    assert st["rc"] == b.SG_NOT_CONVERGED and st["outer_it"] == 1
+    Fn = F.copy()
+    Fn[0, 3] = np.nan
+    with pytest.raises(b.SGError):
+        solver.sg_solve(_dev(Fn))
+
+
+def test_adjoint_parity_small():
+    from oracle import adjoint
+    from sg_inputs import qoi_weights
+    b = _b()
+    prob, s = _sys(n_e=16, M=4, p=3)
+    F = prob.load_block()
+    wm, wv = qoi_weights(prob.n_e)
+    solver = b.SGSolver(prob, b.Options(inner_precision=64, inner_rtol=1e-12))
+    U, st = solver.sg_solve(_dev(F), rtol=1e-12)
+    Q, g, st2 = solver.sg_adjoint_grad(U, b.to_device_vec(wm), b.to_device_vec(wv), rtol=1e-12)
+    Ud = solve.solve_direct(s, F.T.copy())
+    Qo, go, _ = adjoint.adjoint_gradient(s, Ud, wm, wv, lambda R: solve.solve_direct(s, R))
+    assert abs(Q - Qo) <= 1e-10 * abs(Qo)
+    assert np.max(np.abs(g - go)) <= 1e-8 * np.max(np.abs(go))
