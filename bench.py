@@ -1,0 +1,236 @@
+"""Benchmark of the SG solver hot path on one MI355X.
+
+Workload (timed step): the hierarchical-Schur-preconditioned flexible CG solve
+of the 256^2 Q1 problem with M = 10 KL terms and Hermite degree p = 3
+(P = 286, 18.6M unknowns) to relative residual 1e-8, FP64 inner PCG with a
+degree-4 Jacobi-Chebyshev preconditioner stopped at 1e-4. Inputs are seeded
+and synthetic and resident in HBM before timing starts.
+
+Also reported (outside the timed steps): the SG matvec bandwidth (cold and
+warm Infinity Cache), the FP32-inner and mean-preconditioned solves, the
+adjoint gradient of the 512^2 differentiation case, the roofline of the
+dominant kernel, and the CPU oracle timed on a bounded sample on the host.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "SG solve s to relres 1e-8 + matvec HBM GB/s (256², M=10, p=3); adjoint grad s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _ensure_built():
+    from paper_1205_1864_amd.build import LIB, build
+    if not os.path.exists(LIB):
+        build()
+
+
+def time_matvec(solver, U, Y, reps, cold, flush=None):
+    import torch
+    stream = solver.stream
+    times = []
+    for _ in range(reps):
+        if cold:
+            flush.add_(1.0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        solver.sg_matvec(U, Y)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times)), times
+
+
+def cpu_baseline(prob, outer_its, budget_s=30.0):
+    """The oracle on the host cores: one matvec and one HSC action at full size."""
+    import resource  # noqa: F401
+    from oracle import hsc, sg
+    t0 = time.perf_counter()
+    c0 = time.process_time()
+    s = sg.build_system(prob)
+    t_setup = time.perf_counter() - t0
+    F = prob.load_block().T.copy()
+    R = np.random.default_rng(1).standard_normal((s.n, s.P)) * 1e-3
+    R[:, 0] += F[:, 0]
+    t1 = time.perf_counter()
+    sg.matvec(s, R)
+    t_mv = time.perf_counter() - t1
+    ex = hsc.ExactMeanSolver(s)
+    t2 = time.perf_counter()
+    hsc.hsc_apply(s, R, ex)
+    t_hsc = time.perf_counter() - t2
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    est = outer_its * (t_mv + t_hsc) + t_mv
+    return {
+        "value": est, "unit": "s",
+        "cores": len(os.sched_getaffinity(0)),
+        "effective_cores": round(cpu / wall, 2),
+        "kind": "oracle",
+        "sample": (f"one oracle SG matvec ({t_mv:.2f} s) and one HSC action with exact sparse-LU inner "
+                   f"solves ({t_hsc:.2f} s) at 256^2, M=10, p=3, scaled by the GPU solve's {outer_its} outer "
+                   f"iterations plus one residual matvec; oracle setup {t_setup:.1f} s not included"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="only the timed solve and the matvec")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    _ensure_built()
+    from paper_1205_1864_amd.binding import Options, SGSolver, to_device_block, to_device_vec
+    from sg_inputs import named_problem, qoi_weights, random_block
+
+    torch.cuda.set_device(0)
+    prob = named_problem("scale")
+    F = to_device_block(prob.load_block())
+    opts64 = Options(inner_precision=64, cheb_degree=4, inner_maxit=2000, precond="hsc", inner_rtol=1e-4)
+    solver = SGSolver(prob, opts64)
+    U = solver.empty()
+
+    # ---- timed steps: the HSC-FCG solve
+    for _ in range(args.warmup):
+        _, wst = solver.sg_solve(F, U, rtol=1e-8, maxit=100)
+        log(f"warm-up solve: {wst['ms']:.1f} ms, outer {wst['outer_it']}, inner {wst['inner_it_total']}")
+    torch.cuda.synchronize()
+    ms_inner = bytes_inner = 0.0
+    launches = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = solver.sg_solve(F, U, rtol=1e-8, maxit=100)
+        ms_inner += st["ms_inner"]
+        bytes_inner += st["inner_bytes"]
+        launches += st["inner_launches"]
+        log(f"timed solve: {st['ms']:.1f} ms, outer {st['outer_it']}, relres {st['true_relres']:.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solve_s = elapsed / max(1, args.steps)
+    U64 = U.clone()
+
+    # ---- SG matvec bandwidth
+    alg_bytes_mv = 2.0 * prob.n * prob.P * 8 + prob.M * prob.n_e ** 2 * 8
+    Ur = to_device_block(random_block(prob.P, prob.n, seed=0))
+    Yr = solver.empty()
+    time_matvec(solver, Ur, Yr, 5, cold=False)
+    warm_ms, _ = time_matvec(solver, Ur, Yr, 50, cold=False)
+    flush = torch.zeros(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    cold_ms, _ = time_matvec(solver, Ur, Yr, 30, cold=True, flush=flush)
+    del flush
+    log(f"matvec cold {cold_ms:.3f} ms warm {warm_ms:.3f} ms")
+    mv_cold = alg_bytes_mv / (cold_ms * 1e-3) / 1e9
+    mv_warm = alg_bytes_mv / (warm_ms * 1e-3) / 1e9
+
+    extra = {
+        "outer_it": st["outer_it"], "true_relres": st["true_relres"], "kappa_est": st["kappa_est"],
+        "inner_it_total": st["inner_it_total"], "inner_it_max_per_level": st["inner_it_max"][: prob.p + 1],
+        "n_blockmv": st["n_blockmv"], "n_blocksolve": st["n_blocksolve"],
+        "ms_precond": st["ms_precond"], "ms_matvec_in_solve": st["ms_matvec"],
+        "matvec_ms_cold": cold_ms, "matvec_ms_warm": warm_ms,
+        "matvec_GBs_cold": mv_cold, "matvec_GBs_warm": mv_warm,
+        "matvec_frac_cold": mv_cold / HBM_PEAK_GBS, "matvec_alg_bytes": alg_bytes_mv,
+    }
+
+    if not args.no_extra:
+        # FP32 inner (precision variant) and mean-based comparators
+        for label, o in [("hsc_fp32", Options(inner_precision=32, precond="hsc", inner_maxit=2000)),
+                         ("mean_fp64", Options(inner_precision=64, precond="mean", inner_maxit=2000)),
+                         ("mean_fp32", Options(inner_precision=32, precond="mean", inner_maxit=2000))]:
+            sv = SGSolver(prob, o)
+            Uv = sv.empty()
+            sv.sg_solve(F, Uv, rtol=1e-8, maxit=200)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, sv_st = sv.sg_solve(F, Uv, rtol=1e-8, maxit=200)
+            torch.cuda.synchronize()
+            extra[f"solve_s_{label}"] = time.perf_counter() - t1
+            log(f"{label}: {extra[f'solve_s_{label}']:.3f} s, outer {sv_st['outer_it']}")
+            extra[f"outer_it_{label}"] = sv_st["outer_it"]
+            extra[f"inner_it_total_{label}"] = sv_st["inner_it_total"]
+            extra[f"true_relres_{label}"] = sv_st["true_relres"]
+            extra[f"rel_diff_vs_fp64_hsc_{label}"] = float(torch.linalg.norm(Uv - U64) / torch.linalg.norm(U64))
+            if label == "hsc_fp32":
+                # FP32-inner error of one preconditioner action against the FP64 one
+                Rr = to_device_block(random_block(prob.P, prob.n, seed=5))
+                z32 = sv.sg_apply_hsc(Rr)
+                z64 = solver.sg_apply_hsc(Rr)
+                extra["hsc_action_rel_err_fp32"] = float(torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64))
+            del sv, Uv
+            torch.cuda.empty_cache()
+
+        # adjoint gradient, 512^2, M = 8, p = 3
+        pg = named_problem("grad")
+        sg_ = SGSolver(pg, Options(inner_precision=64, precond="hsc", inner_maxit=2000))
+        Fg = to_device_block(pg.load_block())
+        wm, wv = qoi_weights(pg.n_e)
+        wm_d, wv_d = to_device_vec(wm), to_device_vec(wv)
+        Ug = sg_.empty()
+        sg_.sg_solve(Fg, Ug, rtol=1e-8, maxit=100)  # warm-up
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, fst = sg_.sg_solve(Fg, Ug, rtol=1e-8, maxit=100)
+        Q, grad, ast = sg_.sg_adjoint_grad(Ug, wm_d, wv_d, rtol=1e-8, maxit=100)
+        torch.cuda.synchronize()
+        extra["adjoint_grad_s"] = time.perf_counter() - t2
+        log(f"adjoint 512^2: {extra['adjoint_grad_s']:.3f} s")
+        extra["adjoint_outer_it"] = [fst["outer_it"], ast["outer_it"]]
+        extra["adjoint_Q"] = Q
+        extra["adjoint_grad"] = [float(g) for g in grad]
+        del sg_, Ug, Fg
+        torch.cuda.empty_cache()
+
+    achieved = bytes_inner / (ms_inner * 1e-3) / 1e9 if ms_inner > 0 else 0.0
+    roofline = {
+        "kernel": "pcg_kernel (persistent batched inner PCG, all launches of the timed solves)",
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "avg_launch_ms": ms_inner / max(1, launches), "launches": launches,
+        "alg_bytes_per_launch": bytes_inner / max(1, launches),
+    }
+    roofline_mv = {
+        "kernel": "sgop_kernel<double> (SG matvec)", "bound": "hbm", "achieved": mv_cold, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": mv_cold / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": cold_ms,
+        "alg_bytes_per_launch": alg_bytes_mv,
+    }
+    out = {
+        "metric": METRIC, "value": solve_s, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": solve_s * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "HSC-FCG solve, 256^2 Q1, M=10, p=3 (P=286, 18.6M unknowns), "
+                               "FP64 inner PCG Jacobi-Chebyshev d=4 to 1e-4, outer to 1e-8",
+                   "n_e": prob.n_e, "M": prob.M, "p": prob.p, "P": prob.P, "sigma": prob.sigma, "L": prob.L},
+        "roofline": roofline, "roofline_matvec": roofline_mv, "extra": extra,
+    }
+    if not args.no_cpu:
+        log("cpu oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(prob, st["outer_it"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

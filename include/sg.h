@@ -118,6 +118,9 @@ typedef struct sg_stats {
   double ms;                  /* wall time of the call in milliseconds */
   double ms_precond;          /* time in preconditioner actions */
   double ms_matvec;           /* time in SG matvecs */
+  double ms_inner;            /* device time of the inner PCG launches (HIP events on the stream) */
+  double inner_bytes;         /* algorithmic bytes of those launches: per column (11 its + 3) n w */
+  int64_t inner_launches;     /* number of inner PCG launches */
 } sg_stats;
 
 /* Device workspace needed by sg_setup for this problem and options. */

@@ -42,7 +42,9 @@ class SgStats(ctypes.Structure):
                 ("n_blocksolve", ctypes.c_int64), ("inner_it_max", ctypes.c_int32 * 16),
                 ("relres", ctypes.c_double), ("true_relres", ctypes.c_double),
                 ("kappa_est", ctypes.c_double), ("ms", ctypes.c_double),
-                ("ms_precond", ctypes.c_double), ("ms_matvec", ctypes.c_double)]
+                ("ms_precond", ctypes.c_double), ("ms_matvec", ctypes.c_double),
+                ("ms_inner", ctypes.c_double), ("inner_bytes", ctypes.c_double),
+                ("inner_launches", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -252,13 +252,22 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;
   fill_pcg_consts<T>(h, a);
   a.degree = degree;
+  SG_HIP(hipEventRecord(h->ev0, h->stream));
   SG_HIP(sgk::launch_pcg<T>(a, tile, 0, h->stream));
+  SG_HIP(hipEventRecord(h->ev1, h->stream));
   std::vector<int> it(ncols);
   SG_HIP(hipMemcpyAsync(it.data(), h->pcgsc.iters, sizeof(int) * ncols, hipMemcpyDeviceToHost, h->stream));
   SG_HIP(hipStreamSynchronize(h->stream));
+  float ms = 0.f;
+  SG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->inner_ms_acc += ms;
+  h->inner_launch_acc += 1;
   int mx = 0;
   for (int v : it) {
     h->inner_it_acc += v;
+    // phase A reads z, p and writes p, q; phase B reads x, p, r, q and writes x, r, z;
+    // the start reads b and writes z and x
+    h->inner_bytes_acc += (11.0 * v + 3.0) * (double)h->n * sizeof(T);
     mx = std::max(mx, v);
   }
   if (level_for_stats >= 0 && level_for_stats < sgk::kMaxLevels)
@@ -456,6 +465,9 @@ int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x
   const long N = h->n * (long)h->P;
   sg_stats S{};
   h->inner_it_acc = 0;
+  h->inner_ms_acc = 0.0;
+  h->inner_bytes_acc = 0.0;
+  h->inner_launch_acc = 0;
   for (int l = 0; l < sgk::kMaxLevels; ++l) h->inner_it_max[l] = 0;
   long nbmv = 0, nbs = 0;
   double ms_pc = 0.0, ms_mv = 0.0;
@@ -553,6 +565,9 @@ int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x
   S.relres = relres;
   S.true_relres = true_rel;
   S.kappa_est = lanczos_kappa(alphas, betas);
+  S.ms_inner = h->inner_ms_acc;
+  S.inner_bytes = h->inner_bytes_acc;
+  S.inner_launches = h->inner_launch_acc;
   S.ms_precond = ms_pc;
   S.ms_matvec = ms_mv;
   S.ms = total.ms();
@@ -734,6 +749,10 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
     delete h;
     return fail(SG_EDEVICE, std::string("upload failed: ") + hipGetErrorString(e));
   }
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+    delete h;
+    return fail(SG_EDEVICE, "event creation failed");
+  }
   *out = h;
   return SG_OK;
 }
@@ -874,7 +893,12 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
   return status;
 }
 
-void sg_destroy(sg_handle h) { delete h; }
+void sg_destroy(sg_handle h) {
+  if (!h) return;
+  (void)hipEventDestroy(h->ev0);
+  (void)hipEventDestroy(h->ev1);
+  delete h;
+}
 
 const char* sg_last_error(void) { return g_last_error.c_str(); }
 

@@ -170,5 +170,9 @@ struct sg_ctx {
   double* red_out;   // reduction results (device)
   std::vector<double> host_out;  // host mirror of red_out
   long inner_it_acc;
+  double inner_ms_acc;
+  double inner_bytes_acc;
+  long inner_launch_acc;
+  hipEvent_t ev0, ev1;
   int inner_it_max[sgk::kMaxLevels];
 };
