@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsgpc.so")
+LIB_PATH = os.environ.get("SGPC_LIBRARY") or os.path.join(_HERE, "libsgpc.so")
 
 SG_OK, SG_EINVAL, SG_EDEVICE, SG_ENOMEM, SG_NOT_CONVERGED, SG_BREAKDOWN = 0, -1, -2, -3, 1, 2
 SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC = 0, 1, 2

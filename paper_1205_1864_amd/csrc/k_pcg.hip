@@ -17,11 +17,7 @@
 // Per-column scalars are reduced from per-tile partials in a fixed order by
 // every block that needs them, so all blocks agree bit for bit. p and r are
 // double-buffered so halo reads never race with neighbouring tiles.
-#include <hip/hip_cooperative_groups.h>
-
 #include "sg_internal.h"
-
-namespace cg = cooperative_groups;
 
 namespace sgk {
 
@@ -49,32 +45,6 @@ __device__ double block_sum(double v, double* sred) {
   }
   return t;
 }
-
-// Block-uniform read of a flag that another block may be writing concurrently.
-__device__ int block_read(const int* p, int* sbi) {
-  __syncthreads();
-  if (threadIdx.x == 0) *sbi = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  return *sbi;
-}
-
-// Column scalar: sum of the per-tile partials of column c, same order in every block.
-__device__ double column_sum(const double* part, int c, int ntiles, double* sbc) {
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    double v = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += 64) v += part[(long)c * ntiles + t];
-    v = wave_sum(v);
-    if (threadIdx.x == 0) *sbc = v;
-  }
-  __syncthreads();
-  return *sbc;
-}
-
-template <typename T, int TS>
-struct Smem {
-  static constexpr int RMAX = TS + 2 * (kMaxCheb - 1);
-};
 
 // Chebyshev preconditioner on one tile. `rreg(lx, ly)` gives r on the region
 // (tile plus halo H = degree - 1; zero outside the domain). Writes z on the
@@ -141,10 +111,43 @@ __device__ double cheb_tile(const PcgArgs<T>& A, int x0, int y0, RF rreg, T* zco
   return rz;
 }
 
+constexpr int kMaxColsPerBlock = 64;
+constexpr long kSpinLimit = 1L << 26;  // bounded waits: a stuck column aborts the launch
+
+// Split-phase barrier of one column: every block that owns tiles of the column
+// adds its tile count to a monotonic arrival counter after finishing its tiles;
+// phase k of the column is complete once the counter reaches k * ntiles.
+__device__ void column_arrive(unsigned* arr, unsigned count) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(arr, count);
+  }
+}
+
+__device__ bool column_wait(const unsigned* arr, unsigned target, int* status, int* sflag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(arr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        ok = 0;
+        atomicExch(status, 1);
+        break;
+      }
+    }
+    __threadfence();
+    *sflag = ok;
+  }
+  __syncthreads();
+  return *sflag != 0;
+}
+
 template <typename T, int TS>
 __global__ void __launch_bounds__(kThreads) pcg_kernel(const PcgArgs<T> A) {
-  constexpr int RMAX = Smem<T, TS>::RMAX;
-  // LDS: two W buffers, S over the largest region; Z and R over the tile.
+  // LDS: two W buffers and S over the grown tile; Z and R over the tile.
   extern __shared__ unsigned char smem_raw[];
   T* sW0 = reinterpret_cast<T*>(smem_raw);
   const int H = A.degree - 1;
@@ -155,180 +158,223 @@ __global__ void __launch_bounds__(kThreads) pcg_kernel(const PcgArgs<T> A) {
   T* sZ = sS + CAP;
   T* sR = sZ + TS * TS;
   __shared__ double sred[kThreads / 64];
-  __shared__ double sbc;
-  __shared__ int sbi;
-  (void)RMAX;
+  __shared__ double s4[4];
+  __shared__ int sdone[kMaxColsPerBlock + 2];  // a run of < kMaxColsPerBlock * ntiles tiles spans at most kMaxColsPerBlock + 1 columns
+  __shared__ int sflag;
 
-  cg::grid_group grid = cg::this_grid();
   const long n = A.n;
   const int ntiles = A.ntiles;
-  const long nwork = (long)A.ncols * ntiles;
+  const int ncols = A.ncols;
+  const long nwork = (long)ncols * ntiles;
   double* part = A.sc.part;
-  auto P = [&](int which) { return part + (long)which * A.ncols * ntiles; };
-
-  // ---- init: z = M b, partials b.b and b.z (stored as the "iteration -1" r.z)
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *A.sc.ndone = 0u;
-    *A.sc.status = 0;
-  }
-  for (long w = blockIdx.x; w < nwork; w += gridDim.x) {
-    const int c = (int)(w / ntiles), t = (int)(w % ntiles);
+  unsigned* arr = A.sc.arrivals;
+  auto P = [&](int which) { return part + (long)which * ncols * ntiles; };
+  // Each block owns a contiguous run of work items (tiles); columns progress
+  // independently, synchronised only among the blocks that share them.
+  const long per_block = (nwork + gridDim.x - 1) / gridDim.x;
+  const long w_begin = (long)blockIdx.x * per_block;
+  const long w_end = w_begin + per_block < nwork ? w_begin + per_block : nwork;
+  if (w_begin >= w_end) return;
+  const int c_first = (int)(w_begin / ntiles), c_last = (int)((w_end - 1) / ntiles);
+  auto tiles_of = [&](int c, int& t0, int& t1) {
+    const long lo = (long)c * ntiles > w_begin ? (long)c * ntiles : w_begin;
+    const long hi = (long)(c + 1) * ntiles < w_end ? (long)(c + 1) * ntiles : w_end;
+    t0 = (int)(lo - (long)c * ntiles);
+    t1 = (int)(hi - (long)c * ntiles);
+  };
+  auto owner = [&](int c) { return (long)c * ntiles >= w_begin; };  // this block holds tile 0 of c
+  // Fixed-order sums of up to four per-tile partial arrays of column c, one wave each.
+  auto col_sums = [&](int c, const double* q0, const double* q1, const double* q2, const double* q3) {
     __syncthreads();
-    const int x0 = (t % A.ntx) * TS, y0 = (t / A.ntx) * TS;
-    const T* bcol = A.B + (long)c * n;
-    auto rreg = [&](int lx, int ly) { return bcol[(long)(y0 - H + ly) * A.nx + (x0 - H + lx)]; };
-    double rz = cheb_tile<T, TS>(A, x0, y0, rreg, A.Z + (long)c * n, sW0, sW1, sS, sZ, sR);
-    double bb = 0.0;
-    for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
-      const int gx = x0 + i % TS, gy = y0 + i / TS;
-      if (gx < A.nx && gy < A.nx) {
-        const double b = (double)sR[i];
-        bb += b * b;
+    const int wv = threadIdx.x >> 6;
+    const double* src = wv == 0 ? q0 : wv == 1 ? q1 : wv == 2 ? q2 : q3;
+    if (wv < 4 && src) {
+      double v = 0.0;
+      for (int t = threadIdx.x & 63; t < ntiles; t += 64) v += src[(long)c * ntiles + t];
+      v = wave_sum(v);
+      if ((threadIdx.x & 63) == 0) s4[wv] = v;
+    }
+    __syncthreads();
+  };
+  for (int c = c_first + (int)threadIdx.x; c <= c_last; c += kThreads) sdone[c - c_first] = 0;
+
+  // ---- start (column phase 1): x = 0, z = M b, partials b.b and b.z
+  for (int c = c_first; c <= c_last; ++c) {
+    int t0, t1;
+    tiles_of(c, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+      __syncthreads();
+      const int x0 = (t % A.ntx) * TS, y0 = (t / A.ntx) * TS;
+      const T* bcol = A.B + (long)c * n;
+      auto rreg = [&](int lx, int ly) { return bcol[(long)(y0 - H + ly) * A.nx + (x0 - H + lx)]; };
+      double rz = cheb_tile<T, TS>(A, x0, y0, rreg, A.Z + (long)c * n, sW0, sW1, sS, sZ, sR);
+      double bb = 0.0;
+      T* xcol = A.X + (long)c * n;
+      for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
+        const int gx = x0 + i % TS, gy = y0 + i / TS;
+        if (gx < A.nx && gy < A.nx) {
+          const double b = (double)sR[i];
+          bb += b * b;
+          xcol[(long)gy * A.nx + gx] = T(0);
+        }
+      }
+      rz = block_sum(rz, sred);
+      bb = block_sum(bb, sred);
+      if (threadIdx.x == 0) {
+        P(PART_RZ1)[(long)c * ntiles + t] = rz;
+        P(PART_BB)[(long)c * ntiles + t] = bb;
       }
     }
-    T* xcol = A.X + (long)c * n;
-    for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
-      const int gx = x0 + i % TS, gy = y0 + i / TS;
-      if (gx < A.nx && gy < A.nx) xcol[(long)gy * A.nx + gx] = T(0);
-    }
-    rz = block_sum(rz, sred);
-    bb = block_sum(bb, sred);
-    if (threadIdx.x == 0) {
-      P(PART_RZ1)[(long)c * ntiles + t] = rz;
-      P(PART_BB)[(long)c * ntiles + t] = bb;
-      if (t == 0) A.sc.done_at[c] = -1;
-    }
+    column_arrive(arr + c, (unsigned)(t1 - t0));
   }
-  grid.sync();
 
-  for (int it = 0; it < A.maxit; ++it) {
+  bool aborted = false;
+  int it = 0;
+  for (; it < A.maxit && !aborted; ++it) {
     const int par = it & 1;
     T* Pnew = par ? A.P1 : A.P0;
     const T* Pold = par ? A.P0 : A.P1;
-    // ---- phase A
-    // Column state done_at[c]: -1 active, >= 0 finished at that iteration,
-    // <= -2 broke down in phase B of iteration -(state + 2) (counted here).
-    for (long w = blockIdx.x; w < nwork; w += gridDim.x) {
-      const int c = (int)(w / ntiles), t = (int)(w % ntiles);
-      const int state = block_read(A.sc.done_at + c, &sbi);
-      if (state >= 0) continue;
-      if (state <= -2) {
-        if (threadIdx.x == 0 && t == 0) {
-          A.sc.done_at[c] = -(state + 2);
-          atomicAdd(A.sc.ndone, 1u);
-        }
-        continue;
+    bool any_active = false;
+    // ---- phase A (column phase 2 + 2 it): p = z + beta p, q = K_0 p, partial p.q
+    for (int c = c_first; c <= c_last && !aborted; ++c) {
+      if (sdone[c - c_first]) continue;
+      if (!column_wait(arr + c, (unsigned)((1 + 2 * it) * ntiles), A.sc.status, &sflag)) {
+        aborted = true;
+        break;
       }
-      const int x0 = (t % A.ntx) * TS, y0 = (t / A.ntx) * TS;
-      const double bb = column_sum(P(PART_BB), c, ntiles, &sbc);
-      const double rr = it == 0 ? bb : column_sum(P(par ? PART_RR0 : PART_RR1), c, ntiles, &sbc);
+      col_sums(c, P(PART_BB), it == 0 ? nullptr : P(par ? PART_RR0 : PART_RR1),
+               it == 0 ? nullptr : P(par ? PART_RZ0 : PART_RZ1), it == 0 ? nullptr : P(par ? PART_RZ1 : PART_RZ0));
+      const double bb = s4[0];
+      const double rr = it == 0 ? s4[0] : s4[1];
       if (sqrt(rr) <= A.rtol * sqrt(bb)) {
-        if (threadIdx.x == 0 && t == 0) {
-          A.sc.done_at[c] = it;
-          atomicAdd(A.sc.ndone, 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          sdone[c - c_first] = 1;
+          if (owner(c)) A.sc.iters[c] = it;
         }
+        __syncthreads();
         continue;
       }
-      T beta = T(0);
-      if (it > 0) {
-        const double gnew = column_sum(P(par ? PART_RZ0 : PART_RZ1), c, ntiles, &sbc);
-        const double gold = column_sum(P(par ? PART_RZ1 : PART_RZ0), c, ntiles, &sbc);
-        beta = (T)(gnew / gold);
-      }
+      const T beta = it == 0 ? T(0) : (T)(s4[2] / s4[3]);
+      any_active = true;
+      int t0, t1;
+      tiles_of(c, t0, t1);
       const T* zc = A.Z + (long)c * n;
       const T* po = Pold + (long)c * n;
       T* pn = Pnew + (long)c * n;
       T* qc = A.Q + (long)c * n;
-      const int RS1 = TS + 2;
-      T* sP = sW0;
-      for (int i = threadIdx.x; i < RS1 * RS1; i += kThreads) {
-        const int gx = x0 - 1 + i % RS1, gy = y0 - 1 + i / RS1;
-        T v = T(0);
-        if (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) {
-          const long g = (long)gy * A.nx + gx;
-          v = it == 0 ? zc[g] : zc[g] + beta * po[g];
+      for (int t = t0; t < t1; ++t) {
+        const int x0 = (t % A.ntx) * TS, y0 = (t / A.ntx) * TS;
+        const int RS1 = TS + 2;
+        T* sP = sW0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < RS1 * RS1; i += kThreads) {
+          const int gx = x0 - 1 + i % RS1, gy = y0 - 1 + i / RS1;
+          T v = T(0);
+          if (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) {
+            const long g = (long)gy * A.nx + gx;
+            v = it == 0 ? zc[g] : zc[g] + beta * po[g];
+          }
+          sP[i] = v;
         }
-        sP[i] = v;
-      }
-      __syncthreads();
-      double pq = 0.0;
-      for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
-        const int lx = i % TS + 1, ly = i / TS + 1;
-        const int gx = x0 + lx - 1, gy = y0 + ly - 1;
-        if (gx < A.nx && gy < A.nx) {
-          const int k = ly * RS1 + lx;
-          const T pc = sP[k];
-          const T s8 = sP[k - RS1 - 1] + sP[k - RS1] + sP[k - RS1 + 1] + sP[k - 1] + sP[k + 1] +
-                       sP[k + RS1 - 1] + sP[k + RS1] + sP[k + RS1 + 1];
-          const T q = A.c0 * pc + A.c1 * s8;
-          const long g = (long)gy * A.nx + gx;
-          pn[g] = pc;
-          qc[g] = q;
-          pq += (double)pc * (double)q;
+        __syncthreads();
+        double pq = 0.0;
+        for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
+          const int lx = i % TS + 1, ly = i / TS + 1;
+          const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+          if (gx < A.nx && gy < A.nx) {
+            const int k = ly * RS1 + lx;
+            const T pc = sP[k];
+            const T s8 = sP[k - RS1 - 1] + sP[k - RS1] + sP[k - RS1 + 1] + sP[k - 1] + sP[k + 1] +
+                         sP[k + RS1 - 1] + sP[k + RS1] + sP[k + RS1 + 1];
+            const T q = A.c0 * pc + A.c1 * s8;
+            const long g = (long)gy * A.nx + gx;
+            pn[g] = pc;
+            qc[g] = q;
+            pq += (double)pc * (double)q;
+          }
         }
+        pq = block_sum(pq, sred);
+        if (threadIdx.x == 0) P(PART_PQ)[(long)c * ntiles + t] = pq;
       }
-      pq = block_sum(pq, sred);
-      if (threadIdx.x == 0) P(PART_PQ)[(long)c * ntiles + t] = pq;
+      column_arrive(arr + c, (unsigned)(t1 - t0));
     }
-    grid.sync();
-    if (__hip_atomic_load(A.sc.ndone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)A.ncols) break;
-    // ---- phase B
+    if (!any_active || aborted) break;
+    // ---- phase B (column phase 3 + 2 it): x += alpha p, r -= alpha q, z = M r, partials r.r, r.z
     T* Rnew = par ? A.R0 : A.R1;
     const T* Rold = it == 0 ? A.B : (par ? A.R1 : A.R0);
-    for (long w = blockIdx.x; w < nwork; w += gridDim.x) {
-      const int c = (int)(w / ntiles), t = (int)(w % ntiles);
-      if (block_read(A.sc.done_at + c, &sbi) != -1) continue;
-      const int x0 = (t % A.ntx) * TS, y0 = (t / A.ntx) * TS;
-      const double pq = column_sum(P(PART_PQ), c, ntiles, &sbc);
+    for (int c = c_first; c <= c_last && !aborted; ++c) {
+      if (sdone[c - c_first]) continue;
+      if (!column_wait(arr + c, (unsigned)((2 + 2 * it) * ntiles), A.sc.status, &sflag)) {
+        aborted = true;
+        break;
+      }
+      col_sums(c, P(PART_PQ), P(par ? PART_RZ0 : PART_RZ1), nullptr, nullptr);
+      const double pq = s4[0], gam = s4[1];
       if (!(pq > 0.0) || !isfinite(pq)) {
-        // breakdown of this column: keep its current iterate; counted in the next phase A
-        if (threadIdx.x == 0 && t == 0) A.sc.done_at[c] = -2 - it;
+        // breakdown: keep the current iterate
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          sdone[c - c_first] = 1;
+          if (owner(c)) A.sc.iters[c] = it;
+        }
+        __syncthreads();
         continue;
       }
-      const double gam = column_sum(P(par ? PART_RZ0 : PART_RZ1), c, ntiles, &sbc);
       const T alpha = (T)(gam / pq);
+      int t0, t1;
+      tiles_of(c, t0, t1);
       const T* pc = Pnew + (long)c * n;
       const T* qc = A.Q + (long)c * n;
       const T* ro = Rold + (long)c * n;
       T* rn = Rnew + (long)c * n;
       T* xc = A.X + (long)c * n;
-      for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
-        const int gx = x0 + i % TS, gy = y0 + i / TS;
-        if (gx < A.nx && gy < A.nx) {
-          const long g = (long)gy * A.nx + gx;
-          xc[g] = it == 0 ? alpha * pc[g] : xc[g] + alpha * pc[g];
+      for (int t = t0; t < t1; ++t) {
+        const int x0 = (t % A.ntx) * TS, y0 = (t / A.ntx) * TS;
+        __syncthreads();
+        for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
+          const int gx = x0 + i % TS, gy = y0 + i / TS;
+          if (gx < A.nx && gy < A.nx) {
+            const long g = (long)gy * A.nx + gx;
+            xc[g] = it == 0 ? alpha * pc[g] : xc[g] + alpha * pc[g];
+          }
+        }
+        auto rreg = [&](int lx, int ly) {
+          const long g = (long)(y0 - H + ly) * A.nx + (x0 - H + lx);
+          return ro[g] - alpha * qc[g];
+        };
+        double rz = cheb_tile<T, TS>(A, x0, y0, rreg, A.Z + (long)c * n, sW0, sW1, sS, sZ, sR);
+        double rr = 0.0;
+        for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
+          const int gx = x0 + i % TS, gy = y0 + i / TS;
+          if (gx < A.nx && gy < A.nx) {
+            const T r = sR[i];
+            rn[(long)gy * A.nx + gx] = r;
+            rr += (double)r * (double)r;
+          }
+        }
+        rz = block_sum(rz, sred);
+        rr = block_sum(rr, sred);
+        if (threadIdx.x == 0) {
+          P(par ? PART_RZ1 : PART_RZ0)[(long)c * ntiles + t] = rz;
+          P(par ? PART_RR1 : PART_RR0)[(long)c * ntiles + t] = rr;
         }
       }
-      auto rreg = [&](int lx, int ly) {
-        const long g = (long)(y0 - H + ly) * A.nx + (x0 - H + lx);
-        return ro[g] - alpha * qc[g];
-      };
-      double rz = cheb_tile<T, TS>(A, x0, y0, rreg, A.Z + (long)c * n, sW0, sW1, sS, sZ, sR);
-      double rr = 0.0;
-      for (int i = threadIdx.x; i < TS * TS; i += kThreads) {
-        const int gx = x0 + i % TS, gy = y0 + i / TS;
-        if (gx < A.nx && gy < A.nx) {
-          const T r = sR[i];
-          rn[(long)gy * A.nx + gx] = r;
-          rr += (double)r * (double)r;
-        }
-      }
-      rz = block_sum(rz, sred);
-      rr = block_sum(rr, sred);
-      if (threadIdx.x == 0) {
-        P(par ? PART_RZ1 : PART_RZ0)[(long)c * ntiles + t] = rz;
-        P(par ? PART_RR1 : PART_RR0)[(long)c * ntiles + t] = rr;
-      }
-    }
-    grid.sync();
-  }
-  // ---- finalize iteration counts
-  if (blockIdx.x == 0) {
-    for (int c = threadIdx.x; c < A.ncols; c += kThreads) {
-      const int d = A.sc.done_at[c];
-      A.sc.iters[c] = d >= 0 ? d : (d <= -2 ? -(d + 2) : A.maxit);
+      column_arrive(arr + c, (unsigned)(t1 - t0));
     }
   }
+  // ---- iteration counts of columns that ran out of iterations
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = c_first; c <= c_last; ++c)
+      if (!sdone[c - c_first] && owner(c)) A.sc.iters[c] = A.maxit;
+  }
+}
+
+// Zero the per-column arrival counters before a launch.
+__global__ void pcg_reset_kernel(unsigned* arr, int ncols, int* status) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncols; c += gridDim.x * blockDim.x) arr[c] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
 }
 
 template <typename T, int TS>
@@ -356,7 +402,10 @@ hipError_t launch_tile(const PcgArgs<T>& args, int max_blocks, hipStream_t s) {
   if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid > nwork) grid = nwork;
   if (grid < 1) grid = 1;
+  // every block must own at most kMaxColsPerBlock columns
+  if ((nwork + grid - 1) / grid > (long)kMaxColsPerBlock * args.ntiles) return hipErrorInvalidValue;
   PcgArgs<T> a = args;
+  hipLaunchKernelGGL(pcg_reset_kernel, dim3(1), dim3(256), 0, s, a.sc.arrivals, a.ncols, a.sc.status);
   void* kargs[] = {&a};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3((unsigned)grid), dim3(kThreads),
                                     kargs, (unsigned)sm, s);

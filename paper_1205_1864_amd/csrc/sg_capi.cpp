@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -86,11 +87,12 @@ struct Plan {
   int maxcols, ntiles_max;
   size_t o_a64, o_a32, o_c64;
   size_t o_lo_ptr, o_lo_ent, o_lo_g64, o_lo_g32, o_up_ptr, o_up_ent, o_up_g64, o_up_g32;
+  size_t o_st_lo, o_st_up, o_st_glo64, o_st_gup64, o_st_glo32, o_st_gup32;
   size_t o_pair_ptr, o_pair_a, o_pair_b, o_pair_g;
   size_t o_vec[7];
   size_t o_rw, o_zw;
   size_t o_pcg[6];
-  size_t o_part, o_done, o_iters, o_ndone, o_status;
+  size_t o_part, o_arr, o_iters, o_status;
   size_t o_red_part, o_red_out;
   size_t total;
 };
@@ -148,6 +150,13 @@ void make_plan(const sg_problem* pr, const sg_opts* op, Plan& pl) {
   pl.o_up_ent = L.take(sizeof(int) * std::max(1, pl.nup));
   pl.o_up_g64 = L.take(sizeof(double) * std::max(1, pl.nup));
   pl.o_up_g32 = L.take(sizeof(float) * std::max(1, pl.nup));
+  const long PM = std::max<long>(1, (long)pl.P * M);
+  pl.o_st_lo = L.take(sizeof(int) * PM);
+  pl.o_st_up = L.take(sizeof(int) * PM);
+  pl.o_st_glo64 = L.take(sizeof(double) * PM);
+  pl.o_st_gup64 = L.take(sizeof(double) * PM);
+  pl.o_st_glo32 = L.take(sizeof(float) * PM);
+  pl.o_st_gup32 = L.take(sizeof(float) * PM);
   pl.o_pair_ptr = L.take(sizeof(int) * (M + 1));
   pl.o_pair_a = L.take(sizeof(int) * std::max(1, pl.npairs));
   pl.o_pair_b = L.take(sizeof(int) * std::max(1, pl.npairs));
@@ -157,9 +166,8 @@ void make_plan(const sg_problem* pr, const sg_opts* op, Plan& pl) {
   pl.o_zw = L.take(op->inner_precision == 32 ? isz * nP : 0);
   for (int i = 0; i < 6; ++i) pl.o_pcg[i] = L.take(isz * pl.n * (long)pl.maxcols);
   pl.o_part = L.take(sizeof(double) * 6 * (long)pl.maxcols * pl.ntiles_max);
-  pl.o_done = L.take(sizeof(int) * pl.maxcols);
+  pl.o_arr = L.take(sizeof(unsigned) * pl.maxcols);
   pl.o_iters = L.take(sizeof(int) * pl.maxcols);
-  pl.o_ndone = L.take(sizeof(unsigned));
   pl.o_status = L.take(sizeof(int));
   const long nb_contract = (ne2 + 255) / 256;
   pl.o_red_part = L.take(sizeof(double) * std::max<long>(4L * sgk::kRedBlocks, nb_contract * (M + 1)));
@@ -219,10 +227,9 @@ int choose_tile(const sg_ctx* h, int ncols, size_t tsz, int degree) {
     if (h->opts.tile == 32 && pcg_lds_bytes(32, degree, tsz) > 64 * 1024) return 16;
     return h->opts.tile;
   }
+  (void)ncols;
   if (pcg_lds_bytes(32, degree, tsz) > 64 * 1024) return 16;
-  const long t32 = (long)((h->nx + 31) / 32) * ((h->nx + 31) / 32);
-  if ((long)ncols * t32 >= 2L * h->num_cu) return 32;
-  return 16;
+  return 32;
 }
 
 // Batched inner PCG on `ncols` contiguous columns (inner precision T).
@@ -256,8 +263,11 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   SG_HIP(sgk::launch_pcg<T>(a, tile, 0, h->stream));
   SG_HIP(hipEventRecord(h->ev1, h->stream));
   std::vector<int> it(ncols);
+  int wait_status = 0;
   SG_HIP(hipMemcpyAsync(it.data(), h->pcgsc.iters, sizeof(int) * ncols, hipMemcpyDeviceToHost, h->stream));
+  SG_HIP(hipMemcpyAsync(&wait_status, h->pcgsc.status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   SG_HIP(hipStreamSynchronize(h->stream));
+  if (wait_status != 0) return fail(SG_EDEVICE, "inner solver: a bounded column wait expired");
   float ms = 0.f;
   SG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   h->inner_ms_acc += ms;
@@ -287,6 +297,17 @@ sgk::ChaosLists<float> lists<float>(const sg_ctx* h) {
   return {h->lo_ptr_d, h->lo_ent_d, h->lo_g32, h->up_ptr_d, h->up_ent_d, h->up_g32};
 }
 template <typename T>
+sgk::StripTables<T> strip_tables(const sg_ctx* h);
+template <>
+sgk::StripTables<double> strip_tables<double>(const sg_ctx* h) {
+  return {h->st_lo_d, h->st_up_d, h->st_glo64, h->st_gup64, h->M, h->mv_blocks_per_band};
+}
+template <>
+sgk::StripTables<float> strip_tables<float>(const sg_ctx* h) {
+  return {h->st_lo_d, h->st_up_d, h->st_glo32, h->st_gup32, h->M, h->mv_blocks_per_band};
+}
+
+template <typename T>
 const T* coefs(const sg_ctx* h);
 template <>
 const double* coefs<double>(const sg_ctx* h) { return h->a64; }
@@ -313,7 +334,7 @@ void coupling(sg_ctx* h, int l, int dir, T* R, const T* V) {
   a.out = R;
   a.a = coefs<T>(h);
   a.lists = lists<T>(h);
-  sgk::launch_sgop<T>(a, h->stream);
+  sgk::launch_sgop<T>(a, strip_tables<T>(h), h->stream);
 }
 
 long coupling_blocks(const sg_ctx* h, int l, int dir) {
@@ -394,7 +415,7 @@ void matvec(sg_ctx* h, const double* U, double* Y) {
   a.out = Y;
   a.a = h->a64;
   a.lists = lists<double>(h);
-  sgk::launch_sgop<double>(a, h->stream);
+  sgk::launch_sgop<double>(a, strip_tables<double>(h), h->stream);
 }
 
 int read_out(sg_ctx* h, int count) {
@@ -619,6 +640,8 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   h->ws_bytes = workspace_bytes;
   multi_indices(h->M, h->p, h->alpha, h->off);
   cheb_interval(h->n_e, h->lmin, h->lmax);
+  h->mv_blocks_per_band = 0;
+  if (const char* env = std::getenv("SGPC_MV_BLOCKS_PER_BAND")) h->mv_blocks_per_band = std::atoi(env);
   int dev = 0;
   h->num_cu = 1;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -680,6 +703,23 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
     up_ptr[a + 1] = (int)up_ent.size();
   }
   std::vector<float> lo_g32(lo_g.begin(), lo_g.end()), up_g32(up_g.begin(), up_g.end());
+  // dense [P][M] neighbour tables for the strip kernel
+  const size_t PMd = std::max<size_t>(1, (size_t)P * M);
+  std::vector<int> st_lo(PMd, -1), st_up(PMd, -1);
+  std::vector<double> st_glo(PMd, 0.0), st_gup(PMd, 0.0);
+  for (int a = 0; a < P; ++a) {
+    for (int e = lo_ptr[a]; e < lo_ptr[a + 1]; ++e) {
+      const int k = (lo_ent[e] >> 20) - 1;
+      st_lo[(size_t)a * M + k] = lo_ent[e] & 0xFFFFF;
+      st_glo[(size_t)a * M + k] = lo_g[e];
+    }
+    for (int e = up_ptr[a]; e < up_ptr[a + 1]; ++e) {
+      const int k = (up_ent[e] >> 20) - 1;
+      st_up[(size_t)a * M + k] = up_ent[e] & 0xFFFFF;
+      st_gup[(size_t)a * M + k] = up_g[e];
+    }
+  }
+  std::vector<float> st_glo32(st_glo.begin(), st_glo.end()), st_gup32(st_gup.begin(), st_gup.end());
   std::vector<int> pair_ptr(M + 1, 0), pair_a, pair_b;
   std::vector<double> pair_g;
   for (int k = 0; k < M; ++k) {
@@ -704,6 +744,12 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   h->up_ent_d = (int*)(w + pl.o_up_ent);
   h->up_g64 = (double*)(w + pl.o_up_g64);
   h->up_g32 = (float*)(w + pl.o_up_g32);
+  h->st_lo_d = (int*)(w + pl.o_st_lo);
+  h->st_up_d = (int*)(w + pl.o_st_up);
+  h->st_glo64 = (double*)(w + pl.o_st_glo64);
+  h->st_gup64 = (double*)(w + pl.o_st_gup64);
+  h->st_glo32 = (float*)(w + pl.o_st_glo32);
+  h->st_gup32 = (float*)(w + pl.o_st_gup32);
   h->pair_ptr_d = (int*)(w + pl.o_pair_ptr);
   h->pair_a_d = (int*)(w + pl.o_pair_a);
   h->pair_b_d = (int*)(w + pl.o_pair_b);
@@ -716,9 +762,8 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   for (int i = 0; i < 6; ++i) *pcgv[i] = w + pl.o_pcg[i];
   h->pcg_maxcols = pl.maxcols;
   h->pcgsc.part = (double*)(w + pl.o_part);
-  h->pcgsc.done_at = (int*)(w + pl.o_done);
+  h->pcgsc.arrivals = (unsigned*)(w + pl.o_arr);
   h->pcgsc.iters = (int*)(w + pl.o_iters);
-  h->pcgsc.ndone = (unsigned*)(w + pl.o_ndone);
   h->pcgsc.status = (int*)(w + pl.o_status);
   h->red_part = (double*)(w + pl.o_red_part);
   h->red_out = (double*)(w + pl.o_red_out);
@@ -740,6 +785,12 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   if (e == hipSuccess) e = up(h->up_ent_d, up_ent.data(), sizeof(int) * up_ent.size());
   if (e == hipSuccess) e = up(h->up_g64, up_g.data(), sizeof(double) * up_g.size());
   if (e == hipSuccess) e = up(h->up_g32, up_g32.data(), sizeof(float) * up_g32.size());
+  if (e == hipSuccess) e = up(h->st_lo_d, st_lo.data(), sizeof(int) * st_lo.size());
+  if (e == hipSuccess) e = up(h->st_up_d, st_up.data(), sizeof(int) * st_up.size());
+  if (e == hipSuccess) e = up(h->st_glo64, st_glo.data(), sizeof(double) * st_glo.size());
+  if (e == hipSuccess) e = up(h->st_gup64, st_gup.data(), sizeof(double) * st_gup.size());
+  if (e == hipSuccess) e = up(h->st_glo32, st_glo32.data(), sizeof(float) * st_glo32.size());
+  if (e == hipSuccess) e = up(h->st_gup32, st_gup32.data(), sizeof(float) * st_gup32.size());
   if (e == hipSuccess) e = up(h->pair_ptr_d, pair_ptr.data(), sizeof(int) * pair_ptr.size());
   if (e == hipSuccess) e = up(h->pair_a_d, pair_a.data(), sizeof(int) * pair_a.size());
   if (e == hipSuccess) e = up(h->pair_b_d, pair_b.data(), sizeof(int) * pair_b.size());

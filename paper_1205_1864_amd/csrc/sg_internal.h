@@ -51,16 +51,28 @@ struct SgOpArgs {
   ChaosLists<T> lists;
 };
 
+// Dense per-row neighbour tables [P][M] for the strip kernel: lo[a*M + k] is the
+// row index of a - e_{k+1} (or -1) with coefficient glo = sqrt(a_{k+1}); up the same
+// for a + e_{k+1} with gup = sqrt(a_{k+1} + 1).
 template <typename T>
-void launch_sgop(const SgOpArgs<T>& args, hipStream_t s);
+struct StripTables {
+  const int* lo;
+  const int* up;
+  const T* glo;
+  const T* gup;
+  int M;
+  int blocks_per_band;  // row chunks per grid band (0 = default)
+};
+
+template <typename T>
+void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, hipStream_t s);
 
 // Persistent batched PCG on K_0 = theta0 * K_Lap (one independent solve per column).
 struct PcgScratch {
-  double* part;     // [6][ncols][ntiles] partial sums
-  int* done_at;     // [ncols]
-  int* iters;       // [ncols]
-  unsigned* ndone;  // [1]
-  int* status;      // [1]
+  double* part;        // [6][ncols][ntiles] per-tile partial sums
+  unsigned* arrivals;  // [ncols] monotonic per-column arrival counters
+  int* iters;          // [ncols]
+  int* status;         // [1] nonzero if a bounded wait expired
 };
 
 template <typename T>
@@ -147,6 +159,7 @@ struct sg_ctx {
   hipStream_t stream;
   int num_cu;
   int tile;
+  int mv_blocks_per_band;
   // host copies of the chaos lists (for counters)
   std::vector<int> lo_ptr, up_ptr;
   // device arrays inside the workspace
@@ -158,6 +171,9 @@ struct sg_ctx {
   int *lo_ptr_d, *lo_ent_d, *up_ptr_d, *up_ent_d;
   double *lo_g64, *up_g64;
   float *lo_g32, *up_g32;
+  int *st_lo_d, *st_up_d;
+  double *st_glo64, *st_gup64;
+  float *st_glo32, *st_gup32;
   int *pair_ptr_d, *pair_a_d, *pair_b_d;
   double* pair_g_d;
   double *r, *z, *pv, *q, *lam, *tmp, *rhs;  // FP64 n x P blocks

@@ -26,7 +26,11 @@ def _dev(A):
 
 
 SHAPES = [dict(), dict(n_e=7, M=3, p=3), dict(n_e=33, M=5, p=2), dict(n_e=19, M=2, p=4),
-          dict(n_e=10, M=3, p=0), dict(n_e=9, M=0, p=2), dict(n_e=40, M=6, p=3, sigma=0.15)]
+          dict(n_e=10, M=3, p=0), dict(n_e=9, M=0, p=2), dict(n_e=40, M=6, p=3, sigma=0.15),
+          # grid widths that take the register-strip kernel (multiples of 64, up to 512)
+          dict(n_e=64, M=4, p=2), dict(n_e=64, M=12, p=2, sigma=0.1), dict(n_e=128, M=3, p=4),
+          dict(n_e=64, M=0, p=3), dict(n_e=64, M=1, p=5), dict(n_e=192, M=7, p=2),
+          dict(n_e=512, M=2, p=2), dict(n_e=64, M=13, p=2, sigma=0.1)]
 
 
 @pytest.mark.parametrize("kw", SHAPES)
@@ -92,10 +96,12 @@ def test_inner_solve_to_tolerance(prec):
         assert abs(int(its[c]) - int(st.iterations[c])) <= 1
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(n_e=21, M=3, p=3), dict(n_e=12, M=5, p=2)])
+@pytest.mark.parametrize("kw", [dict(), dict(n_e=21, M=3, p=3), dict(n_e=12, M=5, p=2),
+                                dict(n_e=64, M=5, p=3), dict(n_e=128, M=10, p=2)])
 def test_coupling_parity(kw):
     b = _b()
     prob, s = _sys(**kw)
+    print(f"coupling parity n_e={prob.n_e} M={prob.M} p={prob.p}", flush=True)
     solver = b.SGSolver(prob)
     rng = np.random.default_rng(7)
     for l in range(1, prob.p + 1):
