@@ -29,6 +29,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "SG solve s to relres 1e-8 + matvec HBM GB/s (256², M=10, p=3); adjoint grad s"
 HBM_PEAK_GBS = 8000.0
+CHEB_DEGREE = 8  # updates of the Chebyshev preconditioner of the inner PCG
 
 
 def log(msg):
@@ -110,7 +111,7 @@ def main():
     torch.cuda.set_device(0)
     prob = named_problem("scale")
     F = to_device_block(prob.load_block())
-    opts64 = Options(inner_precision=64, cheb_degree=4, inner_maxit=2000, precond="hsc", inner_rtol=1e-4)
+    opts64 = Options(inner_precision=64, cheb_degree=CHEB_DEGREE, inner_maxit=2000, precond="hsc", inner_rtol=1e-4)
     solver = SGSolver(prob, opts64)
     U = solver.empty()
 
@@ -158,9 +159,9 @@ def main():
 
     if not args.no_extra:
         # FP32 inner (precision variant) and mean-based comparators
-        for label, o in [("hsc_fp32", Options(inner_precision=32, precond="hsc", inner_maxit=2000)),
-                         ("mean_fp64", Options(inner_precision=64, precond="mean", inner_maxit=2000)),
-                         ("mean_fp32", Options(inner_precision=32, precond="mean", inner_maxit=2000))]:
+        for label, o in [("hsc_fp32", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="hsc", inner_maxit=2000)),
+                         ("mean_fp64", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000)),
+                         ("mean_fp32", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000))]:
             sv = SGSolver(prob, o)
             Uv = sv.empty()
             sv.sg_solve(F, Uv, rtol=1e-8, maxit=200)
@@ -185,7 +186,7 @@ def main():
 
         # adjoint gradient, 512^2, M = 8, p = 3
         pg = named_problem("grad")
-        sg_ = SGSolver(pg, Options(inner_precision=64, precond="hsc", inner_maxit=2000))
+        sg_ = SGSolver(pg, Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="hsc", inner_maxit=2000))
         Fg = to_device_block(pg.load_block())
         wm, wv = qoi_weights(pg.n_e)
         wm_d, wv_d = to_device_vec(wm), to_device_vec(wv)
@@ -222,8 +223,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": solve_s * 1e3, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "HSC-FCG solve, 256^2 Q1, M=10, p=3 (P=286, 18.6M unknowns), "
-                               "FP64 inner PCG Jacobi-Chebyshev d=4 to 1e-4, outer to 1e-8",
-                   "n_e": prob.n_e, "M": prob.M, "p": prob.p, "P": prob.P, "sigma": prob.sigma, "L": prob.L},
+                               f"FP64 inner PCG Jacobi-Chebyshev d={CHEB_DEGREE} to 1e-4, outer to 1e-8",
+                   "cheb_degree": CHEB_DEGREE, "n_e": prob.n_e, "M": prob.M, "p": prob.p, "P": prob.P, "sigma": prob.sigma, "L": prob.L},
         "roofline": roofline, "roofline_matvec": roofline_mv, "extra": extra,
     }
     if not args.no_cpu:

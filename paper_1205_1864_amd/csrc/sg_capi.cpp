@@ -216,20 +216,11 @@ void fill_pcg_consts(const sg_ctx* h, sgk::PcgArgs<T>& a) {
 
 int effective_degree(const sg_ctx* h) { return h->lmax - h->lmin > 0.0 ? h->opts.cheb_degree : 1; }
 
-size_t pcg_lds_bytes(int tile, int degree, size_t tsz) {
-  const int H = degree - 1;
-  const int RS = tile + 2 * (H > 1 ? H : 1);
-  return tsz * (3 * RS * RS + 2 * tile * tile);
-}
-
-int choose_tile(const sg_ctx* h, int ncols, size_t tsz, int degree) {
-  if (h->opts.tile == 16 || h->opts.tile == 32) {
-    if (h->opts.tile == 32 && pcg_lds_bytes(32, degree, tsz) > 64 * 1024) return 16;
-    return h->opts.tile;
-  }
-  (void)ncols;
-  if (pcg_lds_bytes(32, degree, tsz) > 64 * 1024) return 16;
-  return 32;
+int choose_tile(const sg_ctx* h, int degree) {
+  // 32 x 32 tiles (four per block up to degree 4, two up to degree 8); the
+  // halo of larger degrees makes 16 x 16 tiles the better choice.
+  if (h->opts.tile == 16) return 16;
+  return degree <= 8 ? 32 : 16;
 }
 
 // Batched inner PCG on `ncols` contiguous columns (inner precision T).
@@ -239,7 +230,7 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   if (ncols > h->pcg_maxcols) return fail(SG_EINVAL, "too many columns for the inner solver");
   sgk::PcgArgs<T> a{};
   const int degree = effective_degree(h);
-  const int tile = choose_tile(h, ncols, sizeof(T), degree);
+  const int tile = choose_tile(h, degree);
   a.nx = h->nx;
   a.n = h->n;
   a.ncols = ncols;
@@ -260,7 +251,7 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   fill_pcg_consts<T>(h, a);
   a.degree = degree;
   SG_HIP(hipEventRecord(h->ev0, h->stream));
-  SG_HIP(sgk::launch_pcg<T>(a, tile, 0, h->stream));
+  SG_HIP(sgk::launch_pcg<T>(a, tile, h->pcg_max_blocks, h->stream));
   SG_HIP(hipEventRecord(h->ev1, h->stream));
   std::vector<int> it(ncols);
   int wait_status = 0;
@@ -642,6 +633,8 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   cheb_interval(h->n_e, h->lmin, h->lmax);
   h->mv_blocks_per_band = 0;
   if (const char* env = std::getenv("SGPC_MV_BLOCKS_PER_BAND")) h->mv_blocks_per_band = std::atoi(env);
+  h->pcg_max_blocks = 0;
+  if (const char* env = std::getenv("SGPC_PCG_MAX_BLOCKS")) h->pcg_max_blocks = std::atoi(env);
   int dev = 0;
   h->num_cu = 1;
   if (hipGetDevice(&dev) != hipSuccess ||

@@ -160,6 +160,7 @@ struct sg_ctx {
   int num_cu;
   int tile;
   int mv_blocks_per_band;
+  int pcg_max_blocks;
   // host copies of the chaos lists (for counters)
   std::vector<int> lo_ptr, up_ptr;
   // device arrays inside the workspace
