@@ -268,6 +268,144 @@ __global__ void __launch_bounds__(512) sgop_strip_kernel(const SgOpArgs<T> A, co
   }
 }
 
+// Occupancy variant of the strip kernel: the KL coefficients are read per
+// entry (they stay in L1/L2, shared by every row of the band) instead of being
+// held in registers, and each row walks a compact list of its active KL terms
+// without branches, so more waves hide the load latency.
+template <typename T, int R>
+__global__ void __launch_bounds__(512) sgop_strip_dyn_kernel(const SgOpArgs<T> A, const StripTables<T> tab,
+                                                              int nbands, int nchunks, int chunk_rows) {
+  __shared__ T xch[2][8][R];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ex = threadIdx.x;
+  const int ne = A.n_e, nx = A.nx;
+  const int nblocks = nbands * nchunks;
+  const int per_xcd = (nblocks + 7) / 8;
+  const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (logical >= nblocks) return;
+  const int band = logical / nchunks, chunk = logical % nchunks;
+  const int ey0 = band * R;
+  const int r0 = A.row0 + chunk * chunk_rows;
+  const int r1 = min(A.row0 + A.nrows, r0 + chunk_rows);
+  if (r0 >= r1) return;
+  const long n = A.n;
+  const long ne2 = (long)ne * ne;
+  const bool has_right = ex + 1 <= nx;
+
+  for (int row = r0; row < r1; ++row) {
+    T V[R + 1][4];
+#pragma unroll
+    for (int j = 0; j < R + 1; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) V[j][c] = T(0);
+    if (A.diag != T(0)) {
+      T w[R + 2];
+      load_strip<T, R>(A.in + (long)row * n, ex, ey0, nx, w);
+      T wr[R + 2];
+#pragma unroll
+      for (int i = 0; i < R + 2; ++i) wr[i] = from_next(w[i]);
+      if (lane == 63 && has_right) load_strip<T, R>(A.in + (long)row * n, ex + 1, ey0, nx, wr);
+#pragma unroll
+      for (int j = 0; j < R + 1; ++j) {
+        V[j][0] += A.diag * w[j];
+        V[j][1] += A.diag * wr[j];
+        V[j][2] += A.diag * wr[j + 1];
+        V[j][3] += A.diag * w[j + 1];
+      }
+    }
+    const int e0 = tab.ent_ptr[row], e1 = tab.ent_ptr[row + 1];
+#pragma unroll 2
+    for (int e = e0; e < e1; ++e) {
+      const int k = tab.ent_k[e];
+      const int blo = tab.ent_lo[e], bup = tab.ent_up[e];
+      const T glo = A.use_lower ? tab.ent_glo[e] : T(0);
+      const T gup = A.use_upper ? tab.ent_gup[e] : T(0);
+      if (glo == T(0) && gup == T(0)) continue;
+      T a[R + 1];
+#pragma unroll
+      for (int j = 0; j < R + 1; ++j) {
+        const int ey = ey0 + j;
+        a[j] = ey < ne ? A.a[(long)k * ne2 + (long)ey * ne + ex] : T(0);
+      }
+      T ul[R + 2], uu[R + 2], w[R + 2];
+      load_strip<T, R>(A.in + (long)blo * n, ex, ey0, nx, ul);
+      load_strip<T, R>(A.in + (long)bup * n, ex, ey0, nx, uu);
+#pragma unroll
+      for (int i = 0; i < R + 2; ++i) w[i] = glo * ul[i] + gup * uu[i];
+      T wr[R + 2];
+#pragma unroll
+      for (int i = 0; i < R + 2; ++i) wr[i] = from_next(w[i]);
+      if (lane == 63 && has_right) {
+        load_strip<T, R>(A.in + (long)blo * n, ex + 1, ey0, nx, ul);
+        load_strip<T, R>(A.in + (long)bup * n, ex + 1, ey0, nx, uu);
+#pragma unroll
+        for (int i = 0; i < R + 2; ++i) wr[i] = glo * ul[i] + gup * uu[i];
+      }
+#pragma unroll
+      for (int j = 0; j < R + 1; ++j) {
+        V[j][0] += a[j] * w[j];
+        V[j][1] += a[j] * wr[j];
+        V[j][2] += a[j] * wr[j + 1];
+        V[j][3] += a[j] * w[j + 1];
+      }
+    }
+    T own[R], right[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const T S0 = V[i][0] + V[i][1] + V[i][2] + V[i][3];
+      const T S1 = V[i + 1][0] + V[i + 1][1] + V[i + 1][2] + V[i + 1][3];
+      const T oTL = T(5) * V[i][3] - S0 - V[i][1];
+      const T oTR = T(5) * V[i][2] - S0 - V[i][0];
+      const T oBL = T(5) * V[i + 1][0] - S1 - V[i + 1][2];
+      const T oBR = T(5) * V[i + 1][1] - S1 - V[i + 1][3];
+      own[i] = oTL + oBL;
+      right[i] = oTR + oBR;
+    }
+    const int par = row & 1;
+    if (lane == 63) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) xch[par][wave][i] = right[i];
+    }
+    __syncthreads();
+    T left[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) left[i] = from_prev(right[i]);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) left[i] = wave > 0 ? xch[par][wave - 1][i] : T(0);
+    }
+    if (ex >= 1 && ex <= nx) {
+      T* o = A.out + (long)row * n;
+      const T* rs = A.rsrc ? A.rsrc + (long)row * n : nullptr;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int gy = ey0 + 1 + i;
+        if (gy <= nx) {
+          const long idx = (long)(gy - 1) * nx + (ex - 1);
+          T v = A.sgn * ((own[i] + left[i]) * T(1.0 / 6.0));
+          if (rs) v += A.rcoef * rs[idx];
+          o[idx] = v;
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+void launch_strip_dyn(const SgOpArgs<T>& A, const StripTables<T>& tab, hipStream_t s) {
+  constexpr int R = kStripR;
+  const int nbands = (A.n_e + R - 1) / R;
+  int nchunks = tab.blocks_per_band > 0 ? tab.blocks_per_band : 64;
+  if (nchunks > A.nrows) nchunks = A.nrows;
+  if (nchunks < 1) nchunks = 1;
+  const int chunk_rows = (A.nrows + nchunks - 1) / nchunks;
+  nchunks = (A.nrows + chunk_rows - 1) / chunk_rows;
+  const int nblocks = nbands * nchunks;
+  const int grid = (nblocks + 7) / 8 * 8;
+  hipLaunchKernelGGL((sgop_strip_dyn_kernel<T, R>), dim3(grid), dim3(A.n_e), 0, s, A, tab, nbands, nchunks,
+                     chunk_rows);
+}
+
 template <typename T, int MT>
 void launch_strip(const SgOpArgs<T>& A, const StripTables<T>& tab, hipStream_t s) {
   constexpr int R = kStripR;
@@ -303,8 +441,12 @@ constexpr int kStripMaxM = 12;
 template <typename T>
 void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, hipStream_t s) {
   if (args.nrows <= 0) return;
-  const bool strip_ok = args.n_e % 64 == 0 && args.n_e >= 64 && args.n_e <= 512 && tab.M <= kStripMaxM &&
-                        tab.lo != nullptr;
+  const bool shape_ok = args.n_e % 64 == 0 && args.n_e >= 64 && args.n_e <= 512;
+  if (shape_ok && tab.variant == 1 && tab.ent_ptr != nullptr) {
+    launch_strip_dyn<T>(args, tab, s);
+    return;
+  }
+  const bool strip_ok = shape_ok && tab.M <= kStripMaxM && tab.lo != nullptr;
   if (strip_ok && dispatch_strip<T, kStripMaxM>(args, tab, s)) return;
   const int tiles = (args.nx + kTile - 1) / kTile;
   dim3 grid(tiles * tiles, args.nrows);

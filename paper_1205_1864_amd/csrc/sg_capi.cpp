@@ -88,6 +88,7 @@ struct Plan {
   size_t o_a64, o_a32, o_c64;
   size_t o_lo_ptr, o_lo_ent, o_lo_g64, o_lo_g32, o_up_ptr, o_up_ent, o_up_g64, o_up_g32;
   size_t o_st_lo, o_st_up, o_st_glo64, o_st_gup64, o_st_glo32, o_st_gup32;
+  size_t o_en_ptr, o_en_k, o_en_lo, o_en_up, o_en_glo64, o_en_gup64, o_en_glo32, o_en_gup32;
   size_t o_pair_ptr, o_pair_a, o_pair_b, o_pair_g;
   size_t o_vec[7];
   size_t o_rw, o_zw;
@@ -157,6 +158,14 @@ void make_plan(const sg_problem* pr, const sg_opts* op, Plan& pl) {
   pl.o_st_gup64 = L.take(sizeof(double) * PM);
   pl.o_st_glo32 = L.take(sizeof(float) * PM);
   pl.o_st_gup32 = L.take(sizeof(float) * PM);
+  pl.o_en_ptr = L.take(sizeof(int) * (pl.P + 1));
+  pl.o_en_k = L.take(sizeof(int) * PM);
+  pl.o_en_lo = L.take(sizeof(int) * PM);
+  pl.o_en_up = L.take(sizeof(int) * PM);
+  pl.o_en_glo64 = L.take(sizeof(double) * PM);
+  pl.o_en_gup64 = L.take(sizeof(double) * PM);
+  pl.o_en_glo32 = L.take(sizeof(float) * PM);
+  pl.o_en_gup32 = L.take(sizeof(float) * PM);
   pl.o_pair_ptr = L.take(sizeof(int) * (M + 1));
   pl.o_pair_a = L.take(sizeof(int) * std::max(1, pl.npairs));
   pl.o_pair_b = L.take(sizeof(int) * std::max(1, pl.npairs));
@@ -291,11 +300,13 @@ template <typename T>
 sgk::StripTables<T> strip_tables(const sg_ctx* h);
 template <>
 sgk::StripTables<double> strip_tables<double>(const sg_ctx* h) {
-  return {h->st_lo_d, h->st_up_d, h->st_glo64, h->st_gup64, h->M, h->mv_blocks_per_band};
+  return {h->st_lo_d, h->st_up_d, h->st_glo64, h->st_gup64, h->M, h->mv_blocks_per_band,
+          h->en_ptr_d, h->en_k_d, h->en_lo_d, h->en_up_d, h->en_glo64, h->en_gup64, h->mv_variant};
 }
 template <>
 sgk::StripTables<float> strip_tables<float>(const sg_ctx* h) {
-  return {h->st_lo_d, h->st_up_d, h->st_glo32, h->st_gup32, h->M, h->mv_blocks_per_band};
+  return {h->st_lo_d, h->st_up_d, h->st_glo32, h->st_gup32, h->M, h->mv_blocks_per_band,
+          h->en_ptr_d, h->en_k_d, h->en_lo_d, h->en_up_d, h->en_glo32, h->en_gup32, h->mv_variant};
 }
 
 template <typename T>
@@ -633,6 +644,8 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   cheb_interval(h->n_e, h->lmin, h->lmax);
   h->mv_blocks_per_band = 0;
   if (const char* env = std::getenv("SGPC_MV_BLOCKS_PER_BAND")) h->mv_blocks_per_band = std::atoi(env);
+  h->mv_variant = 1;
+  if (const char* env = std::getenv("SGPC_MV_VARIANT")) h->mv_variant = std::atoi(env);
   h->pcg_max_blocks = 0;
   if (const char* env = std::getenv("SGPC_PCG_MAX_BLOCKS")) h->pcg_max_blocks = std::atoi(env);
   int dev = 0;
@@ -713,6 +726,22 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
     }
   }
   std::vector<float> st_glo32(st_glo.begin(), st_glo.end()), st_gup32(st_gup.begin(), st_gup.end());
+  // compact entry lists: one entry per KL term with at least one Galerkin neighbour
+  std::vector<int> en_ptr(P + 1, 0), en_k, en_lo, en_up;
+  std::vector<double> en_glo, en_gup;
+  for (int a = 0; a < P; ++a) {
+    for (int k = 0; k < M; ++k) {
+      const int lo = st_lo[(size_t)a * M + k], upi = st_up[(size_t)a * M + k];
+      if (lo < 0 && upi < 0) continue;
+      en_k.push_back(k);
+      en_lo.push_back(lo >= 0 ? lo : a);
+      en_up.push_back(upi >= 0 ? upi : a);
+      en_glo.push_back(lo >= 0 ? st_glo[(size_t)a * M + k] : 0.0);
+      en_gup.push_back(upi >= 0 ? st_gup[(size_t)a * M + k] : 0.0);
+    }
+    en_ptr[a + 1] = (int)en_k.size();
+  }
+  std::vector<float> en_glo32(en_glo.begin(), en_glo.end()), en_gup32(en_gup.begin(), en_gup.end());
   std::vector<int> pair_ptr(M + 1, 0), pair_a, pair_b;
   std::vector<double> pair_g;
   for (int k = 0; k < M; ++k) {
@@ -743,6 +772,14 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   h->st_gup64 = (double*)(w + pl.o_st_gup64);
   h->st_glo32 = (float*)(w + pl.o_st_glo32);
   h->st_gup32 = (float*)(w + pl.o_st_gup32);
+  h->en_ptr_d = (int*)(w + pl.o_en_ptr);
+  h->en_k_d = (int*)(w + pl.o_en_k);
+  h->en_lo_d = (int*)(w + pl.o_en_lo);
+  h->en_up_d = (int*)(w + pl.o_en_up);
+  h->en_glo64 = (double*)(w + pl.o_en_glo64);
+  h->en_gup64 = (double*)(w + pl.o_en_gup64);
+  h->en_glo32 = (float*)(w + pl.o_en_glo32);
+  h->en_gup32 = (float*)(w + pl.o_en_gup32);
   h->pair_ptr_d = (int*)(w + pl.o_pair_ptr);
   h->pair_a_d = (int*)(w + pl.o_pair_a);
   h->pair_b_d = (int*)(w + pl.o_pair_b);
@@ -784,6 +821,14 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   if (e == hipSuccess) e = up(h->st_gup64, st_gup.data(), sizeof(double) * st_gup.size());
   if (e == hipSuccess) e = up(h->st_glo32, st_glo32.data(), sizeof(float) * st_glo32.size());
   if (e == hipSuccess) e = up(h->st_gup32, st_gup32.data(), sizeof(float) * st_gup32.size());
+  if (e == hipSuccess) e = up(h->en_ptr_d, en_ptr.data(), sizeof(int) * en_ptr.size());
+  if (e == hipSuccess) e = up(h->en_k_d, en_k.data(), sizeof(int) * en_k.size());
+  if (e == hipSuccess) e = up(h->en_lo_d, en_lo.data(), sizeof(int) * en_lo.size());
+  if (e == hipSuccess) e = up(h->en_up_d, en_up.data(), sizeof(int) * en_up.size());
+  if (e == hipSuccess) e = up(h->en_glo64, en_glo.data(), sizeof(double) * en_glo.size());
+  if (e == hipSuccess) e = up(h->en_gup64, en_gup.data(), sizeof(double) * en_gup.size());
+  if (e == hipSuccess) e = up(h->en_glo32, en_glo32.data(), sizeof(float) * en_glo32.size());
+  if (e == hipSuccess) e = up(h->en_gup32, en_gup32.data(), sizeof(float) * en_gup32.size());
   if (e == hipSuccess) e = up(h->pair_ptr_d, pair_ptr.data(), sizeof(int) * pair_ptr.size());
   if (e == hipSuccess) e = up(h->pair_a_d, pair_a.data(), sizeof(int) * pair_a.size());
   if (e == hipSuccess) e = up(h->pair_b_d, pair_b.data(), sizeof(int) * pair_b.size());

@@ -62,6 +62,15 @@ struct StripTables {
   const T* gup;
   int M;
   int blocks_per_band;  // row chunks per grid band (0 = default)
+  // Compact per-row entry lists for the occupancy variant: entries of row a are
+  // ent_ptr[a] .. ent_ptr[a+1]-1, each (k, lo, up) with glo/gup (absent side: index a, weight 0).
+  const int* ent_ptr;
+  const int* ent_k;
+  const int* ent_lo;
+  const int* ent_up;
+  const T* ent_glo;
+  const T* ent_gup;
+  int variant;  // 0: coefficients in registers, 1: coefficients loaded per entry
 };
 
 template <typename T>
@@ -160,6 +169,7 @@ struct sg_ctx {
   int num_cu;
   int tile;
   int mv_blocks_per_band;
+  int mv_variant;
   int pcg_max_blocks;
   // host copies of the chaos lists (for counters)
   std::vector<int> lo_ptr, up_ptr;
@@ -173,6 +183,9 @@ struct sg_ctx {
   double *lo_g64, *up_g64;
   float *lo_g32, *up_g32;
   int *st_lo_d, *st_up_d;
+  int *en_ptr_d, *en_k_d, *en_lo_d, *en_up_d;
+  double *en_glo64, *en_gup64;
+  float *en_glo32, *en_gup32;
   double *st_glo64, *st_gup64;
   float *st_glo32, *st_gup32;
   int *pair_ptr_d, *pair_a_d, *pair_b_d;
