@@ -122,6 +122,14 @@ __device__ __forceinline__ double from_prev(double v) {
 __device__ __forceinline__ float from_next(float v) { return __int_as_float(dpp_from_next(__float_as_int(v))); }
 __device__ __forceinline__ float from_prev(float v) { return __int_as_float(dpp_from_prev(__float_as_int(v))); }
 
+// Uniform read of a table the kernels never write: through the constant address
+// space so that it becomes a scalar load instead of a vector load plus readfirstlane.
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T* p, long i) {
+  typedef const __attribute__((address_space(4))) T* cptr;
+  return ((cptr)(p))[i];
+}
+
 // Node values of column gx for node rows gy0 .. gy0 + R + 1 (grid coordinates; zero outside).
 template <typename T, int R>
 __device__ __forceinline__ void load_strip(const T* __restrict__ col, int gx, int gy0, int nx, T (&u)[R + 2]) {
@@ -391,6 +399,256 @@ __global__ void __launch_bounds__(512) sgop_strip_dyn_kernel(const SgOpArgs<T> A
   }
 }
 
+// ---------------------------------------------------------------------------
+// y-marching kernel. A block spans the grid width (thread ex owns element
+// column ex and node column ex) and walks one segment of node rows upwards for
+// a small group of output chaos rows, so every node row of an input column is
+// read once per use within the segment. The segments of one XCD are handled by
+// all row groups at once, so the columns that several rows share are served
+// from that XCD's L2.
+//
+// At node row gy the block loads, for each output row a of the group, the
+// node values of a and of its Galerkin neighbours and forms per node x
+//   T  = sum_k a_k(e[x],   gy-1) w_k(x)   top-left corner of element x (row gy-1)
+//   Rt = sum_k a_k(e[x-1], gy-1) w_k(x)   top-right corner of element x-1
+//   B  = sum_k a_k(e[x],   gy)   w_k(x)   bottom-left corner of element x (row gy)
+//   Rb = sum_k a_k(e[x-1], gy)   w_k(x)   bottom-right corner of element x-1
+// with w_0 = diag * u_a and w_k = g_lo u_{a-e_k} + g_up u_{a+e_k}. Element x
+// of row gy-1 then has all four corner values (B and Rb from the previous node
+// row, Rt and Rb of node x+1 from lane x+1) and applies the Q1 element matrix
+// o_c = (5 V_c - sum V - V_opp(c)) / 6. Node row gy-1 is complete after that
+// and is written one step later, once the contribution across the wave
+// boundary has arrived through LDS (one barrier per node row). All loads of a
+// step are issued before the first of them is used.
+// ---------------------------------------------------------------------------
+constexpr int kMarchRGmax = kMarchRGU > kMarchRGL ? kMarchRGU : kMarchRGL;
+
+template <typename T, int NK, int RG, bool LK>
+__device__ __forceinline__ void march_body(const SgOpArgs<T>& A, const StripTables<T>& tab, const MarchJob& job,
+                                           int g, int ys, int ye, T (*xs)[8][kMarchRGmax][2],
+                                           T (*xo)[8][kMarchRGmax][2]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nwaves = blockDim.x >> 6;
+  const int ex = threadIdx.x;
+  const int ne = A.n_e, nx = A.nx, M = tab.M;
+  const long n = A.n;
+  const long ne2 = (long)ne * ne;
+  const int gbeg = ld_uniform(job.gptr, g);
+  const int cnt = ld_uniform(job.gptr, g + 1) - gbeg;
+  int rows[RG];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) rows[j] = j < cnt ? ld_uniform(job.grows, gbeg + j) : -1;
+  int ks[NK];
+#pragma unroll
+  for (int s = 0; s < NK; ++s) ks[s] = LK ? ld_uniform(job.lk, g * kMarchNS + s) : s;
+  const bool xin = ex >= 1 && ex <= nx;
+  const bool has_left = ex >= 1;
+  const int xl = wave * 64 - 1;  // element to the left of lane 0 (-1 for the first wave)
+  const bool last_wave = wave + 1 == nwaves;
+  const T scale = A.sgn / T(6);
+  const T* __restrict__ in = A.in;
+  const T* __restrict__ acoef = A.a;
+
+  T ac[NK], acp[NK], an[NK], anp[NK];
+#pragma unroll
+  for (int s = 0; s < NK; ++s) ac[s] = acp[s] = T(0);
+  T dc = T(0), dcp = T(0);
+  T pend[RG], carry[RG], Bp[RG], Rbp[RG];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) pend[j] = carry[j] = Bp[j] = Rbp[j] = T(0);
+
+  for (int gy = ys - 1; gy <= ye; ++gy) {
+    const int par = gy & 1;
+    const bool ev = gy <= ne - 1;  // element row gy (above node row gy) exists
+    const long abase = (long)gy * ne + ex;
+    const bool nin = xin && gy >= 1 && gy <= nx;
+    const long nidx = (long)(gy - 1) * nx + (ex - 1);
+    // ---- loads of the step: coefficients of element row gy, then the node values
+    T al0[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      const bool use = ev && ks[s] >= 0;
+      an[s] = use ? acoef[(long)ks[s] * ne2 + abase] : T(0);
+      al0[s] = (use && xl >= 0) ? ld_uniform(acoef, (long)ks[s] * ne2 + (long)gy * ne + xl) : T(0);
+    }
+    T ud[RG], ul[RG][NK], uu[RG][NK];
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      const int row = rows[j];
+      ud[j] = (row >= 0 && A.diag != T(0) && nin) ? in[(long)row * n + nidx] : T(0);
+#pragma unroll
+      for (int s = 0; s < NK; ++s) {
+        int lo = -1, up = -1;
+        if (row >= 0) {
+          if constexpr (LK) {
+            lo = ld_uniform(job.lcol, (g * kMarchRGL + j) * kMarchNS + s);
+          } else {
+            lo = A.use_lower ? ld_uniform(tab.lo, row * M + s) : -1;
+            up = A.use_upper ? ld_uniform(tab.up, row * M + s) : -1;
+          }
+        }
+        ul[j][s] = (lo >= 0 && nin) ? in[(long)lo * n + nidx] : T(0);
+        uu[j][s] = (!LK && up >= 0 && nin) ? in[(long)up * n + nidx] : T(0);
+      }
+    }
+    // ---- corner sums
+    const T dn = ev ? A.diag : T(0);
+    const T dnp = has_left ? dn : T(0);
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      T v = from_prev(an[s]);
+      if (lane == 0) v = al0[s];
+      anp[s] = v;
+    }
+    T sT[RG], sB[RG], Rtn[RG], Rbn[RG];
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      sT[j] = sB[j] = Rtn[j] = Rbn[j] = T(0);
+      const int row = rows[j];
+      if (row < 0) continue;
+      T t = dc * ud[j], rt = dcp * ud[j], b = dn * ud[j], rb = dnp * ud[j];
+#pragma unroll
+      for (int s = 0; s < NK; ++s) {
+        T w;
+        if constexpr (LK) {
+          const int lo = ld_uniform(job.lcol, (g * kMarchRGL + j) * kMarchNS + s);
+          if (lo < 0) continue;
+          w = T(ld_uniform(job.lw, (g * kMarchRGL + j) * kMarchNS + s)) * ul[j][s];
+        } else {
+          const int lo = A.use_lower ? ld_uniform(tab.lo, row * M + s) : -1;
+          const int up = A.use_upper ? ld_uniform(tab.up, row * M + s) : -1;
+          if (lo < 0 && up < 0) continue;
+          w = (lo >= 0 ? ld_uniform(tab.glo, row * M + s) * ul[j][s] : T(0)) +
+              (up >= 0 ? ld_uniform(tab.gup, row * M + s) * uu[j][s] : T(0));
+        }
+        t += ac[s] * w;
+        rt += acp[s] * w;
+        b += an[s] * w;
+        rb += anp[s] * w;
+      }
+      sT[j] = t;
+      sB[j] = b;
+      Rtn[j] = from_next(rt);
+      Rbn[j] = from_next(rb);
+      if (lane == 0) {
+        xs[par][wave][j][0] = rt;
+        xs[par][wave][j][1] = rb;
+      }
+    }
+    __syncthreads();
+    const int orow = gy - 2;  // node row completed one step ago
+    const bool wr = xin && orow >= ys && orow < ye;
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      const int row = rows[j];
+      if (row < 0) continue;
+      if (lane == 63 && !last_wave) {
+        Rtn[j] = xs[par][wave + 1][j][0];
+        Rbn[j] = xs[par][wave + 1][j][1];
+      }
+      if (lane == 0 && wave > 0 && gy >= ys) {
+        pend[j] += xo[par ^ 1][wave - 1][j][0];
+        carry[j] += xo[par ^ 1][wave - 1][j][1];
+      }
+      if (wr) {
+        const long idx = (long)row * n + (long)(orow - 1) * nx + (ex - 1);
+        T v = scale * pend[j];
+        if (A.rsrc) v += A.rcoef * A.rsrc[idx];
+        A.out[idx] = v;
+      }
+      // element x of element row gy-1: corners BL, BR (node row gy-1), TR, TL (node row gy)
+      const T BL = Bp[j], BR = Rbp[j], TR = Rtn[j], TL = sT[j];
+      const T S = (BL + BR) + (TR + TL);
+      const T oBL = T(5) * BL - S - TR;
+      const T oBR = T(5) * BR - S - TL;
+      const T oTR = T(5) * TR - S - BL;
+      const T oTL = T(5) * TL - S - BR;
+      pend[j] = oBL + carry[j] + from_prev(oBR);
+      carry[j] = oTL + from_prev(oTR);
+      if (lane == 63) {
+        xo[par][wave][j][0] = oBR;
+        xo[par][wave][j][1] = oTR;
+      }
+      Bp[j] = sB[j];
+      Rbp[j] = Rbn[j];
+    }
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      ac[s] = an[s];
+      acp[s] = anp[s];
+    }
+    dc = dn;
+    dcp = dnp;
+  }
+  // node row ye-1 waits for the wave-boundary term of the last step
+  __syncthreads();
+  const int orow = ye - 1;
+  const int lp = ye & 1;
+  if (xin && orow >= ys) {
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      const int row = rows[j];
+      if (row < 0) continue;
+      T pv = pend[j];
+      if (lane == 0 && wave > 0) pv += xo[lp][wave - 1][j][0];
+      const long idx = (long)row * n + (long)(orow - 1) * nx + (ex - 1);
+      T v = scale * pv;
+      if (A.rsrc) v += A.rcoef * A.rsrc[idx];
+      A.out[idx] = v;
+    }
+  }
+}
+
+template <typename T, int MT>
+__global__ void __launch_bounds__(512) sgop_march_kernel(const SgOpArgs<T> A, const StripTables<T> tab,
+                                                          const MarchJob job) {
+  __shared__ T xs[2][8][kMarchRGmax][2];  // lane 0 of each wave: (Rt, Rb) for lane 63 of the wave before
+  __shared__ T xo[2][8][kMarchRGmax][2];  // lane 63 of each wave: (o_BR, o_TR) for lane 0 of the wave after
+  const int nblocks = job.ngroups * job.nseg;
+  const int per_xcd = (nblocks + 7) / 8;
+  const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (logical >= nblocks) return;
+  const int seg = logical / job.ngroups, g = logical % job.ngroups;
+  const int ys = 1 + seg * job.seg_rows;
+  const int ye = min(A.nx + 1, ys + job.seg_rows);  // output node rows ys .. ye-1
+  if (ys >= ye) return;
+  if (ld_uniform(job.gkind, g) == 0) {
+    if constexpr (MT > 0) march_body<T, MT, kMarchRGU, false>(A, tab, job, g, ys, ye, xs, xo);
+  } else {
+    march_body<T, kMarchNS, kMarchRGL, true>(A, tab, job, g, ys, ye, xs, xo);
+  }
+}
+
+template <typename T, int MT>
+void launch_march(const SgOpArgs<T>& A, const StripTables<T>& tab, const MarchJob& job, hipStream_t s) {
+  const int nblocks = job.ngroups * job.nseg;
+  const int grid = (nblocks + 7) / 8 * 8;
+  hipLaunchKernelGGL((sgop_march_kernel<T, MT>), dim3(grid), dim3(A.n_e), 0, s, A, tab, job);
+}
+
+template <typename T, int MT>
+bool dispatch_march(const SgOpArgs<T>& A, const StripTables<T>& tab, const MarchJob& job, hipStream_t s) {
+  if (tab.M == MT) {
+    launch_march<T, MT>(A, tab, job, s);
+    return true;
+  }
+  if constexpr (MT > 0) return dispatch_march<T, MT - 1>(A, tab, job, s);
+  return false;
+}
+
+template <int MT>
+int march_occ(int M, int block) {
+  if (M == MT) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sgop_march_kernel<double, MT>, block, 0) != hipSuccess)
+      return 0;
+    return nb;
+  }
+  if constexpr (MT > 0) return march_occ<MT - 1>(M, block);
+  return 0;
+}
+
 template <typename T>
 void launch_strip_dyn(const SgOpArgs<T>& A, const StripTables<T>& tab, hipStream_t s) {
   constexpr int R = kStripR;
@@ -438,10 +696,17 @@ bool dispatch_strip(const SgOpArgs<T>& A, const StripTables<T>& tab, hipStream_t
 
 constexpr int kStripMaxM = 12;
 
+bool march_supported(int n_e, int M) { return n_e % 64 == 0 && n_e >= 64 && n_e <= 512 && M <= kStripMaxM; }
+
+int march_blocks_per_cu(int M, int block) { return march_occ<kStripMaxM>(M, block); }
+
 template <typename T>
-void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, hipStream_t s) {
+void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, const MarchJob* job, hipStream_t s) {
   if (args.nrows <= 0) return;
   const bool shape_ok = args.n_e % 64 == 0 && args.n_e >= 64 && args.n_e <= 512;
+  if (job != nullptr && shape_ok && tab.lo != nullptr && job->ngroups > 0 &&
+      dispatch_march<T, kStripMaxM>(args, tab, *job, s))
+    return;
   if (shape_ok && tab.variant == 1 && tab.ent_ptr != nullptr) {
     launch_strip_dyn<T>(args, tab, s);
     return;
@@ -453,7 +718,9 @@ void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, hipStream_t
   hipLaunchKernelGGL(sgop_kernel<T>, grid, dim3(256), 0, s, args);
 }
 
-template void launch_sgop<double>(const SgOpArgs<double>&, const StripTables<double>&, hipStream_t);
-template void launch_sgop<float>(const SgOpArgs<float>&, const StripTables<float>&, hipStream_t);
+template void launch_sgop<double>(const SgOpArgs<double>&, const StripTables<double>&, const MarchJob*,
+                                  hipStream_t);
+template void launch_sgop<float>(const SgOpArgs<float>&, const StripTables<float>&, const MarchJob*,
+                                 hipStream_t);
 
 }  // namespace sgk

@@ -90,6 +90,7 @@ struct Plan {
   size_t o_st_lo, o_st_up, o_st_glo64, o_st_gup64, o_st_glo32, o_st_gup32;
   size_t o_en_ptr, o_en_k, o_en_lo, o_en_up, o_en_glo64, o_en_gup64, o_en_glo32, o_en_gup32;
   size_t o_pair_ptr, o_pair_a, o_pair_b, o_pair_g;
+  size_t o_mj_ptr, o_mj_rows, o_mj_kind, o_mj_lk, o_mj_lcol, o_mj_lw;
   size_t o_vec[7];
   size_t o_rw, o_zw;
   size_t o_pcg[6];
@@ -170,6 +171,15 @@ void make_plan(const sg_problem* pr, const sg_opts* op, Plan& pl) {
   pl.o_pair_a = L.take(sizeof(int) * std::max(1, pl.npairs));
   pl.o_pair_b = L.take(sizeof(int) * std::max(1, pl.npairs));
   pl.o_pair_g = L.take(sizeof(double) * std::max(1, pl.npairs));
+  // row groups of the y-marching operator: the matvec (P rows) and the 2p coupling
+  // products (two levels each), at most one group per row
+  const long mj_rows = 3L * pl.P;
+  pl.o_mj_ptr = L.take(sizeof(int) * (mj_rows + 2L * p + 2));
+  pl.o_mj_rows = L.take(sizeof(int) * mj_rows);
+  pl.o_mj_kind = L.take(sizeof(int) * mj_rows);
+  pl.o_mj_lk = L.take(sizeof(int) * mj_rows * sgk::kMarchNS);
+  pl.o_mj_lcol = L.take(sizeof(int) * mj_rows * sgk::kMarchRGL * sgk::kMarchNS);
+  pl.o_mj_lw = L.take(sizeof(double) * mj_rows * sgk::kMarchRGL * sgk::kMarchNS);
   for (int i = 0; i < 7; ++i) pl.o_vec[i] = L.take(sizeof(double) * nP);
   pl.o_rw = L.take(isz * nP);
   pl.o_zw = L.take(op->inner_precision == 32 ? isz * nP : 0);
@@ -182,6 +192,79 @@ void make_plan(const sg_problem* pr, const sg_opts* op, Plan& pl) {
   pl.o_red_part = L.take(sizeof(double) * std::max<long>(4L * sgk::kRedBlocks, nb_contract * (M + 1)));
   pl.o_red_out = L.take(sizeof(double) * std::max(64, M + 1));
   pl.total = L.total;
+}
+
+// Row groups of one use of the y-marching SG operator. Rows that use upper
+// neighbours go into groups of kMarchRGU rows that carry all KL terms; the
+// other rows are packed greedily, in order, into groups of at most kMarchRGL
+// rows whose lower neighbours use at most kMarchNS distinct KL terms. The
+// number of grid segments aims at one resident wave of blocks (cap_blocks).
+struct HostMarchJob {
+  std::vector<int> ptr, rows, kind, lk, lcol;
+  std::vector<double> lw;
+  int nseg = 8, seg_rows = 1;
+};
+
+void build_march_job(int M, int nx, const std::vector<int>& rows, bool lower, bool upper,
+                     const std::vector<int>& st_lo, const std::vector<int>& st_up,
+                     const std::vector<double>& st_glo, long cap_blocks, HostMarchJob& J) {
+  const int RGU = sgk::kMarchRGU, RGL = sgk::kMarchRGL, NS = sgk::kMarchNS;
+  std::vector<int> ru, rl;
+  for (int r : rows) {
+    bool has_up = false;
+    for (int k = 0; k < M && upper; ++k) has_up = has_up || st_up[(size_t)r * M + k] >= 0;
+    (has_up ? ru : rl).push_back(r);
+  }
+  J.ptr.assign(1, 0);
+  J.rows.clear();
+  J.kind.clear();
+  J.lk.clear();
+  J.lcol.clear();
+  J.lw.clear();
+  auto close = [&](int kind, const std::vector<int>& grp, const std::vector<int>& slots) {
+    J.rows.insert(J.rows.end(), grp.begin(), grp.end());
+    J.ptr.push_back((int)J.rows.size());
+    J.kind.push_back(kind);
+    for (int s = 0; s < NS; ++s) J.lk.push_back(s < (int)slots.size() ? slots[s] : -1);
+    for (int j = 0; j < RGL; ++j)
+      for (int s = 0; s < NS; ++s) {
+        int col = -1;
+        double w = 0.0;
+        if (kind == 1 && j < (int)grp.size() && s < (int)slots.size() && lower) {
+          const size_t e = (size_t)grp[j] * M + slots[s];
+          col = st_lo[e];
+          w = col >= 0 ? st_glo[e] : 0.0;
+        }
+        J.lcol.push_back(col);
+        J.lw.push_back(w);
+      }
+  };
+  for (size_t i = 0; i < ru.size(); i += RGU) {
+    std::vector<int> grp(ru.begin() + i, ru.begin() + std::min(ru.size(), i + RGU));
+    close(0, grp, {});
+  }
+  std::vector<int> grp, slots;
+  for (int r : rl) {
+    std::vector<int> need;
+    for (int k = 0; k < M && lower; ++k)
+      if (st_lo[(size_t)r * M + k] >= 0) need.push_back(k);
+    std::vector<int> merged = slots;
+    for (int k : need)
+      if (std::find(merged.begin(), merged.end(), k) == merged.end()) merged.push_back(k);
+    if (!grp.empty() && ((int)grp.size() == RGL || (int)merged.size() > NS)) {
+      close(1, grp, slots);
+      grp.clear();
+      slots.clear();
+      merged = need;
+    }
+    grp.push_back(r);
+    slots = merged;
+  }
+  if (!grp.empty()) close(1, grp, slots);
+  const long ng = std::max<long>(1, (long)J.kind.size());
+  const long spx = std::max<long>(1, std::min<long>(nx / 64, cap_blocks / (8 * ng)));
+  J.nseg = (int)(8 * spx);
+  J.seg_rows = (nx + J.nseg - 1) / J.nseg;
 }
 
 // Spectrum of D^-1 K_0 for the Q1 stencil: (8 - 2 c_i - 2 c_j - 4 c_i c_j) / 8, c_i = cos(i pi / n_e).
@@ -336,7 +419,7 @@ void coupling(sg_ctx* h, int l, int dir, T* R, const T* V) {
   a.out = R;
   a.a = coefs<T>(h);
   a.lists = lists<T>(h);
-  sgk::launch_sgop<T>(a, strip_tables<T>(h), h->stream);
+  sgk::launch_sgop<T>(a, strip_tables<T>(h), h->march_ok ? &h->mjobs[1 + 2 * (l - 1) + dir] : nullptr, h->stream);
 }
 
 long coupling_blocks(const sg_ctx* h, int l, int dir) {
@@ -417,7 +500,7 @@ void matvec(sg_ctx* h, const double* U, double* Y) {
   a.out = Y;
   a.a = h->a64;
   a.lists = lists<double>(h);
-  sgk::launch_sgop<double>(a, strip_tables<double>(h), h->stream);
+  sgk::launch_sgop<double>(a, strip_tables<double>(h), h->march_ok ? &h->mjobs[0] : nullptr, h->stream);
 }
 
 int read_out(sg_ctx* h, int count) {
@@ -644,7 +727,7 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   cheb_interval(h->n_e, h->lmin, h->lmax);
   h->mv_blocks_per_band = 0;
   if (const char* env = std::getenv("SGPC_MV_BLOCKS_PER_BAND")) h->mv_blocks_per_band = std::atoi(env);
-  h->mv_variant = 1;
+  h->mv_variant = 2;
   if (const char* env = std::getenv("SGPC_MV_VARIANT")) h->mv_variant = std::atoi(env);
   h->pcg_max_blocks = 0;
   if (const char* env = std::getenv("SGPC_PCG_MAX_BLOCKS")) h->pcg_max_blocks = std::atoi(env);
@@ -833,6 +916,62 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   if (e == hipSuccess) e = up(h->pair_a_d, pair_a.data(), sizeof(int) * pair_a.size());
   if (e == hipSuccess) e = up(h->pair_b_d, pair_b.data(), sizeof(int) * pair_b.size());
   if (e == hipSuccess) e = up(h->pair_g_d, pair_g.data(), sizeof(double) * pair_g.size());
+  // row groups of the y-marching SG operator: job 0 is the matvec, job 1 + 2 (l - 1) + dir the
+  // coupling product of level l in direction dir
+  h->march_ok = false;
+  if (sgk::march_supported(h->n_e, M) && h->mv_variant == 2) {
+    const int occ = sgk::march_blocks_per_cu(M, h->n_e);
+    if (occ > 0) {
+      const long cap = (long)occ * h->num_cu;
+      std::vector<HostMarchJob> jobs(1 + 2 * h->p);
+      std::vector<int> all(P);
+      for (int a = 0; a < P; ++a) all[a] = a;
+      build_march_job(M, h->nx, all, true, true, st_lo, st_up, st_glo, cap, jobs[0]);
+      for (int l = 1; l <= h->p; ++l)
+        for (int dir = 0; dir < 2; ++dir) {
+          const int rl = dir == 0 ? l - 1 : l;
+          std::vector<int> rows;
+          for (int a = h->off[rl]; a < h->off[rl + 1]; ++a) rows.push_back(a);
+          build_march_job(M, h->nx, rows, dir == 1, dir == 0, st_lo, st_up, st_glo, cap, jobs[1 + 2 * (l - 1) + dir]);
+        }
+      std::vector<int> ptr, rws, knd, lk, lcol;
+      std::vector<double> lw;
+      h->mjobs.clear();
+      int* ptr_d = (int*)(w + pl.o_mj_ptr);
+      int* rows_d = (int*)(w + pl.o_mj_rows);
+      int* kind_d = (int*)(w + pl.o_mj_kind);
+      int* lk_d = (int*)(w + pl.o_mj_lk);
+      int* lcol_d = (int*)(w + pl.o_mj_lcol);
+      double* lw_d = (double*)(w + pl.o_mj_lw);
+      for (const HostMarchJob& J : jobs) {
+        sgk::MarchJob mj{};
+        mj.gptr = ptr_d + ptr.size();
+        mj.grows = rows_d;
+        mj.gkind = kind_d + knd.size();
+        mj.lk = lk_d + lk.size();
+        mj.lcol = lcol_d + lcol.size();
+        mj.lw = lw_d + lw.size();
+        mj.ngroups = (int)J.kind.size();
+        mj.nseg = J.nseg;
+        mj.seg_rows = J.seg_rows;
+        h->mjobs.push_back(mj);
+        const int base = (int)rws.size();
+        for (int v : J.ptr) ptr.push_back(base + v);
+        rws.insert(rws.end(), J.rows.begin(), J.rows.end());
+        knd.insert(knd.end(), J.kind.begin(), J.kind.end());
+        lk.insert(lk.end(), J.lk.begin(), J.lk.end());
+        lcol.insert(lcol.end(), J.lcol.begin(), J.lcol.end());
+        lw.insert(lw.end(), J.lw.begin(), J.lw.end());
+      }
+      if (e == hipSuccess) e = up(ptr_d, ptr.data(), sizeof(int) * ptr.size());
+      if (e == hipSuccess) e = up(rows_d, rws.data(), sizeof(int) * rws.size());
+      if (e == hipSuccess) e = up(kind_d, knd.data(), sizeof(int) * knd.size());
+      if (e == hipSuccess) e = up(lk_d, lk.data(), sizeof(int) * lk.size());
+      if (e == hipSuccess) e = up(lcol_d, lcol.data(), sizeof(int) * lcol.size());
+      if (e == hipSuccess) e = up(lw_d, lw.data(), sizeof(double) * lw.size());
+      h->march_ok = true;
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete h;

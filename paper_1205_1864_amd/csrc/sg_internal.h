@@ -73,8 +73,37 @@ struct StripTables {
   int variant;  // 0: coefficients in registers, 1: coefficients loaded per entry
 };
 
+// Row groups of one use of the SG operator (the full matvec, or one coupling
+// product) for the y-marching kernel. Group g owns rows grows[gptr[g] ..
+// gptr[g+1]-1]. A group of kind 0 holds at most kMarchRGU rows that have upper
+// neighbours (all KL terms used, neighbours from the dense [P][M] tables); a
+// group of kind 1 holds at most kMarchRGL rows with lower neighbours only,
+// whose KL terms are gathered into kMarchNS slots: lk[g][s] is the KL term
+// (0-based, -1 unused) of slot s and lcol/lw[g][j][s] the lower neighbour of
+// row j through that term (-1 none) and its weight. The grid rows 1..nx are cut
+// into nseg segments of seg_rows node rows; a block handles one (segment,
+// group) pair.
+constexpr int kMarchRGU = 2;
+constexpr int kMarchRGL = 6;
+constexpr int kMarchNS = 4;
+struct MarchJob {
+  const int* gptr;
+  const int* grows;
+  const int* gkind;
+  const int* lk;
+  const int* lcol;
+  const double* lw;
+  int ngroups;
+  int nseg;
+  int seg_rows;
+};
+
 template <typename T>
-void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, hipStream_t s);
+void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, const MarchJob* job, hipStream_t s);
+
+// Resident blocks per CU of the y-marching kernel for this M and block size (0 if unsupported).
+int march_blocks_per_cu(int M, int block);
+bool march_supported(int n_e, int M);
 
 // Persistent batched PCG on K_0 = theta0 * K_Lap (one independent solve per column).
 struct PcgScratch {
@@ -169,8 +198,10 @@ struct sg_ctx {
   int num_cu;
   int tile;
   int mv_blocks_per_band;
-  int mv_variant;
+  int mv_variant;  // 0, 1: band kernels; 2: y-marching kernel
   int pcg_max_blocks;
+  bool march_ok;
+  std::vector<sgk::MarchJob> mjobs;
   // host copies of the chaos lists (for counters)
   std::vector<int> lo_ptr, up_ptr;
   // device arrays inside the workspace
