@@ -191,6 +191,45 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
 /* Release the handle (the workspace stays with the caller). */
 void sg_destroy(sg_handle h);
 
+/* ---- Multi-problem batch.
+ * Many independent problems (each as in sg_setup: its own grid, KL terms and
+ * chaos degree) solved together by the flexible CG of Section 5 with the
+ * preconditioner opts.precond (SG_PC_HSC, Algorithm 1, or SG_PC_MEAN,
+ * Section 6); all problems share the options. One outer iteration of the
+ * batch runs, for all problems that have not stopped yet: the diagonal-block
+ * solves of each step of Algorithm 1 for every problem in one inner launch,
+ * the coupling products and SG matvecs of each problem, and batched vector
+ * updates whose scalars stay on the device. A problem stops on its own test
+ * (same stopping rule as sg_solve, zero initial guess) and is skipped from
+ * then on. */
+typedef struct sg_batch_ctx* sg_batch;
+
+/* Device workspace for a batch of `count` problems (probs[count], host). */
+int sg_batch_workspace_bytes(int32_t count, const sg_problem* probs, const sg_opts* opts, size_t* bytes);
+
+/* Set up the batch inside the workspace (device, 256-byte aligned, at least
+ * sg_batch_workspace_bytes long); all work goes to `stream`. */
+int sg_batch_setup(int32_t count, const sg_problem* probs, const sg_opts* opts, void* workspace,
+                   size_t workspace_bytes, void* stream, sg_batch* out);
+
+/* n and P of problem i of the batch. */
+int sg_batch_sizes(sg_batch b, int32_t i, int64_t* n, int32_t* P);
+
+/* Solve problem i: F[i] (right-hand side) and U[i] (solution) are n_i x P_i
+ * device blocks in the layout of sg_solve; F and U are host arrays of
+ * `count` device pointers. use_graph != 0 captures one outer iteration of the
+ * batch into a HIP graph at the second iteration and replays it afterwards
+ * (the batch's stream must then not be the default stream: SG_EINVAL).
+ * stats[count] (host, may be NULL) receives each problem's statistics (ms is
+ * the wall time of the whole batch); *ms_total (may be NULL) the same time.
+ * Returns SG_OK if every problem converged, else the first non-OK outcome
+ * (SG_BREAKDOWN before SG_NOT_CONVERGED); per-problem outcomes are in stats. */
+int sg_batch_solve(sg_batch b, const double* const* F, double* const* U, double rtol, int32_t maxit,
+                   int32_t use_graph, sg_stats* stats, double* ms_total);
+
+/* Release the batch and its per-problem handles (the workspace stays with the caller). */
+void sg_batch_destroy(sg_batch b);
+
 /* Thread-local description of the last failure (never NULL). */
 const char* sg_last_error(void);
 

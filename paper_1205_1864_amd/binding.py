@@ -70,6 +70,10 @@ def _load():
         "sg_solve": [VP, VP, VP, D, I32, I32, P(SgStats)],
         "sg_qoi": [VP, VP, VP, VP, P(D)],
         "sg_adjoint_grad": [VP, VP, VP, VP, D, I32, P(D), P(D), VP, P(SgStats)],
+        "sg_batch_workspace_bytes": [I32, P(SgProblem), P(SgOpts), P(ctypes.c_size_t)],
+        "sg_batch_setup": [I32, P(SgProblem), P(SgOpts), VP, ctypes.c_size_t, VP, P(VP)],
+        "sg_batch_sizes": [VP, I32, P(I64), P(I32)],
+        "sg_batch_solve": [VP, P(VP), P(VP), D, I32, I32, P(SgStats), P(D)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -77,6 +81,8 @@ def _load():
         fn.restype = ctypes.c_int
     lib.sg_destroy.argtypes = [VP]
     lib.sg_destroy.restype = None
+    lib.sg_batch_destroy.argtypes = [VP]
+    lib.sg_batch_destroy.restype = None
     lib.sg_last_error.argtypes = []
     lib.sg_last_error.restype = ctypes.c_char_p
     return lib
@@ -245,6 +251,79 @@ class SGSolver:
     def close(self):
         if getattr(self, "handle", None):
             lib.sg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SGBatch:
+    """Many independent SG problems solved together (a batch handle plus its workspace).
+
+    All problems share the options; ``precond`` must be "hsc" or "mean".
+    """
+
+    def __init__(self, problems, opts: Options = None, device="cuda", stream=None):
+        self.opts = opts or Options(inner_precision=32)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.count = len(problems)
+        cps, self._keep = [], []
+        for pr in problems:
+            cp, keep = make_c_problem(pr)
+            cps.append(cp)
+            self._keep.append(keep)
+        self._cps = (SgProblem * self.count)(*cps)
+        co = self.opts.to_c()
+        nb = ctypes.c_size_t(0)
+        _check(lib.sg_batch_workspace_bytes(self.count, self._cps, ctypes.byref(co), ctypes.byref(nb)))
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        # a graph is captured on the batch's stream, which therefore cannot be the default stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        h = ctypes.c_void_p()
+        _check(lib.sg_batch_setup(self.count, self._cps, ctypes.byref(co),
+                                  ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_size_t(int(nb.value)),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        self.sizes = []
+        for i in range(self.count):
+            n, P = ctypes.c_int64(), ctypes.c_int32()
+            _check(lib.sg_batch_sizes(h, i, ctypes.byref(n), ctypes.byref(P)))
+            self.sizes.append((int(n.value), int(P.value)))
+
+    def empty(self):
+        return [torch.empty((P, n), dtype=torch.float64, device=self.device) for n, P in self.sizes]
+
+    def sg_batch_solve(self, F, U=None, rtol=1e-8, maxit=200, use_graph=True):
+        U = self.empty() if U is None else U
+        if len(F) != self.count or len(U) != self.count:
+            raise ValueError(f"expected {self.count} right-hand sides and solutions")
+        for (n, P), f, u in zip(self.sizes, F, U):
+            for t in (f, u):
+                if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous() or \
+                        tuple(t.shape) != (P, n):
+                    raise ValueError(f"expected contiguous float64 ({P}, {n}) tensors on {self.device}")
+        fp = (ctypes.c_void_p * self.count)(*[f.data_ptr() for f in F])
+        up = (ctypes.c_void_p * self.count)(*[u.data_ptr() for u in U])
+        st = (SgStats * self.count)()
+        ms = ctypes.c_double()
+        caller = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(caller)  # F and U were produced on the caller's stream
+        rc = _check(lib.sg_batch_solve(self.handle, fp, up, float(rtol), int(maxit), int(bool(use_graph)), st,
+                                       ctypes.byref(ms)), allow_positive=True)
+        caller.wait_stream(self.stream)
+        stats = [s.as_dict() for s in st]
+        return U, stats, {"rc": rc, "ms": ms.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.sg_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -19,14 +19,19 @@
 // them, through split-phase counters (no grid-wide barrier). Per-column scalars
 // are reduced from per-tile partials in a fixed order, identically in every
 // block, so all owners of a column take the same decisions.
+//
+// The same kernel runs a ragged set of columns from several problems (grids
+// of different sizes, own constants, a per-problem skip flag): the tiles of
+// all columns form one work list and every column keeps its own arithmetic,
+// so a column's iterates do not depend on what else is in the launch.
 #include "sg_internal.h"
+#include "sg_device.h"
 
 namespace sgk {
 
 namespace {
 
 constexpr int kGroup = 256;                // threads per tile group
-constexpr int kMaxColsPerBlock = 64;
 constexpr long kSpinLimit = 1L << 26;      // bounded waits: a stuck column aborts the launch
 
 enum { PART_BB = 0, PART_PQ = 1, PART_RR0 = 2, PART_RR1 = 3, PART_RZ0 = 4, PART_RZ1 = 5, PART_N = 6 };
@@ -89,12 +94,24 @@ struct Interior {
 // domain). On return Zi holds z and Ri holds r on this thread's interior
 // nodes; the return value is the thread's partial r.z. With `valid` false the
 // group only takes part in the block-wide synchronisation.
+// The grid, state vectors and constants of one column.
+template <typename T>
+struct ColView {
+  int nx, ntx, ntiles;
+  long tbase;
+  const T* b;
+  T *x, *r0, *r1, *p0, *p1, *q, *z;
+  T c0, c1, inv_diag, inv_theta;
+  const T* chebA;
+  const T* chebB;
+};
+
 template <typename T, int TS, int NS, typename RF>
-__device__ double cheb_tile(const PcgArgs<T>& A, bool valid, int x0, int y0, RF rreg, T* W0, T* W1,
+__device__ double cheb_tile(const ColView<T>& A, int degree, bool valid, int x0, int y0, RF rreg, T* W0, T* W1,
                             T (&Zi)[Interior<TS>::NI], T (&Ri)[Interior<TS>::NI]) {
   constexpr int NI = Interior<TS>::NI;
   const int lt = threadIdx.x % kGroup;
-  const int H = A.degree - 1;
+  const int H = degree - 1;
   const int RS = TS + 2 * H;
   const int nreg = RS * RS;
   T S[NS];
@@ -126,9 +143,9 @@ __device__ double cheb_tile(const PcgArgs<T>& A, bool valid, int x0, int y0, RF 
   }
   T* cur = W0;
   T* nxt = W1;
-  for (int j = 1; j < A.degree; ++j) {
+  for (int j = 1; j < degree; ++j) {
     __syncthreads();  // reads of the buffer about to be overwritten are done
-    const T ca = A.chebA[j], cb = A.chebB[j];
+    const T ca = ld_uniform(A.chebA, j), cb = ld_uniform(A.chebB, j);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int i = lt + s * kGroup;
@@ -163,94 +180,161 @@ __device__ double cheb_tile(const PcgArgs<T>& A, bool valid, int x0, int y0, RF 
   return rz;
 }
 
-template <typename T, int TS, int NS, int G>
-__global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A) {
+template <typename T, int TS, int NS, int G, bool RAGGED>
+__global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, const PcgCols<T> C) {
   constexpr int NI = Interior<TS>::NI;
   extern __shared__ unsigned char smem_raw[];
   const int grp = threadIdx.x / kGroup;
   const int lt = threadIdx.x % kGroup;
-  const int H = A.degree - 1;
+  const int degree = A.degree;
+  const int H = degree - 1;
   const int RSa = TS + 2 * (H > 1 ? H : 1);  // phase A needs a 1-node halo
   const int CAP = RSa * RSa;
   T* W0 = reinterpret_cast<T*>(smem_raw) + (long)grp * 2 * CAP;
   T* W1 = W0 + CAP;
+  // per-column done flags of this block's columns, after the tile buffers
+  int* sdone = reinterpret_cast<int*>(reinterpret_cast<T*>(smem_raw) + (long)G * 2 * CAP);
   __shared__ double sred[G][4];
   __shared__ double s4[4];
-  __shared__ int sdone[kMaxColsPerBlock + 2];  // a run of <= kMaxColsPerBlock * ntiles tiles spans <= kMaxColsPerBlock + 1 columns
   __shared__ int sflag;
 
-  const long n = A.n;
-  const int ntiles = A.ntiles;
   const int ncols = A.ncols;
-  const long nwork = (long)ncols * ntiles;
+  const long nwork = RAGGED ? C.nwork : (long)ncols * A.ntiles;
   double* part = A.sc.part;
   unsigned* arr = A.sc.arrivals;
-  auto P = [&](int which) { return part + (long)which * ncols * ntiles; };
+  auto P = [&](int which) { return part + (long)which * nwork; };
+  // the grid, vectors and constants of column c
+  auto view = [&](int c) {
+    ColView<T> v;
+    if constexpr (RAGGED) {
+      v.nx = ld_uniform(C.nx, c);
+      v.ntx = ld_uniform(C.ntx, c);
+      v.ntiles = ld_uniform(C.ntiles, c);
+      v.tbase = ld_uniform(C.tbase, c);
+      v.b = ld_uniform(C.b, c);
+      v.x = ld_uniform(C.x, c);
+      v.r0 = ld_uniform(C.r0, c);
+      v.r1 = ld_uniform(C.r1, c);
+      v.p0 = ld_uniform(C.p0, c);
+      v.p1 = ld_uniform(C.p1, c);
+      v.q = ld_uniform(C.q, c);
+      v.z = ld_uniform(C.z, c);
+      const PcgConsts<T>* k = C.consts + ld_uniform(C.prob, c);
+      v.c0 = ld_uniform(&k->c0, 0);
+      v.c1 = ld_uniform(&k->c1, 0);
+      v.inv_diag = ld_uniform(&k->inv_diag, 0);
+      v.inv_theta = ld_uniform(&k->inv_theta, 0);
+      v.chebA = k->chebA;
+      v.chebB = k->chebB;
+    } else {
+      const long n = A.n;
+      v.nx = A.nx;
+      v.ntx = A.ntx;
+      v.ntiles = A.ntiles;
+      v.tbase = (long)c * A.ntiles;
+      v.b = A.B + (long)c * n;
+      v.x = A.X + (long)c * n;
+      v.r0 = A.R0 + (long)c * n;
+      v.r1 = A.R1 + (long)c * n;
+      v.p0 = A.P0 + (long)c * n;
+      v.p1 = A.P1 + (long)c * n;
+      v.q = A.Q + (long)c * n;
+      v.z = A.Z + (long)c * n;
+      v.c0 = A.c0;
+      v.c1 = A.c1;
+      v.inv_diag = A.inv_diag;
+      v.inv_theta = A.inv_theta;
+      v.chebA = A.chebA;
+      v.chebB = A.chebB;
+    }
+    return v;
+  };
+  // column holding work index w
+  auto column_of = [&](long w) {
+    if constexpr (RAGGED) {
+      int lo = 0, hi = ncols - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ld_uniform(C.tbase, mid) <= w) lo = mid; else hi = mid - 1;
+      }
+      return lo;
+    } else {
+      return (int)(w / A.ntiles);
+    }
+  };
   const long per_block = (nwork + gridDim.x - 1) / gridDim.x;
   const long w_begin = (long)blockIdx.x * per_block;
   const long w_end = w_begin + per_block < nwork ? w_begin + per_block : nwork;
   if (w_begin >= w_end) return;
-  const int c_first = (int)(w_begin / ntiles), c_last = (int)((w_end - 1) / ntiles);
-  auto tiles_of = [&](int c, int& t0, int& t1) {
-    const long lo = (long)c * ntiles > w_begin ? (long)c * ntiles : w_begin;
-    const long hi = (long)(c + 1) * ntiles < w_end ? (long)(c + 1) * ntiles : w_end;
-    t0 = (int)(lo - (long)c * ntiles);
-    t1 = (int)(hi - (long)c * ntiles);
+  const int c_first = column_of(w_begin), c_last = column_of(w_end - 1);
+  auto tiles_of = [&](const ColView<T>& v, int& t0, int& t1) {
+    const long lo = v.tbase > w_begin ? v.tbase : w_begin;
+    const long hi = v.tbase + v.ntiles < w_end ? v.tbase + v.ntiles : w_end;
+    t0 = (int)(lo - v.tbase);
+    t1 = (int)(hi - v.tbase);
   };
-  auto owner = [&](int c) { return (long)c * ntiles >= w_begin; };  // this block holds tile 0 of c
-  // Fixed-order sums of up to four per-tile partial arrays of column c, one wave each.
-  auto col_sums = [&](int c, const double* q0, const double* q1, const double* q2, const double* q3) {
+  auto owner = [&](const ColView<T>& v) { return v.tbase >= w_begin; };  // this block holds tile 0
+  // Fixed-order sums of up to four per-tile partial arrays of a column, one wave each.
+  auto col_sums = [&](const ColView<T>& v, const double* q0, const double* q1, const double* q2, const double* q3) {
     __syncthreads();
     const int wv = threadIdx.x >> 6;
     const double* src = wv == 0 ? q0 : wv == 1 ? q1 : wv == 2 ? q2 : q3;
     if (wv < 4 && src) {
-      double v = 0.0;
-      for (int t = threadIdx.x & 63; t < ntiles; t += 64) v += src[(long)c * ntiles + t];
-      v = wave_sum(v);
-      if ((threadIdx.x & 63) == 0) s4[wv] = v;
+      double s = 0.0;
+      for (int t = threadIdx.x & 63; t < v.ntiles; t += 64) s += src[v.tbase + t];
+      s = wave_sum(s);
+      if ((threadIdx.x & 63) == 0) s4[wv] = s;
     }
     __syncthreads();
   };
-  auto tile_xy = [&](int t, int& x0, int& y0) {
-    x0 = (t % A.ntx) * TS;
-    y0 = (t / A.ntx) * TS;
+  auto tile_xy = [&](const ColView<T>& v, int t, int& x0, int& y0) {
+    x0 = (t % v.ntx) * TS;
+    y0 = (t / v.ntx) * TS;
   };
-  for (int c = c_first + (int)threadIdx.x; c <= c_last; c += kGroup * G) sdone[c - c_first] = 0;
+  for (int c = c_first + (int)threadIdx.x; c <= c_last; c += kGroup * G) {
+    int skip = 0;
+    if constexpr (RAGGED) skip = C.active[C.prob[c]] == 0;
+    sdone[c - c_first] = skip;
+  }
+  __syncthreads();
 
   T Zi[NI], Ri[NI];
 
   // ---- start (column phase 1): x = 0, z = M b, partials b.b and b.z
   for (int c = c_first; c <= c_last; ++c) {
+    const ColView<T> v = view(c);
+    if (sdone[c - c_first]) {
+      if (threadIdx.x == 0 && owner(v)) A.sc.iters[c] = 0;
+      continue;
+    }
     int t0, t1;
-    tiles_of(c, t0, t1);
-    const T* bcol = A.B + (long)c * n;
-    T* xcol = A.X + (long)c * n;
-    T* zcol = A.Z + (long)c * n;
+    tiles_of(v, t0, t1);
+    const int nx = v.nx;
     for (int tb = t0; tb < t1; tb += G) {
       const int t = tb + grp;
       const bool valid = t < t1;
       int x0 = 0, y0 = 0;
-      if (valid) tile_xy(t, x0, y0);
+      if (valid) tile_xy(v, t, x0, y0);
       __syncthreads();
-      auto rreg = [&](int lx, int ly) { return bcol[(long)(y0 - H + ly) * A.nx + (x0 - H + lx)]; };
-      double rz = cheb_tile<T, TS, NS>(A, valid, x0, y0, rreg, W0, W1, Zi, Ri);
+      auto rreg = [&](int lx, int ly) { return v.b[(long)(y0 - H + ly) * nx + (x0 - H + lx)]; };
+      double rz = cheb_tile<T, TS, NS>(v, degree, valid, x0, y0, rreg, W0, W1, Zi, Ri);
       double bb = 0.0;
 #pragma unroll
       for (int k = 0; k < NI; ++k) {
         const int i = lt + k * kGroup;
         const int gx = x0 + i % TS, gy = y0 + i / TS;
-        if (valid && i < TS * TS && gx < A.nx && gy < A.nx) {
-          const long g = (long)gy * A.nx + gx;
+        if (valid && i < TS * TS && gx < nx && gy < nx) {
+          const long g = (long)gy * nx + gx;
           bb += (double)Ri[k] * (double)Ri[k];
-          xcol[g] = T(0);
-          zcol[g] = Zi[k];
+          v.x[g] = T(0);
+          v.z[g] = Zi[k];
         }
       }
       rz = group_sum<G>(rz, sred);
       bb = group_sum<G>(bb, sred);
       if (valid && lt == 0) {
-        P(PART_RZ1)[(long)c * ntiles + t] = rz;
-        P(PART_BB)[(long)c * ntiles + t] = bb;
+        P(PART_RZ1)[v.tbase + t] = rz;
+        P(PART_BB)[v.tbase + t] = bb;
       }
     }
     column_arrive(arr + c, (unsigned)(t1 - t0));
@@ -259,17 +343,16 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A) {
   bool aborted = false;
   for (int it = 0; it < A.maxit && !aborted; ++it) {
     const int par = it & 1;
-    T* Pnew = par ? A.P1 : A.P0;
-    const T* Pold = par ? A.P0 : A.P1;
     bool any_active = false;
     // ---- phase A (column phase 2 + 2 it): p = z + beta p, q = K_0 p, partial p.q
     for (int c = c_first; c <= c_last && !aborted; ++c) {
       if (sdone[c - c_first]) continue;
-      if (!column_wait(arr + c, (unsigned)((1 + 2 * it) * ntiles), A.sc.status, &sflag)) {
+      const ColView<T> v = view(c);
+      if (!column_wait(arr + c, (unsigned)((1 + 2 * it) * v.ntiles), A.sc.status, &sflag)) {
         aborted = true;
         break;
       }
-      col_sums(c, P(PART_BB), it == 0 ? nullptr : P(par ? PART_RR0 : PART_RR1),
+      col_sums(v, P(PART_BB), it == 0 ? nullptr : P(par ? PART_RR0 : PART_RR1),
                it == 0 ? nullptr : P(par ? PART_RZ0 : PART_RZ1), it == 0 ? nullptr : P(par ? PART_RZ1 : PART_RZ0));
       const double bb = s4[0];
       const double rr = it == 0 ? s4[0] : s4[1];
@@ -277,7 +360,7 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A) {
         __syncthreads();
         if (threadIdx.x == 0) {
           sdone[c - c_first] = 1;
-          if (owner(c)) A.sc.iters[c] = it;
+          if (owner(v)) A.sc.iters[c] = it;
         }
         __syncthreads();
         continue;
@@ -285,27 +368,28 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A) {
       const T beta = it == 0 ? T(0) : (T)(s4[2] / s4[3]);
       any_active = true;
       int t0, t1;
-      tiles_of(c, t0, t1);
-      const T* zc = A.Z + (long)c * n;
-      const T* po = Pold + (long)c * n;
-      T* pn = Pnew + (long)c * n;
-      T* qc = A.Q + (long)c * n;
+      tiles_of(v, t0, t1);
+      const int nx = v.nx;
+      const T* zc = v.z;
+      const T* po = par ? v.p0 : v.p1;
+      T* pn = par ? v.p1 : v.p0;
+      T* qc = v.q;
       const int RS1 = TS + 2;
       for (int tb = t0; tb < t1; tb += G) {
         const int t = tb + grp;
         const bool valid = t < t1;
         int x0 = 0, y0 = 0;
-        if (valid) tile_xy(t, x0, y0);
+        if (valid) tile_xy(v, t, x0, y0);
         __syncthreads();
         if (valid) {
           for (int i = lt; i < RS1 * RS1; i += kGroup) {
             const int gx = x0 - 1 + i % RS1, gy = y0 - 1 + i / RS1;
-            T v = T(0);
-            if (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) {
-              const long g = (long)gy * A.nx + gx;
-              v = it == 0 ? zc[g] : zc[g] + beta * po[g];
+            T val = T(0);
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < nx) {
+              const long g = (long)gy * nx + gx;
+              val = it == 0 ? zc[g] : zc[g] + beta * po[g];
             }
-            W0[i] = v;
+            W0[i] = val;
           }
         }
         __syncthreads();
@@ -315,72 +399,72 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A) {
           const int i = lt + k * kGroup;
           const int lx = i % TS + 1, ly = i / TS + 1;
           const int gx = x0 + lx - 1, gy = y0 + ly - 1;
-          if (valid && i < TS * TS && gx < A.nx && gy < A.nx) {
+          if (valid && i < TS * TS && gx < nx && gy < nx) {
             const int q = ly * RS1 + lx;
             const T pc = W0[q];
             const T s8 = W0[q - RS1 - 1] + W0[q - RS1] + W0[q - RS1 + 1] + W0[q - 1] + W0[q + 1] +
                          W0[q + RS1 - 1] + W0[q + RS1] + W0[q + RS1 + 1];
-            const T qv = A.c0 * pc + A.c1 * s8;
-            const long g = (long)gy * A.nx + gx;
+            const T qv = v.c0 * pc + v.c1 * s8;
+            const long g = (long)gy * nx + gx;
             pn[g] = pc;
             qc[g] = qv;
             pq += (double)pc * (double)qv;
           }
         }
         pq = group_sum<G>(pq, sred);
-        if (valid && lt == 0) P(PART_PQ)[(long)c * ntiles + t] = pq;
+        if (valid && lt == 0) P(PART_PQ)[v.tbase + t] = pq;
       }
       column_arrive(arr + c, (unsigned)(t1 - t0));
     }
     if (!any_active || aborted) break;
     // ---- phase B (column phase 3 + 2 it): x += alpha p, r -= alpha q, z = M r, partials r.r, r.z
-    T* Rnew = par ? A.R0 : A.R1;
-    const T* Rold = it == 0 ? A.B : (par ? A.R1 : A.R0);
     for (int c = c_first; c <= c_last && !aborted; ++c) {
       if (sdone[c - c_first]) continue;
-      if (!column_wait(arr + c, (unsigned)((2 + 2 * it) * ntiles), A.sc.status, &sflag)) {
+      const ColView<T> v = view(c);
+      if (!column_wait(arr + c, (unsigned)((2 + 2 * it) * v.ntiles), A.sc.status, &sflag)) {
         aborted = true;
         break;
       }
-      col_sums(c, P(PART_PQ), P(par ? PART_RZ0 : PART_RZ1), nullptr, nullptr);
+      col_sums(v, P(PART_PQ), P(par ? PART_RZ0 : PART_RZ1), nullptr, nullptr);
       const double pq = s4[0], gam = s4[1];
       if (!(pq > 0.0) || !isfinite(pq)) {
         // breakdown: keep the current iterate
         __syncthreads();
         if (threadIdx.x == 0) {
           sdone[c - c_first] = 1;
-          if (owner(c)) A.sc.iters[c] = it;
+          if (owner(v)) A.sc.iters[c] = it;
         }
         __syncthreads();
         continue;
       }
       const T alpha = (T)(gam / pq);
       int t0, t1;
-      tiles_of(c, t0, t1);
-      const T* pc = Pnew + (long)c * n;
-      const T* qc = A.Q + (long)c * n;
-      const T* ro = Rold + (long)c * n;
-      T* rn = Rnew + (long)c * n;
-      T* xc = A.X + (long)c * n;
-      T* zc = A.Z + (long)c * n;
+      tiles_of(v, t0, t1);
+      const int nx = v.nx;
+      const T* pc = par ? v.p1 : v.p0;
+      const T* qc = v.q;
+      const T* ro = it == 0 ? v.b : (par ? v.r1 : v.r0);
+      T* rn = par ? v.r0 : v.r1;
+      T* xc = v.x;
+      T* zc = v.z;
       for (int tb = t0; tb < t1; tb += G) {
         const int t = tb + grp;
         const bool valid = t < t1;
         int x0 = 0, y0 = 0;
-        if (valid) tile_xy(t, x0, y0);
+        if (valid) tile_xy(v, t, x0, y0);
         __syncthreads();
         auto rreg = [&](int lx, int ly) {
-          const long g = (long)(y0 - H + ly) * A.nx + (x0 - H + lx);
+          const long g = (long)(y0 - H + ly) * nx + (x0 - H + lx);
           return ro[g] - alpha * qc[g];
         };
-        double rz = cheb_tile<T, TS, NS>(A, valid, x0, y0, rreg, W0, W1, Zi, Ri);
+        double rz = cheb_tile<T, TS, NS>(v, degree, valid, x0, y0, rreg, W0, W1, Zi, Ri);
         double rr = 0.0;
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
           const int i = lt + k * kGroup;
           const int gx = x0 + i % TS, gy = y0 + i / TS;
-          if (valid && i < TS * TS && gx < A.nx && gy < A.nx) {
-            const long g = (long)gy * A.nx + gx;
+          if (valid && i < TS * TS && gx < nx && gy < nx) {
+            const long g = (long)gy * nx + gx;
             xc[g] = it == 0 ? alpha * pc[g] : xc[g] + alpha * pc[g];
             rn[g] = Ri[k];
             zc[g] = Zi[k];
@@ -390,8 +474,8 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A) {
         rz = group_sum<G>(rz, sred);
         rr = group_sum<G>(rr, sred);
         if (valid && lt == 0) {
-          P(par ? PART_RZ1 : PART_RZ0)[(long)c * ntiles + t] = rz;
-          P(par ? PART_RR1 : PART_RR0)[(long)c * ntiles + t] = rr;
+          P(par ? PART_RZ1 : PART_RZ0)[v.tbase + t] = rz;
+          P(par ? PART_RR1 : PART_RR0)[v.tbase + t] = rr;
         }
       }
       column_arrive(arr + c, (unsigned)(t1 - t0));
@@ -401,7 +485,7 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A) {
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int c = c_first; c <= c_last; ++c)
-      if (!sdone[c - c_first] && owner(c)) A.sc.iters[c] = A.maxit;
+      if (!sdone[c - c_first] && owner(view(c))) A.sc.iters[c] = A.maxit;
   }
 }
 
@@ -411,56 +495,86 @@ __global__ void pcg_reset_kernel(unsigned* arr, int ncols, int* status) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
 }
 
-template <typename T, int TS, int NS, int G>
-hipError_t launch_cfg(const PcgArgs<T>& args, int max_blocks, hipStream_t s) {
+template <typename T, int TS, int NS, int G, bool RAGGED>
+hipError_t launch_cfg(const PcgArgs<T>& args, const PcgCols<T>& cols, int max_blocks, hipStream_t s) {
   const int H = args.degree - 1;
   const int RSa = TS + 2 * (H > 1 ? H : 1);
   if ((TS + 2 * H) * (TS + 2 * H) > NS * kGroup) return hipErrorInvalidValue;
-  const size_t sm = sizeof(T) * 2 * (size_t)RSa * RSa * G;
-  auto kfn = pcg_kernel<T, TS, NS, G>;
-  hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  if (ea != hipSuccess) return ea;
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kGroup * G, sm);
-  if (e != hipSuccess) return e;
+  const size_t tiles_bytes = sizeof(T) * 2 * (size_t)RSa * RSa * G;
+  auto kfn = pcg_kernel<T, TS, NS, G, RAGGED>;
+  const long nwork = RAGGED ? cols.nwork : (long)args.ncols * args.ntiles;
+  if (nwork <= 0) return hipSuccess;
   int dev = 0;
-  e = hipGetDevice(&dev);
+  hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   int ncu = 0;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const long nwork = (long)args.ncols * args.ntiles;
   // Enough blocks to keep every tile group busy, as few as possible beyond
-  // that: every block pays a device-wide release per column and phase.
+  // that: every block pays a device-wide release per column and phase. The
+  // grid must fit on the device at once with the LDS it needs (tile buffers
+  // plus one done flag per column a block can touch).
+  const long min_tiles = RAGGED ? 1 : args.ntiles;
   long grid = (nwork + 2L * G - 1) / (2L * G);
-  const long cap = (long)per_cu * ncu;
-  if (grid > cap) grid = cap;
   if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid < 1) grid = 1;
-  if ((nwork + grid - 1) / grid > (long)kMaxColsPerBlock * args.ntiles) return hipErrorInvalidValue;
+  size_t sm = 0;
+  for (int pass = 0; pass < 8; ++pass) {
+    const long per_block = (nwork + grid - 1) / grid;
+    const long max_cols = per_block / min_tiles + 2;  // a run of per_block items spans at most this many columns
+    sm = tiles_bytes + sizeof(int) * (size_t)max_cols;
+    if (sm > 160 * 1024) return hipErrorInvalidValue;
+    // the cooperative launch checks co-residency against this attribute, so keep it exact
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kGroup * G, sm);
+    if (e != hipSuccess) return e;
+    const long cap = (long)per_cu * ncu;
+    if (cap < 1) return hipErrorInvalidValue;
+    if (grid <= cap) break;
+    grid = cap;
+    if (pass == 7) return hipErrorInvalidValue;
+  }
   PcgArgs<T> a = args;
+  PcgCols<T> c = cols;
   hipLaunchKernelGGL(pcg_reset_kernel, dim3(1), dim3(256), 0, s, a.sc.arrivals, a.ncols, a.sc.status);
-  void* kargs[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3((unsigned)grid), dim3(kGroup * G),
-                                    kargs, (unsigned)sm, s);
+  if (!RAGGED) {
+    void* kargs[] = {&a, &c};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3((unsigned)grid),
+                                      dim3(kGroup * G), kargs, (unsigned)sm, s);
+  }
+  hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(kGroup * G), sm, s, a, c);
+  return hipGetLastError();
 }
 
 constexpr int slots(int ts, int maxh) { return ((ts + 2 * maxh) * (ts + 2 * maxh) + kGroup - 1) / kGroup; }
+
+template <typename T, bool RAGGED>
+hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile, int max_blocks, hipStream_t s) {
+  if (args.ncols <= 0) return hipSuccess;
+  const int H = args.degree - 1;
+  if (tile == 32) {
+    if (H <= 3) return launch_cfg<T, 32, slots(32, 3), 4, RAGGED>(args, cols, max_blocks, s);
+    if (H <= 7) return launch_cfg<T, 32, slots(32, 7), 2, RAGGED>(args, cols, max_blocks, s);
+  }
+  return launch_cfg<T, 16, slots(16, 15), 4, RAGGED>(args, cols, max_blocks, s);
+}
 
 }  // namespace
 
 template <typename T>
 hipError_t launch_pcg(const PcgArgs<T>& args, int tile, int max_blocks, hipStream_t s) {
-  if (args.ncols <= 0) return hipSuccess;
-  const int H = args.degree - 1;
-  if (tile == 32) {
-    if (H <= 3) return launch_cfg<T, 32, slots(32, 3), 4>(args, max_blocks, s);
-    if (H <= 7) return launch_cfg<T, 32, slots(32, 7), 2>(args, max_blocks, s);
-  }
-  return launch_cfg<T, 16, slots(16, 15), 4>(args, max_blocks, s);
+  return dispatch_pcg<T, false>(args, PcgCols<T>{}, tile, max_blocks, s);
 }
 
+template <typename T>
+hipError_t launch_pcg_ragged(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile, hipStream_t s) {
+  return dispatch_pcg<T, true>(args, cols, tile, 0, s);
+}
+
+template hipError_t launch_pcg_ragged<double>(const PcgArgs<double>&, const PcgCols<double>&, int, hipStream_t);
+template hipError_t launch_pcg_ragged<float>(const PcgArgs<float>&, const PcgCols<float>&, int, hipStream_t);
 template hipError_t launch_pcg<double>(const PcgArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_pcg<float>(const PcgArgs<float>&, int, int, hipStream_t);
 

@@ -10,6 +10,7 @@
 //   (K_k u)_i = 1/6 sum_{e ni i} a_k(e) (4 u_i - u_adj1 - u_adj2 - 2 u_opp)
 // over the four elements sharing i (the Q1 element matrix of a square).
 #include "sg_internal.h"
+#include "sg_device.h"
 
 namespace sgk {
 
@@ -25,6 +26,7 @@ __device__ __forceinline__ T load_node(const T* __restrict__ col, int gx, int gy
 
 template <typename T>
 __global__ void __launch_bounds__(256) sgop_kernel(const SgOpArgs<T> A) {
+  if (A.active && ld_uniform(A.active, 0) == 0) return;
   const int tiles_x = (A.nx + kTile - 1) / kTile;
   const int tx = blockIdx.x % tiles_x;
   const int ty = blockIdx.x / tiles_x;
@@ -122,14 +124,6 @@ __device__ __forceinline__ double from_prev(double v) {
 __device__ __forceinline__ float from_next(float v) { return __int_as_float(dpp_from_next(__float_as_int(v))); }
 __device__ __forceinline__ float from_prev(float v) { return __int_as_float(dpp_from_prev(__float_as_int(v))); }
 
-// Uniform read of a table the kernels never write: through the constant address
-// space so that it becomes a scalar load instead of a vector load plus readfirstlane.
-template <typename T>
-__device__ __forceinline__ T ld_uniform(const T* p, long i) {
-  typedef const __attribute__((address_space(4))) T* cptr;
-  return ((cptr)(p))[i];
-}
-
 // Node values of column gx for node rows gy0 .. gy0 + R + 1 (grid coordinates; zero outside).
 template <typename T, int R>
 __device__ __forceinline__ void load_strip(const T* __restrict__ col, int gx, int gy0, int nx, T (&u)[R + 2]) {
@@ -162,6 +156,7 @@ __device__ __forceinline__ void combo_strip(const T* in, long n, int blo, T glo,
 template <typename T, int MT, int R>
 __global__ void __launch_bounds__(512) sgop_strip_kernel(const SgOpArgs<T> A, const StripTables<T> tab, int nbands,
                                                           int nchunks, int chunk_rows) {
+  if (A.active && ld_uniform(A.active, 0) == 0) return;
   __shared__ T xch[2][8][R];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ex = threadIdx.x;
@@ -283,6 +278,7 @@ __global__ void __launch_bounds__(512) sgop_strip_kernel(const SgOpArgs<T> A, co
 template <typename T, int R>
 __global__ void __launch_bounds__(512) sgop_strip_dyn_kernel(const SgOpArgs<T> A, const StripTables<T> tab,
                                                               int nbands, int nchunks, int chunk_rows) {
+  if (A.active && ld_uniform(A.active, 0) == 0) return;
   __shared__ T xch[2][8][R];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ex = threadIdx.x;
@@ -605,6 +601,7 @@ __global__ void __launch_bounds__(512) sgop_march_kernel(const SgOpArgs<T> A, co
                                                           const MarchJob job) {
   __shared__ T xs[2][8][kMarchRGmax][2];  // lane 0 of each wave: (Rt, Rb) for lane 63 of the wave before
   __shared__ T xo[2][8][kMarchRGmax][2];  // lane 63 of each wave: (o_BR, o_TR) for lane 0 of the wave after
+  if (A.active && ld_uniform(A.active, 0) == 0) return;
   const int nblocks = job.ngroups * job.nseg;
   const int per_xcd = (nblocks + 7) / 8;
   const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;

@@ -16,9 +16,10 @@
 #include <string>
 #include <vector>
 
+#include "sg_host.h"
 #include "sg_internal.h"
 
-namespace {
+namespace sgh {
 
 thread_local std::string g_last_error = "no error";
 
@@ -26,13 +27,6 @@ int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
-
-#define SG_HIP(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(SG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));        \
-  } while (0)
 
 long binom(int n, int k) {
   if (k < 0 || k > n) return 0;
@@ -306,6 +300,9 @@ void fill_pcg_consts(const sg_ctx* h, sgk::PcgArgs<T>& a) {
   }
 }
 
+template void fill_pcg_consts<double>(const sg_ctx*, sgk::PcgArgs<double>&);
+template void fill_pcg_consts<float>(const sg_ctx*, sgk::PcgArgs<float>&);
+
 int effective_degree(const sg_ctx* h) { return h->lmax - h->lmin > 0.0 ? h->opts.cheb_degree : 1; }
 
 int choose_tile(const sg_ctx* h, int degree) {
@@ -419,8 +416,12 @@ void coupling(sg_ctx* h, int l, int dir, T* R, const T* V) {
   a.out = R;
   a.a = coefs<T>(h);
   a.lists = lists<T>(h);
+  a.active = h->mask;
   sgk::launch_sgop<T>(a, strip_tables<T>(h), h->march_ok ? &h->mjobs[1 + 2 * (l - 1) + dir] : nullptr, h->stream);
 }
+
+template void coupling<double>(sg_ctx*, int, int, double*, const double*);
+template void coupling<float>(sg_ctx*, int, int, float*, const float*);
 
 long coupling_blocks(const sg_ctx* h, int l, int dir) {
   const int rl = dir == 0 ? l - 1 : l;
@@ -500,6 +501,7 @@ void matvec(sg_ctx* h, const double* U, double* Y) {
   a.out = Y;
   a.a = h->a64;
   a.lists = lists<double>(h);
+  a.active = h->mask;
   sgk::launch_sgop<double>(a, strip_tables<double>(h), h->march_ok ? &h->mjobs[0] : nullptr, h->stream);
 }
 
@@ -510,8 +512,8 @@ int read_out(sg_ctx* h, int count) {
   return SG_OK;
 }
 
-int dots(sg_ctx* h, int nd, const double* a0, const double* b0, const double* a1 = nullptr,
-         const double* b1 = nullptr, const double* a2 = nullptr, const double* b2 = nullptr) {
+int dots(sg_ctx* h, int nd, const double* a0, const double* b0, const double* a1, const double* b1,
+         const double* a2, const double* b2) {
   const double* A[3] = {a0, a1, a2};
   const double* B[3] = {b0, b1, b2};
   sgk::launch_dots(A, B, nd, h->n * (long)h->P, h->red_part, h->red_out, h->stream);
@@ -683,7 +685,9 @@ int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x
   return status;
 }
 
-}  // namespace
+}  // namespace sgh
+
+using namespace sgh;
 
 extern "C" {
 

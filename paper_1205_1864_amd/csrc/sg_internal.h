@@ -49,6 +49,7 @@ struct SgOpArgs {
   T* out;
   const T* a;  // [M][n_e * n_e] element coefficients of K_1..K_M
   ChaosLists<T> lists;
+  const int* active;  // if not null: the launch does nothing while *active == 0
 };
 
 // Dense per-row neighbour tables [P][M] for the strip kernel: lo[a*M + k] is the
@@ -140,8 +141,47 @@ struct PcgArgs {
   T chebB[kMaxCheb];
 };
 
+// Per-problem constants of a ragged launch (same meaning as the fields of PcgArgs).
+template <typename T>
+struct PcgConsts {
+  T c0, c1, inv_diag, inv_theta;
+  T chebA[kMaxCheb];
+  T chebB[kMaxCheb];
+};
+
+// A ragged column set: columns from several problems with their own grids.
+// Column c has nx[c] nodes per side, ntx[c] tiles per side, ntiles[c] tiles
+// whose work indices start at tbase[c] (prefix sums, nwork in total), belongs
+// to problem prob[c] (constants consts[prob], skipped while active[prob] == 0)
+// and keeps its PCG state in the n-vectors b, x, r0, r1, p0, p1, q, z.
+template <typename T>
+struct PcgCols {
+  const int* nx;
+  const int* ntx;
+  const int* ntiles;
+  const long* tbase;
+  const int* prob;
+  const T* const* b;
+  T* const* x;
+  T* const* r0;
+  T* const* r1;
+  T* const* p0;
+  T* const* p1;
+  T* const* q;
+  T* const* z;
+  const PcgConsts<T>* consts;
+  const int* active;
+  long nwork;
+};
+
 template <typename T>
 hipError_t launch_pcg(const PcgArgs<T>& args, int tile, int max_blocks, hipStream_t s);
+
+// Ragged launch over `ncols` columns described by `cols`; degree, maxit, rtol and
+// the scratch come from `args`. A regular launch whose grid fits on the device
+// at once (so it can be captured into a graph); every wait is bounded.
+template <typename T>
+hipError_t launch_pcg_ragged(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile, hipStream_t s);
 
 template <typename T>
 size_t pcg_scratch_bytes(int ncols, int ntiles);
@@ -182,6 +222,51 @@ struct ContractArgs {
 };
 void launch_contract(const ContractArgs& args, hipStream_t s);
 
+// ---- multi-problem batch: the flexible CG of many independent problems with
+// its scalars on the device, so that one outer iteration of the whole batch is
+// a fixed sequence of launches (it can be captured into a graph).
+constexpr int kBatchBlocks = 256;  // blocks per problem of the batched vector kernels
+
+struct BatchScal {
+  double fn2;        // ||f||^2
+  double rr;         // ||r||^2 after the last update
+  double pq, pr, zq;
+  double pq_prev;
+  double rtol2;      // the solve stops once rr <= rtol2 (= rtol^2 ||f||^2)
+  int it;            // outer iterations done
+  int status;        // SG_NOT_CONVERGED while iterating, then SG_OK or SG_BREAKDOWN
+  long long inner_it;  // inner PCG iterations summed over the solve
+};
+
+// Per problem b: the length N[b] = n P of its blocks and their addresses.
+struct BatchVecs {
+  int nprob;
+  const long* N;
+  double* const* x;
+  const double* const* f;
+  double* const* r;
+  double* const* z;
+  double* const* p;
+  double* const* q;
+  void* const* rw;  // residual in inner precision
+  void* const* zw;  // preconditioned residual in FP32 (FP32 inner only)
+  BatchScal* sc;
+  int* active;      // 1 while problem b iterates; every batched launch skips it otherwise
+  double* part;     // [nprob][kBatchBlocks][2]
+  long maxN;
+};
+
+void launch_batch_init(const BatchVecs& V, double rtol, hipStream_t s);
+void launch_batch_dot_zq(const BatchVecs& V, hipStream_t s);
+void launch_batch_dirupdate(const BatchVecs& V, hipStream_t s);   // p = z + beta p, beta = -zq / pq_prev
+void launch_batch_dot_pq_pr(const BatchVecs& V, hipStream_t s);
+void launch_batch_update(const BatchVecs& V, hipStream_t s);      // alpha = pr / pq; x += alpha p, r -= alpha q; test
+template <typename T>
+void launch_batch_to_inner(const BatchVecs& V, hipStream_t s);    // rw = r
+void launch_batch_from_inner(const BatchVecs& V, hipStream_t s);  // z = zw
+void launch_batch_count_iters(const int* iters, const int* prob, int ncols, BatchScal* sc, const int* pcg_status,
+                              int* sticky_status, hipStream_t s);
+
 }  // namespace sgk
 
 // Host-side context behind sg_handle.
@@ -202,6 +287,7 @@ struct sg_ctx {
   int pcg_max_blocks;
   bool march_ok;
   std::vector<sgk::MarchJob> mjobs;
+  const int* mask = nullptr;  // device flag of a batch member: SG operator launches skip while it is 0
   // host copies of the chaos lists (for counters)
   std::vector<int> lo_ptr, up_ptr;
   // device arrays inside the workspace
