@@ -3,13 +3,15 @@
 Workload (timed step): the hierarchical-Schur-preconditioned flexible CG solve
 of the 256^2 Q1 problem with M = 10 KL terms and Hermite degree p = 3
 (P = 286, 18.6M unknowns) to relative residual 1e-8, FP64 inner PCG with a
-degree-4 Jacobi-Chebyshev preconditioner stopped at 1e-4. Inputs are seeded
+degree-8 Jacobi-Chebyshev preconditioner stopped at 1e-4. Inputs are seeded
 and synthetic and resident in HBM before timing starts.
 
 Also reported (outside the timed steps): the SG matvec bandwidth (cold and
 warm Infinity Cache), the FP32-inner and mean-preconditioned solves, the
-adjoint gradient of the 512^2 differentiation case, the roofline of the
-dominant kernel, and the CPU oracle timed on a bounded sample on the host.
+adjoint gradient of the 512^2 differentiation case, the 48-problem uneven
+batch (FP32 inner / FP64 outer, graph replay) against the same problems
+solved one after another, the roofline of the dominant kernel, and the CPU
+oracle timed on a bounded sample on the host.
 
 Prints one JSON line.
 """
@@ -57,6 +59,55 @@ def time_matvec(solver, U, Y, reps, cold, flush=None):
         e1.synchronize()
         times.append(e0.elapsed_time(e1))
     return float(np.median(times)), times
+
+
+def bench_batch(degree, count=48, seed=0):
+    """The uneven batch solved together (graph replay) and one problem after another."""
+    import torch
+    from paper_1205_1864_amd.binding import Options, SGBatch, SGSolver, to_device_block
+    from sg_inputs import batch_problems
+    probs = batch_problems(seed=seed, count=count)
+    opts = Options(inner_precision=32, cheb_degree=degree, precond="hsc", inner_maxit=2000)
+    log(f"batch: {count} problems, {sum(p.n * p.P for p in probs) / 1e6:.1f}M unknowns")
+    batch = SGBatch(probs, opts)
+    F = [to_device_block(p.load_block()) for p in probs]
+    U = batch.empty()
+    batch.sg_batch_solve(F, U, rtol=1e-8, maxit=100)  # warm-up; captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st, info = batch.sg_batch_solve(F, U, rtol=1e-8, maxit=100)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batch: {t_batch:.3f} s ({count / t_batch:.2f} solves/s), rc {info['rc']}")
+    batch.close()
+    del batch
+    torch.cuda.empty_cache()
+    # the same problems one after another (setup not timed)
+    t_seq, diffs, seq_outer = 0.0, [], []
+    for i, pr in enumerate(probs):
+        sv = SGSolver(pr, opts)
+        Us = sv.empty()
+        if i == 0:
+            sv.sg_solve(F[i], Us, rtol=1e-8, maxit=100)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, ss = sv.sg_solve(F[i], Us, rtol=1e-8, maxit=100)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t1
+        diffs.append(float(torch.linalg.norm(U[i] - Us) / torch.linalg.norm(Us)))
+        seq_outer.append(ss["outer_it"])
+        sv.close()
+        del sv, Us
+    log(f"sequential: {t_seq:.3f} s ({count / t_seq:.2f} solves/s)")
+    return {
+        "batch_count": count, "batch_unknowns": int(sum(p.n * p.P for p in probs)),
+        "batch_s": t_batch, "batch_solves_per_s": count / t_batch,
+        "batch_sequential_s": t_seq, "batch_sequential_solves_per_s": count / t_seq,
+        "batch_speedup_vs_sequential": t_seq / t_batch, "batch_rc": info["rc"],
+        "batch_outer_it": [s["outer_it"] for s in st], "batch_sequential_outer_it": seq_outer,
+        "batch_max_true_relres": max(s["true_relres"] for s in st),
+        "batch_max_rel_diff_vs_sequential": max(diffs),
+    }
 
 
 def cpu_baseline(prob, outer_its, budget_s=30.0):
@@ -205,6 +256,10 @@ def main():
         del sg_, Ug, Fg
         torch.cuda.empty_cache()
 
+        # multi-problem batch: 48 seeded uneven problems, FP32 inner / FP64 outer
+        extra.update(bench_batch(CHEB_DEGREE))
+        torch.cuda.empty_cache()
+
     achieved = bytes_inner / (ms_inner * 1e-3) / 1e9 if ms_inner > 0 else 0.0
     roofline = {
         "kernel": "pcg_kernel (persistent batched inner PCG, all launches of the timed solves)",
@@ -214,7 +269,7 @@ def main():
         "alg_bytes_per_launch": bytes_inner / max(1, launches),
     }
     roofline_mv = {
-        "kernel": "sgop_kernel<double> (SG matvec)", "bound": "hbm", "achieved": mv_cold, "peak": HBM_PEAK_GBS,
+        "kernel": "sgop_march_kernel<double> (SG matvec)", "bound": "hbm", "achieved": mv_cold, "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": mv_cold / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": cold_ms,
         "alg_bytes_per_launch": alg_bytes_mv,
     }

@@ -125,3 +125,26 @@ def test_batch_not_converged_and_rejection():
     assert all(st["outer_it"] == 1 and st["status"] == b.SG_NOT_CONVERGED for st in stats)
     with pytest.raises(b.SGError):
         b.SGBatch(probs, b.Options(precond="none"))
+
+
+@pytest.mark.timeout(600)
+def test_batch_full_recipe_members_against_oracle():
+    """The 48-problem uneven recipe (grids 32^2..256^2, P <= 495, FP32 inner / FP64 outer)
+    in one batch: every member converges, and the members small enough for a direct
+    solve agree with the oracle within the bound of the stopping test."""
+    b = _b()
+    probs = batch_problems(seed=0, count=48)
+    batch = b.SGBatch(probs, b.Options(inner_precision=32, cheb_degree=8, inner_rtol=1e-4, inner_maxit=2000))
+    F = [b.to_device_block(pr.load_block()) for pr in probs]
+    U, stats, info = batch.sg_batch_solve(F, rtol=1e-8, maxit=100)
+    assert info["rc"] == 0
+    assert all(st["status"] == 0 and st["true_relres"] <= 1.05e-8 for st in stats)
+    small = sorted(range(len(probs)), key=lambda i: probs[i].n * probs[i].P)[:4]
+    for i in small:
+        pr = probs[i]
+        s = sg.build_system(pr)
+        Fh = pr.load_block()
+        Ud = solve.solve_direct(s, Fh.T.copy())
+        err = np.linalg.norm(U[i].cpu().numpy().T - Ud) / np.linalg.norm(Ud)
+        # ||u - u*|| / ||u*|| <= kappa(A) ||r|| / ||f||; kappa(A) <= 4 for these coefficient margins
+        assert err <= 4.0 * 1.05e-8, (i, err)
