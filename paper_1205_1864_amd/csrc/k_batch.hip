@@ -226,11 +226,60 @@ __global__ void __launch_bounds__(kThreads) from_inner_kernel(const BatchVecs V)
 
 // Adds the inner iteration counts of a ragged PCG launch to their problems and
 // keeps a sticky copy of the launch's wait status.
-__global__ void count_iters_kernel(const int* iters, const int* prob, int ncols, BatchScal* sc, const int* pcg_status,
-                                   int* sticky) {
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncols; c += gridDim.x * blockDim.x)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&sc[prob[c]].inner_it), (unsigned long long)iters[c]);
+// Adds the inner iteration counts of a ragged PCG launch (over the listed
+// columns) to their problems and keeps a sticky copy of the wait status.
+__global__ void count_iters_kernel(const int* iters, const int* act, const int* nact, const int* prob, BatchScal* sc,
+                                   const int* pcg_status, int* sticky) {
+  const int n = *nact;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&sc[prob[act[i]]].inner_it), (unsigned long long)iters[i]);
   if (blockIdx.x == 0 && threadIdx.x == 0 && *pcg_status != 0) *sticky = 1;
+}
+
+// One block: order-preserving list of the columns whose problem is active and
+// the exclusive prefix sums of their tile counts.
+__global__ void __launch_bounds__(1024) compact_kernel(const int* prob, const int* ntiles, int ncols,
+                                                       const int* active, int* act, int* nact, long* cbase,
+                                                       long* nwork_act) {
+  __shared__ int cnt[1024];
+  __shared__ long tiles[1024];
+  const int per = (ncols + 1023) / 1024;
+  const int c0 = threadIdx.x * per;
+  const int c1 = min(ncols, c0 + per);
+  int k = 0;
+  long t = 0;
+  for (int c = c0; c < c1; ++c)
+    if (active[prob[c]]) {
+      ++k;
+      t += ntiles[c];
+    }
+  cnt[threadIdx.x] = k;
+  tiles[threadIdx.x] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int rk = 0;
+    long rt = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int vk = cnt[i];
+      const long vt = tiles[i];
+      cnt[i] = rk;
+      tiles[i] = rt;
+      rk += vk;
+      rt += vt;
+    }
+    *nact = rk;
+    *nwork_act = rt;
+  }
+  __syncthreads();
+  int pos = cnt[threadIdx.x];
+  long base = tiles[threadIdx.x];
+  for (int c = c0; c < c1; ++c)
+    if (active[prob[c]]) {
+      act[pos] = c;
+      cbase[pos] = base;
+      ++pos;
+      base += ntiles[c];
+    }
 }
 
 dim3 vec_grid(const BatchVecs& V) {
@@ -280,12 +329,19 @@ void launch_batch_from_inner(const BatchVecs& V, hipStream_t s) {
   hipLaunchKernelGGL(from_inner_kernel, vec_grid(V), dim3(kThreads), 0, s, V);
 }
 
-void launch_batch_count_iters(const int* iters, const int* prob, int ncols, BatchScal* sc, const int* pcg_status,
-                              int* sticky_status, hipStream_t s) {
+void launch_batch_count_iters(const int* iters, const int* act, const int* nact, const int* prob, int ncols,
+                              BatchScal* sc, const int* pcg_status, int* sticky_status, hipStream_t s) {
   if (ncols <= 0) return;
   const int blocks = (ncols + 255) / 256 < 64 ? (ncols + 255) / 256 : 64;
-  hipLaunchKernelGGL(count_iters_kernel, dim3(blocks), dim3(256), 0, s, iters, prob, ncols, sc, pcg_status,
+  hipLaunchKernelGGL(count_iters_kernel, dim3(blocks), dim3(256), 0, s, iters, act, nact, prob, sc, pcg_status,
                      sticky_status);
+}
+
+void launch_batch_compact(const int* prob, const int* ntiles, int ncols, const int* active, int* act, int* nact,
+                          long* cbase, long* nwork_act, hipStream_t s) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, prob, ntiles, ncols, active, act, nact, cbase,
+                     nwork_act);
 }
 
 }  // namespace sgk

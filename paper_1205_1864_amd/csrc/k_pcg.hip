@@ -98,7 +98,7 @@ struct Interior {
 template <typename T>
 struct ColView {
   int nx, ntx, ntiles;
-  long tbase;
+  long tbase;  // first index of the column's per-tile partials (and of its work items)
   const T* b;
   T *x, *r0, *r1, *p0, *p1, *q, *z;
   T c0, c1, inv_diag, inv_theta;
@@ -198,28 +198,33 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
   __shared__ double s4[4];
   __shared__ int sflag;
 
-  const int ncols = A.ncols;
-  const long nwork = RAGGED ? C.nwork : (long)ncols * A.ntiles;
+  // a compacted ragged launch covers the listed columns only; scratch is indexed by list position
+  const bool listed = RAGGED && C.act != nullptr;
+  const int ncols = listed ? ld_uniform(C.nact, 0) : A.ncols;
+  const long nslots = RAGGED ? C.nwork : (long)A.ncols * A.ntiles;  // stride of the partial arrays
+  const long nwork = listed ? ld_uniform(C.nwork_act, 0) : nslots;
+  if (ncols <= 0 || nwork <= 0) return;
   double* part = A.sc.part;
   unsigned* arr = A.sc.arrivals;
-  auto P = [&](int which) { return part + (long)which * nwork; };
+  auto P = [&](int which) { return part + (long)which * nslots; };
   // the grid, vectors and constants of column c
   auto view = [&](int c) {
     ColView<T> v;
     if constexpr (RAGGED) {
-      v.nx = ld_uniform(C.nx, c);
-      v.ntx = ld_uniform(C.ntx, c);
-      v.ntiles = ld_uniform(C.ntiles, c);
-      v.tbase = ld_uniform(C.tbase, c);
-      v.b = ld_uniform(C.b, c);
-      v.x = ld_uniform(C.x, c);
-      v.r0 = ld_uniform(C.r0, c);
-      v.r1 = ld_uniform(C.r1, c);
-      v.p0 = ld_uniform(C.p0, c);
-      v.p1 = ld_uniform(C.p1, c);
-      v.q = ld_uniform(C.q, c);
-      v.z = ld_uniform(C.z, c);
-      const PcgConsts<T>* k = C.consts + ld_uniform(C.prob, c);
+      const int o = listed ? ld_uniform(C.act, c) : c;  // index into the column arrays
+      v.nx = ld_uniform(C.nx, o);
+      v.ntx = ld_uniform(C.ntx, o);
+      v.ntiles = ld_uniform(C.ntiles, o);
+      v.tbase = listed ? ld_uniform(C.cbase, c) : ld_uniform(C.tbase, o);
+      v.b = ld_uniform(C.b, o);
+      v.x = ld_uniform(C.x, o);
+      v.r0 = ld_uniform(C.r0, o);
+      v.r1 = ld_uniform(C.r1, o);
+      v.p0 = ld_uniform(C.p0, o);
+      v.p1 = ld_uniform(C.p1, o);
+      v.q = ld_uniform(C.q, o);
+      v.z = ld_uniform(C.z, o);
+      const PcgConsts<T>* k = C.consts + ld_uniform(C.prob, o);
       v.c0 = ld_uniform(&k->c0, 0);
       v.c1 = ld_uniform(&k->c1, 0);
       v.inv_diag = ld_uniform(&k->inv_diag, 0);
@@ -252,10 +257,11 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
   // column holding work index w
   auto column_of = [&](long w) {
     if constexpr (RAGGED) {
+      const long* base = listed ? C.cbase : C.tbase;
       int lo = 0, hi = ncols - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (ld_uniform(C.tbase, mid) <= w) lo = mid; else hi = mid - 1;
+        if (ld_uniform(base, mid) <= w) lo = mid; else hi = mid - 1;
       }
       return lo;
     } else {
@@ -267,6 +273,7 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
   const long w_end = w_begin + per_block < nwork ? w_begin + per_block : nwork;
   if (w_begin >= w_end) return;
   const int c_first = column_of(w_begin), c_last = column_of(w_end - 1);
+  // tiles of the column that fall in this block's range [w_begin, w_end)
   auto tiles_of = [&](const ColView<T>& v, int& t0, int& t1) {
     const long lo = v.tbase > w_begin ? v.tbase : w_begin;
     const long hi = v.tbase + v.ntiles < w_end ? v.tbase + v.ntiles : w_end;
@@ -293,7 +300,9 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
   };
   for (int c = c_first + (int)threadIdx.x; c <= c_last; c += kGroup * G) {
     int skip = 0;
-    if constexpr (RAGGED) skip = C.active[C.prob[c]] == 0;
+    if constexpr (RAGGED) {
+      if (!listed) skip = C.active[C.prob[c]] == 0;
+    }
     sdone[c - c_first] = skip;
   }
   __syncthreads();
@@ -309,6 +318,7 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
     }
     int t0, t1;
     tiles_of(v, t0, t1);
+    if (t1 <= t0) continue;
     const int nx = v.nx;
     for (int tb = t0; tb < t1; tb += G) {
       const int t = tb + grp;
@@ -348,6 +358,9 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
     for (int c = c_first; c <= c_last && !aborted; ++c) {
       if (sdone[c - c_first]) continue;
       const ColView<T> v = view(c);
+      int t0, t1;
+      tiles_of(v, t0, t1);
+      if (t1 <= t0) continue;
       if (!column_wait(arr + c, (unsigned)((1 + 2 * it) * v.ntiles), A.sc.status, &sflag)) {
         aborted = true;
         break;
@@ -367,8 +380,6 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
       }
       const T beta = it == 0 ? T(0) : (T)(s4[2] / s4[3]);
       any_active = true;
-      int t0, t1;
-      tiles_of(v, t0, t1);
       const int nx = v.nx;
       const T* zc = v.z;
       const T* po = par ? v.p0 : v.p1;
@@ -421,6 +432,9 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
     for (int c = c_first; c <= c_last && !aborted; ++c) {
       if (sdone[c - c_first]) continue;
       const ColView<T> v = view(c);
+      int t0, t1;
+      tiles_of(v, t0, t1);
+      if (t1 <= t0) continue;
       if (!column_wait(arr + c, (unsigned)((2 + 2 * it) * v.ntiles), A.sc.status, &sflag)) {
         aborted = true;
         break;
@@ -438,8 +452,6 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
         continue;
       }
       const T alpha = (T)(gam / pq);
-      int t0, t1;
-      tiles_of(v, t0, t1);
       const int nx = v.nx;
       const T* pc = par ? v.p1 : v.p0;
       const T* qc = v.q;

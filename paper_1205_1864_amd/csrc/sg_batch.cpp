@@ -96,8 +96,9 @@ struct BatchPlan {
 };
 
 size_t set_stride(long ncols) {
-  // nx, ntx, ntiles, prob (int) + tbase (long) + eight pointers, per column
-  return (size_t)ncols * (4 * sizeof(int) + sizeof(long) + 8 * sizeof(void*)) + 16 * 256;
+  // per column: nx, ntx, ntiles, prob, list entry (int), tbase, list base (long) and eight
+  // pointers; plus the two list totals and the alignment of the 17 arrays
+  return (size_t)ncols * (5 * sizeof(int) + 2 * sizeof(long) + 8 * sizeof(void*)) + 20 * 256;
 }
 
 int make_batch_plan(int count, const sg_problem* probs, const sg_opts* op, BatchPlan& bp) {
@@ -215,6 +216,13 @@ int build_set(sg_batch_ctx* B, int s, char* base, std::vector<char>& host, sgk::
   cols.q = (T* const*)put(pq.data(), sizeof(void*) * nc);
   cols.z = (T* const*)put(pz.data(), sizeof(void*) * nc);
   cols.nwork = w;
+  // list of the active columns, rebuilt on the device before every launch
+  const std::vector<int> zero_i(nc + 1, 0);
+  const std::vector<long> zero_l(nc + 1, 0);
+  cols.act = (const int*)put(zero_i.data(), sizeof(int) * nc);
+  cols.nact = (const int*)put(zero_i.data(), sizeof(int));
+  cols.cbase = (const long*)put(zero_l.data(), sizeof(long) * nc);
+  cols.nwork_act = (const long*)put(zero_l.data(), sizeof(long));
   B->set_ncols[s] = (int)nc;
   if (L.total > set_stride((long)nc)) return fail(SG_EINVAL, "internal: column set larger than planned");
   return SG_OK;
@@ -237,9 +245,14 @@ int run_set(sg_batch_ctx* B, int s) {
   a.maxit = B->opts.inner_maxit;
   a.rtol = B->opts.inner_rtol > 0.0 ? B->opts.inner_rtol : 0.0;
   a.sc = B->sc;
-  SG_HIP(sgk::launch_pcg_ragged<T>(a, sets<T>(B)[s], B->tile, B->stream));
-  sgk::launch_batch_count_iters(B->sc.iters, sets<T>(B)[s].prob, ncols, B->V.sc, B->sc.status, B->sticky,
-                                B->stream);
+  const sgk::PcgCols<T>& cols = sets<T>(B)[s];
+  // only the columns of problems that still iterate take part in the launch
+  sgk::launch_batch_compact(cols.prob, cols.ntiles, ncols, B->V.active, const_cast<int*>(cols.act),
+                            const_cast<int*>(cols.nact), const_cast<long*>(cols.cbase),
+                            const_cast<long*>(cols.nwork_act), B->stream);
+  SG_HIP(sgk::launch_pcg_ragged<T>(a, cols, B->tile, B->stream));
+  sgk::launch_batch_count_iters(B->sc.iters, cols.act, cols.nact, cols.prob, ncols, B->V.sc, B->sc.status,
+                                B->sticky, B->stream);
   return SG_OK;
 }
 

@@ -172,6 +172,14 @@ struct PcgCols {
   const PcgConsts<T>* consts;
   const int* active;
   long nwork;
+  // Optional compaction: if act is not null, the launch covers only the
+  // columns act[0 .. *nact - 1] (indices into the arrays above, in order);
+  // their per-tile partials start at cbase[i] (prefix sums over the listed
+  // columns, *nwork_act in total). Scratch arrays are indexed by list position.
+  const int* act;
+  const int* nact;
+  const long* cbase;
+  const long* nwork_act;
 };
 
 template <typename T>
@@ -264,8 +272,12 @@ void launch_batch_update(const BatchVecs& V, hipStream_t s);      // alpha = pr 
 template <typename T>
 void launch_batch_to_inner(const BatchVecs& V, hipStream_t s);    // rw = r
 void launch_batch_from_inner(const BatchVecs& V, hipStream_t s);  // z = zw
-void launch_batch_count_iters(const int* iters, const int* prob, int ncols, BatchScal* sc, const int* pcg_status,
-                              int* sticky_status, hipStream_t s);
+void launch_batch_count_iters(const int* iters, const int* act, const int* nact, const int* prob, int ncols,
+                              BatchScal* sc, const int* pcg_status, int* sticky_status, hipStream_t s);
+// List of the columns of a ragged set whose problem is still active, with the
+// prefix sums of their tile counts (the partial slots of the next launch).
+void launch_batch_compact(const int* prob, const int* ntiles, int ncols, const int* active, int* act, int* nact,
+                          long* cbase, long* nwork_act, hipStream_t s);
 
 }  // namespace sgk
 
