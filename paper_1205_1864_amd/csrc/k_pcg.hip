@@ -568,7 +568,7 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
   const int H = args.degree - 1;
   if (tile == 32) {
     if (H <= 3) return launch_cfg<T, 32, slots(32, 3), 4, RAGGED>(args, cols, max_blocks, s);
-    if (H <= 7) return launch_cfg<T, 32, slots(32, 7), 2, RAGGED>(args, cols, max_blocks, s);
+    if (H <= 7) return launch_cfg<T, 32, slots(32, 7), 3, RAGGED>(args, cols, max_blocks, s);
   }
   return launch_cfg<T, 16, slots(16, 15), 4, RAGGED>(args, cols, max_blocks, s);
 }
