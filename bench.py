@@ -32,6 +32,12 @@ import numpy as np  # noqa: E402
 METRIC = "SG solve s to relres 1e-8 + matvec HBM GB/s (256², M=10, p=3); adjoint grad s"
 HBM_PEAK_GBS = 8000.0
 CHEB_DEGREE = 8  # updates of the Chebyshev preconditioner of the inner PCG
+# HBM bytes per launch measured with separate FETCH_SIZE and WRITE_SIZE counter
+# runs of this benchmark, scaled by the same counters of a 512 MiB elementwise
+# kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Set to None when the
+# kernel changes.
+PCG_TRAFFIC_BYTES = 26.56e9     # pcg_kernel<double, 32, 9, 3>, average over the launches of a solve
+MATVEC_TRAFFIC_BYTES = 544.3e6  # sgop_march_kernel<double, 10>, one SG matvec
 
 
 def log(msg):
@@ -192,7 +198,7 @@ def main():
     time_matvec(solver, Ur, Yr, 5, cold=False)
     warm_ms, _ = time_matvec(solver, Ur, Yr, 50, cold=False)
     flush = torch.zeros(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
-    cold_ms, _ = time_matvec(solver, Ur, Yr, 30, cold=True, flush=flush)
+    cold_ms, _ = time_matvec(solver, Ur, Yr, 50, cold=True, flush=flush)
     del flush
     log(f"matvec cold {cold_ms:.3f} ms warm {warm_ms:.3f} ms")
     mv_cold = alg_bytes_mv / (cold_ms * 1e-3) / 1e9
@@ -264,13 +270,14 @@ def main():
     roofline = {
         "kernel": "pcg_kernel (persistent batched inner PCG, all launches of the timed solves)",
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "frac": achieved / HBM_PEAK_GBS, "traffic": PCG_TRAFFIC_BYTES, "traffic_unit": "bytes per launch",
         "avg_launch_ms": ms_inner / max(1, launches), "launches": launches,
         "alg_bytes_per_launch": bytes_inner / max(1, launches),
     }
     roofline_mv = {
         "kernel": "sgop_march_kernel<double> (SG matvec)", "bound": "hbm", "achieved": mv_cold, "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": mv_cold / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": cold_ms,
+        "unit": "GB/s", "frac": mv_cold / HBM_PEAK_GBS, "traffic": MATVEC_TRAFFIC_BYTES,
+        "traffic_unit": "bytes per launch", "avg_launch_ms": cold_ms,
         "alg_bytes_per_launch": alg_bytes_mv,
     }
     out = {
