@@ -170,6 +170,8 @@ def main():
     F = to_device_block(prob.load_block())
     opts64 = Options(inner_precision=64, cheb_degree=CHEB_DEGREE, inner_maxit=2000, precond="hsc", inner_rtol=1e-4)
     solver = SGSolver(prob, opts64)
+    schedule = solver.sg_autotune(3)  # not timed: picks the launch schedules for this problem
+    log(f"autotune: {schedule}")
     U = solver.empty()
 
     # ---- timed steps: the HSC-FCG solve
@@ -220,6 +222,7 @@ def main():
                          ("mean_fp64", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000)),
                          ("mean_fp32", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000))]:
             sv = SGSolver(prob, o)
+            sv.sg_autotune(3)
             Uv = sv.empty()
             sv.sg_solve(F, Uv, rtol=1e-8, maxit=200)
             torch.cuda.synchronize()
@@ -244,6 +247,7 @@ def main():
         # adjoint gradient, 512^2, M = 8, p = 3
         pg = named_problem("grad")
         sg_ = SGSolver(pg, Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="hsc", inner_maxit=2000))
+        sg_.sg_autotune(3)
         Fg = to_device_block(pg.load_block())
         wm, wv = qoi_weights(pg.n_e)
         wm_d, wv_d = to_device_vec(wm), to_device_vec(wv)
@@ -267,16 +271,21 @@ def main():
         torch.cuda.empty_cache()
 
     achieved = bytes_inner / (ms_inner * 1e-3) / 1e9 if ms_inner > 0 else 0.0
+    # the counter traffic belongs to the schedules it was measured with
+    pcg_traffic = PCG_TRAFFIC_BYTES if (schedule["pcg_tile"], schedule["pcg_max_blocks"]) == (32, 0) else None
+    mv_traffic = MATVEC_TRAFFIC_BYTES if (schedule["mv_variant"], schedule["mv_param"]) == (2, 0) else None
+    mv_kernel = {2: "sgop_march_kernel<double>", 1: "sgop_strip_dyn_kernel<double>",
+                 0: "sgop_strip_kernel<double>"}[schedule["mv_variant"]]
     roofline = {
         "kernel": "pcg_kernel (persistent batched inner PCG, all launches of the timed solves)",
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": PCG_TRAFFIC_BYTES, "traffic_unit": "bytes per launch",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": pcg_traffic, "traffic_unit": "bytes per launch",
         "avg_launch_ms": ms_inner / max(1, launches), "launches": launches,
         "alg_bytes_per_launch": bytes_inner / max(1, launches),
     }
     roofline_mv = {
-        "kernel": "sgop_march_kernel<double> (SG matvec)", "bound": "hbm", "achieved": mv_cold, "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": mv_cold / HBM_PEAK_GBS, "traffic": MATVEC_TRAFFIC_BYTES,
+        "kernel": f"{mv_kernel} (SG matvec)", "bound": "hbm", "achieved": mv_cold, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": mv_cold / HBM_PEAK_GBS, "traffic": mv_traffic,
         "traffic_unit": "bytes per launch", "avg_launch_ms": cold_ms,
         "alg_bytes_per_launch": alg_bytes_mv,
     }
@@ -286,7 +295,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "HSC-FCG solve, 256^2 Q1, M=10, p=3 (P=286, 18.6M unknowns), "
                                f"FP64 inner PCG Jacobi-Chebyshev d={CHEB_DEGREE} to 1e-4, outer to 1e-8",
-                   "cheb_degree": CHEB_DEGREE, "n_e": prob.n_e, "M": prob.M, "p": prob.p, "P": prob.P, "sigma": prob.sigma, "L": prob.L},
+                   "cheb_degree": CHEB_DEGREE, "schedule": schedule, "n_e": prob.n_e, "M": prob.M, "p": prob.p, "P": prob.P, "sigma": prob.sigma, "L": prob.L},
         "roofline": roofline, "roofline_matvec": roofline_mv, "extra": extra,
     }
     if not args.no_cpu:

@@ -188,6 +188,32 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
                     double rtol, int32_t maxit, double* Q, double* grad, double* Lambda,
                     sg_stats* stats);
 
+/* Schedule autotuner. Times candidate launch schedules on this handle's own
+ * grid and chaos sizes and keeps the fastest for all later calls:
+ *   flags bit 0: the SG operator (y-marching kernel with 1, 2 or 4 grid
+ *                segments per XCD or the automatic count; band kernels with
+ *                32..128 row chunks per band, where the grid shape allows them);
+ *   flags bit 1: the inner PCG (tile edge 16 or 32 where the Chebyshev halo
+ *                allows 32; block count automatic or half the CUs), timed on
+ *                the columns of the largest chaos level with a constant
+ *                right-hand side.
+ * Runs on the handle's stream inside its workspace (the FCG vectors and the
+ * inner solver's state are overwritten) and synchronises it. The schedules
+ * differ only in the order of floating-point sums. report (host, may be NULL)
+ * receives the choice. */
+typedef struct sg_tune_report {
+  int32_t mv_variant;      /* 0, 1: band kernels; 2: y-marching kernel */
+  int32_t mv_param;        /* row chunks per band (variants 0, 1) or segments per XCD (2; 0 = automatic) */
+  int32_t pcg_tile;        /* inner tile edge */
+  int32_t pcg_max_blocks;  /* cap on the blocks of an inner launch (0 = as many as fit) */
+  double mv_ms;            /* median time of one SG matvec with the chosen schedule */
+  double pcg_ms;           /* time of the inner test solve with the chosen schedule */
+  int32_t candidates;      /* schedules timed */
+  int32_t reserved;
+} sg_tune_report;
+
+int sg_autotune(sg_handle h, int32_t flags, sg_tune_report* report);
+
 /* Release the handle (the workspace stays with the caller). */
 void sg_destroy(sg_handle h);
 

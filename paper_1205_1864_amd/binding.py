@@ -52,6 +52,15 @@ class SgStats(ctypes.Structure):
         return d
 
 
+class SgTuneReport(ctypes.Structure):
+    _fields_ = [("mv_variant", ctypes.c_int32), ("mv_param", ctypes.c_int32), ("pcg_tile", ctypes.c_int32),
+                ("pcg_max_blocks", ctypes.c_int32), ("mv_ms", ctypes.c_double), ("pcg_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
@@ -70,6 +79,7 @@ def _load():
         "sg_solve": [VP, VP, VP, D, I32, I32, P(SgStats)],
         "sg_qoi": [VP, VP, VP, VP, P(D)],
         "sg_adjoint_grad": [VP, VP, VP, VP, D, I32, P(D), P(D), VP, P(SgStats)],
+        "sg_autotune": [VP, I32, P(SgTuneReport)],
         "sg_batch_workspace_bytes": [I32, P(SgProblem), P(SgOpts), P(ctypes.c_size_t)],
         "sg_batch_setup": [I32, P(SgProblem), P(SgOpts), VP, ctypes.c_size_t, VP, P(VP)],
         "sg_batch_sizes": [VP, I32, P(I64), P(I32)],
@@ -247,6 +257,11 @@ class SGSolver:
         d = st.as_dict()
         d["rc"] = rc
         return Q.value, np.array(grad[:]), d
+
+    def sg_autotune(self, flags=3):
+        rep = SgTuneReport()
+        _check(lib.sg_autotune(self.handle, int(flags), ctypes.byref(rep)))
+        return rep.as_dict()
 
     def close(self):
         if getattr(self, "handle", None):

@@ -201,7 +201,7 @@ struct HostMarchJob {
 
 void build_march_job(int M, int nx, const std::vector<int>& rows, bool lower, bool upper,
                      const std::vector<int>& st_lo, const std::vector<int>& st_up,
-                     const std::vector<double>& st_glo, long cap_blocks, HostMarchJob& J) {
+                     const std::vector<double>& st_glo, long cap_blocks, int seg_per_xcd, HostMarchJob& J) {
   const int RGU = sgk::kMarchRGU, RGL = sgk::kMarchRGL, NS = sgk::kMarchNS;
   std::vector<int> ru, rl;
   for (int r : rows) {
@@ -256,9 +256,70 @@ void build_march_job(int M, int nx, const std::vector<int>& rows, bool lower, bo
   }
   if (!grp.empty()) close(1, grp, slots);
   const long ng = std::max<long>(1, (long)J.kind.size());
-  const long spx = std::max<long>(1, std::min<long>(nx / 64, cap_blocks / (8 * ng)));
+  // segments per XCD: as many as one resident wave of blocks allows (or the requested
+  // number), each at least 8 node rows tall
+  long spx = seg_per_xcd > 0 ? seg_per_xcd : std::min<long>(nx / 64, cap_blocks / (8 * ng));
+  spx = std::max<long>(1, std::min<long>(spx, nx / 64 > 0 ? nx / 64 : 1));
   J.nseg = (int)(8 * spx);
   J.seg_rows = (nx + J.nseg - 1) / J.nseg;
+}
+
+// Row groups of the y-marching SG operator for every use: job 0 is the matvec,
+// job 1 + 2 (l - 1) + dir the coupling product of level l in direction dir.
+// seg_per_xcd = 0 chooses the number of grid segments per XCD automatically.
+int build_march_jobs(sg_ctx* h, int seg_per_xcd) {
+  h->march_ok = false;
+  h->mjobs.clear();
+  if (!sgk::march_supported(h->n_e, h->M) || h->mv_variant != 2) return SG_OK;
+  const int occ = sgk::march_blocks_per_cu(h->M, h->n_e);
+  if (occ <= 0) return SG_OK;
+  const long cap = (long)occ * h->num_cu;
+  const int M = h->M, P = h->P;
+  std::vector<HostMarchJob> jobs(1 + 2 * h->p);
+  std::vector<int> all(P);
+  for (int a = 0; a < P; ++a) all[a] = a;
+  build_march_job(M, h->nx, all, true, true, h->st_lo_h, h->st_up_h, h->st_glo_h, cap, seg_per_xcd, jobs[0]);
+  for (int l = 1; l <= h->p; ++l)
+    for (int dir = 0; dir < 2; ++dir) {
+      const int rl = dir == 0 ? l - 1 : l;
+      std::vector<int> rows;
+      for (int a = h->off[rl]; a < h->off[rl + 1]; ++a) rows.push_back(a);
+      build_march_job(M, h->nx, rows, dir == 1, dir == 0, h->st_lo_h, h->st_up_h, h->st_glo_h, cap, seg_per_xcd,
+                      jobs[1 + 2 * (l - 1) + dir]);
+    }
+  std::vector<int> ptr, rws, knd, lk, lcol;
+  std::vector<double> lw;
+  for (const HostMarchJob& J : jobs) {
+    sgk::MarchJob mj{};
+    mj.gptr = h->mj_ptr_d + ptr.size();
+    mj.grows = h->mj_rows_d;
+    mj.gkind = h->mj_kind_d + knd.size();
+    mj.lk = h->mj_lk_d + lk.size();
+    mj.lcol = h->mj_lcol_d + lcol.size();
+    mj.lw = h->mj_lw_d + lw.size();
+    mj.ngroups = (int)J.kind.size();
+    mj.nseg = J.nseg;
+    mj.seg_rows = J.seg_rows;
+    h->mjobs.push_back(mj);
+    const int base = (int)rws.size();
+    for (int v : J.ptr) ptr.push_back(base + v);
+    rws.insert(rws.end(), J.rows.begin(), J.rows.end());
+    knd.insert(knd.end(), J.kind.begin(), J.kind.end());
+    lk.insert(lk.end(), J.lk.begin(), J.lk.end());
+    lcol.insert(lcol.end(), J.lcol.begin(), J.lcol.end());
+    lw.insert(lw.end(), J.lw.begin(), J.lw.end());
+  }
+  hipStream_t s = h->stream;
+  SG_HIP(hipMemcpyAsync(h->mj_ptr_d, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice, s));
+  SG_HIP(hipMemcpyAsync(h->mj_rows_d, rws.data(), sizeof(int) * rws.size(), hipMemcpyHostToDevice, s));
+  SG_HIP(hipMemcpyAsync(h->mj_kind_d, knd.data(), sizeof(int) * knd.size(), hipMemcpyHostToDevice, s));
+  SG_HIP(hipMemcpyAsync(h->mj_lk_d, lk.data(), sizeof(int) * lk.size(), hipMemcpyHostToDevice, s));
+  SG_HIP(hipMemcpyAsync(h->mj_lcol_d, lcol.data(), sizeof(int) * lcol.size(), hipMemcpyHostToDevice, s));
+  SG_HIP(hipMemcpyAsync(h->mj_lw_d, lw.data(), sizeof(double) * lw.size(), hipMemcpyHostToDevice, s));
+  SG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  h->march_ok = true;
+  h->mv_seg_per_xcd = seg_per_xcd;
+  return SG_OK;
 }
 
 // Spectrum of D^-1 K_0 for the Q1 stencil: (8 - 2 c_i - 2 c_j - 4 c_i c_j) / 8, c_i = cos(i pi / n_e).
@@ -685,6 +746,110 @@ int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x
   return status;
 }
 
+// Schedule autotuner (sg_autotune).
+int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
+  sg_tune_report R{};
+  const long N = h->n * (long)h->P;
+  hipStream_t s = h->stream;
+  auto event_ms = [&](const std::function<void()>& body, int reps, double* med) -> int {
+    std::vector<float> t;
+    for (int r = 0; r < reps; ++r) {
+      SG_HIP(hipEventRecord(h->ev0, s));
+      body();
+      SG_HIP(hipEventRecord(h->ev1, s));
+      SG_HIP(hipEventSynchronize(h->ev1));
+      float ms = 0.f;
+      SG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    *med = t[t.size() / 2];
+    return SG_OK;
+  };
+  if (flags & 1) {
+    sgk::launch_fill(h->pv, 1.0, N, s);
+    struct Cand {
+      int variant, param;
+    };
+    std::vector<Cand> cands;
+    const bool wide = h->n_e % 64 == 0 && h->n_e >= 64 && h->n_e <= 512;
+    if (sgk::march_supported(h->n_e, h->M))
+      for (int spx : {0, 1, 2, 4}) cands.push_back({2, spx});
+    if (wide) {
+      for (int bpb : {32, 64, 128}) cands.push_back({1, bpb});
+      if (h->M <= 12)
+        for (int bpb : {64, 128}) cands.push_back({0, bpb});
+    }
+    auto apply = [&](const Cand& c) -> int {
+      h->mv_variant = c.variant;
+      h->mv_blocks_per_band = c.variant == 2 ? 0 : c.param;
+      return build_march_jobs(h, c.variant == 2 ? c.param : 0);
+    };
+    double best = 1e300;
+    Cand pick{h->mv_variant, h->mv_variant == 2 ? h->mv_seg_per_xcd : h->mv_blocks_per_band};
+    for (const Cand& c : cands) {
+      int rc = apply(c);
+      if (rc) return rc;
+      matvec(h, h->pv, h->q);
+      matvec(h, h->pv, h->q);
+      double med = 0.0;
+      rc = event_ms([&] { matvec(h, h->pv, h->q); }, 5, &med);
+      if (rc) return rc;
+      ++R.candidates;
+      if (med < best) {
+        best = med;
+        pick = c;
+      }
+    }
+    int rc = apply(pick);
+    if (rc) return rc;
+    R.mv_ms = cands.empty() ? 0.0 : best;
+  }
+  R.mv_variant = h->mv_variant;
+  R.mv_param = h->mv_variant == 2 ? h->mv_seg_per_xcd : h->mv_blocks_per_band;
+  const int degree = effective_degree(h);
+  if (flags & 2) {
+    const int lev = h->p;
+    const int ncols = h->off[lev + 1] - h->off[lev];
+    sgk::launch_fill(h->pv, 1.0, N, s);
+    if (h->opts.inner_precision == 32) sgk::launch_copy_d2f((float*)h->rw, h->pv, N, s);
+    else sgk::launch_copy_d2d((double*)h->rw, h->pv, N, s);
+    std::vector<int> tiles = degree <= 8 ? std::vector<int>{32, 16} : std::vector<int>{16};
+    std::vector<int> blocks = {0, std::max(1, h->num_cu / 2)};
+    double best = 1e300;
+    int bt = choose_tile(h, degree), bb = h->pcg_max_blocks;
+    for (int t : tiles)
+      for (int mb : blocks) {
+        h->opts.tile = t;
+        h->pcg_max_blocks = mb;
+        int rc = h->opts.inner_precision == 32 ? run_pcg<float>(h, (const float*)h->rw, (float*)h->zw, ncols, -1)
+                                               : run_pcg<double>(h, (const double*)h->rw, h->z, ncols, -1);
+        if (rc) return rc;
+        h->inner_ms_acc = 0.0;
+        rc = h->opts.inner_precision == 32 ? run_pcg<float>(h, (const float*)h->rw, (float*)h->zw, ncols, -1)
+                                           : run_pcg<double>(h, (const double*)h->rw, h->z, ncols, -1);
+        if (rc) return rc;
+        ++R.candidates;
+        if (h->inner_ms_acc < best) {
+          best = h->inner_ms_acc;
+          bt = t;
+          bb = mb;
+        }
+      }
+    h->opts.tile = bt;
+    h->pcg_max_blocks = bb;
+    R.pcg_ms = best;
+    h->inner_it_acc = 0;
+    h->inner_ms_acc = 0.0;
+    h->inner_bytes_acc = 0.0;
+    h->inner_launch_acc = 0;
+  }
+  R.pcg_tile = choose_tile(h, degree);
+  R.pcg_max_blocks = h->pcg_max_blocks;
+  if (out) *out = R;
+  return SG_OK;
+}
+
 }  // namespace sgh
 
 using namespace sgh;
@@ -920,62 +1085,17 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   if (e == hipSuccess) e = up(h->pair_a_d, pair_a.data(), sizeof(int) * pair_a.size());
   if (e == hipSuccess) e = up(h->pair_b_d, pair_b.data(), sizeof(int) * pair_b.size());
   if (e == hipSuccess) e = up(h->pair_g_d, pair_g.data(), sizeof(double) * pair_g.size());
-  // row groups of the y-marching SG operator: job 0 is the matvec, job 1 + 2 (l - 1) + dir the
-  // coupling product of level l in direction dir
-  h->march_ok = false;
-  if (sgk::march_supported(h->n_e, M) && h->mv_variant == 2) {
-    const int occ = sgk::march_blocks_per_cu(M, h->n_e);
-    if (occ > 0) {
-      const long cap = (long)occ * h->num_cu;
-      std::vector<HostMarchJob> jobs(1 + 2 * h->p);
-      std::vector<int> all(P);
-      for (int a = 0; a < P; ++a) all[a] = a;
-      build_march_job(M, h->nx, all, true, true, st_lo, st_up, st_glo, cap, jobs[0]);
-      for (int l = 1; l <= h->p; ++l)
-        for (int dir = 0; dir < 2; ++dir) {
-          const int rl = dir == 0 ? l - 1 : l;
-          std::vector<int> rows;
-          for (int a = h->off[rl]; a < h->off[rl + 1]; ++a) rows.push_back(a);
-          build_march_job(M, h->nx, rows, dir == 1, dir == 0, st_lo, st_up, st_glo, cap, jobs[1 + 2 * (l - 1) + dir]);
-        }
-      std::vector<int> ptr, rws, knd, lk, lcol;
-      std::vector<double> lw;
-      h->mjobs.clear();
-      int* ptr_d = (int*)(w + pl.o_mj_ptr);
-      int* rows_d = (int*)(w + pl.o_mj_rows);
-      int* kind_d = (int*)(w + pl.o_mj_kind);
-      int* lk_d = (int*)(w + pl.o_mj_lk);
-      int* lcol_d = (int*)(w + pl.o_mj_lcol);
-      double* lw_d = (double*)(w + pl.o_mj_lw);
-      for (const HostMarchJob& J : jobs) {
-        sgk::MarchJob mj{};
-        mj.gptr = ptr_d + ptr.size();
-        mj.grows = rows_d;
-        mj.gkind = kind_d + knd.size();
-        mj.lk = lk_d + lk.size();
-        mj.lcol = lcol_d + lcol.size();
-        mj.lw = lw_d + lw.size();
-        mj.ngroups = (int)J.kind.size();
-        mj.nseg = J.nseg;
-        mj.seg_rows = J.seg_rows;
-        h->mjobs.push_back(mj);
-        const int base = (int)rws.size();
-        for (int v : J.ptr) ptr.push_back(base + v);
-        rws.insert(rws.end(), J.rows.begin(), J.rows.end());
-        knd.insert(knd.end(), J.kind.begin(), J.kind.end());
-        lk.insert(lk.end(), J.lk.begin(), J.lk.end());
-        lcol.insert(lcol.end(), J.lcol.begin(), J.lcol.end());
-        lw.insert(lw.end(), J.lw.begin(), J.lw.end());
-      }
-      if (e == hipSuccess) e = up(ptr_d, ptr.data(), sizeof(int) * ptr.size());
-      if (e == hipSuccess) e = up(rows_d, rws.data(), sizeof(int) * rws.size());
-      if (e == hipSuccess) e = up(kind_d, knd.data(), sizeof(int) * knd.size());
-      if (e == hipSuccess) e = up(lk_d, lk.data(), sizeof(int) * lk.size());
-      if (e == hipSuccess) e = up(lcol_d, lcol.data(), sizeof(int) * lcol.size());
-      if (e == hipSuccess) e = up(lw_d, lw.data(), sizeof(double) * lw.size());
-      h->march_ok = true;
-    }
-  }
+  h->st_lo_h = st_lo;
+  h->st_up_h = st_up;
+  h->st_glo_h = st_glo;
+  h->mj_ptr_d = (int*)(w + pl.o_mj_ptr);
+  h->mj_rows_d = (int*)(w + pl.o_mj_rows);
+  h->mj_kind_d = (int*)(w + pl.o_mj_kind);
+  h->mj_lk_d = (int*)(w + pl.o_mj_lk);
+  h->mj_lcol_d = (int*)(w + pl.o_mj_lcol);
+  h->mj_lw_d = (double*)(w + pl.o_mj_lw);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && build_march_jobs(h, 0) != SG_OK) e = hipErrorUnknown;
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete h;
@@ -1123,6 +1243,12 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
   if (rc) return rc;
   for (int k = 0; k <= h->M; ++k) grad[k] = h->host_out[k];
   return status;
+}
+
+int sg_autotune(sg_handle h, int32_t flags, sg_tune_report* report) {
+  if (!h) return fail(SG_EINVAL, "null handle");
+  if (flags & ~3) return fail(SG_EINVAL, "unknown autotune flags");
+  return autotune(h, flags, report);
 }
 
 void sg_destroy(sg_handle h) {

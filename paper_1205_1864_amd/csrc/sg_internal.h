@@ -298,7 +298,12 @@ struct sg_ctx {
   int mv_variant;  // 0, 1: band kernels; 2: y-marching kernel
   int pcg_max_blocks;
   bool march_ok;
+  int mv_seg_per_xcd = 0;  // grid segments per XCD of the y-marching kernel (0 = automatic)
   std::vector<sgk::MarchJob> mjobs;
+  std::vector<int> st_lo_h, st_up_h;  // host copies of the dense neighbour tables (row groups)
+  std::vector<double> st_glo_h;
+  int *mj_ptr_d, *mj_rows_d, *mj_kind_d, *mj_lk_d, *mj_lcol_d;
+  double* mj_lw_d;
   const int* mask = nullptr;  // device flag of a batch member: SG operator launches skip while it is 0
   // host copies of the chaos lists (for counters)
   std::vector<int> lo_ptr, up_ptr;

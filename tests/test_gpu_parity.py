@@ -195,3 +195,22 @@ def test_adjoint_parity_small():
     Qo, go, _ = adjoint.adjoint_gradient(s, Ud, wm, wv, lambda R: solve.solve_direct(s, R))
     assert abs(Q - Qo) <= 1e-10 * abs(Qo)
     assert np.max(np.abs(g - go)) <= 1e-8 * np.max(np.abs(go))
+
+
+@pytest.mark.parametrize("kw,prec", [(dict(n_e=64, M=4, p=2), 64), (dict(n_e=128, M=3, p=3), 32),
+                                     (dict(n_e=33, M=5, p=2), 64)])
+def test_autotune_keeps_parity(kw, prec):
+    """The tuned schedules compute the same operator and solves (to rounding)."""
+    b = _b()
+    prob, s = _sys(**kw)
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=8, inner_rtol=1e-4))
+    rep = solver.sg_autotune(3)
+    assert rep["candidates"] >= 2 and rep["pcg_tile"] in (16, 32) and rep["pcg_ms"] > 0
+    assert rep["mv_variant"] in (0, 1, 2)
+    U = random_block(prob.P, prob.n, seed=4)
+    Y = solver.sg_matvec(_dev(U)).cpu().numpy()
+    Yo = sg.matvec(s, U.T.copy()).T
+    assert np.linalg.norm(Y - Yo) <= 1e-12 * np.linalg.norm(Yo)
+    F = prob.load_block()
+    Ux, st = solver.sg_solve(_dev(F), rtol=1e-8, maxit=100)
+    assert st["rc"] == 0 and solve.true_relres(s, F.T, Ux.cpu().numpy().T) <= 1.05e-8
