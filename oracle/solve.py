@@ -7,7 +7,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from . import hsc, krylov
+from . import bgs, hsc, krylov
 from .sg import SGSystem, assemble, matvec, unvec, vec
 
 
@@ -26,7 +26,7 @@ def mean_solver(sys: SGSystem, inner="exact", inner_rtol=1e-4, inner_maxit=1000,
 def solve_fcg(sys: SGSystem, F: np.ndarray, precond: str = "hsc", inner="exact",
               rtol: float = 1e-8, maxit: int = 200, inner_rtol: float = 1e-4,
               inner_maxit: int = 1000, degree: int = 4, X0=None):
-    """FCG on the SG system with M in {none, mean, hsc}; returns (FCGResult, counters, solver)."""
+    """FCG on the SG system with M in {none, mean, hsc, bgs}; returns (FCGResult, counters, solver)."""
     solver = mean_solver(sys, inner, inner_rtol, inner_maxit, degree)
     counters = hsc.Counters()
     if precond == "hsc":
@@ -35,6 +35,9 @@ def solve_fcg(sys: SGSystem, F: np.ndarray, precond: str = "hsc", inner="exact",
     elif precond == "mean":
         def M(R):
             return hsc.mean_apply(sys, R, solver)
+    elif precond == "bgs":
+        def M(R):
+            return bgs.bgs_apply(sys, R, solver, counters)
     elif precond == "none":
         def M(R):
             return R.copy()
