@@ -7,7 +7,8 @@ degree-8 Jacobi-Chebyshev preconditioner stopped at 1e-4. Inputs are seeded
 and synthetic and resident in HBM before timing starts.
 
 Also reported (outside the timed steps): the SG matvec bandwidth (cold and
-warm Infinity Cache), the FP32-inner and mean-preconditioned solves, the
+warm Infinity Cache), the FP32-inner, mean-preconditioned and block symmetric
+Gauss-Seidel-preconditioned solves, the
 adjoint gradient of the 512^2 differentiation case, the 48-problem uneven
 batch (FP32 inner / FP64 outer, graph replay) against the same problems
 solved one after another, the roofline of the dominant kernel, and the CPU
@@ -220,7 +221,8 @@ def main():
         # FP32 inner (precision variant) and mean-based comparators
         for label, o in [("hsc_fp32", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="hsc", inner_maxit=2000)),
                          ("mean_fp64", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000)),
-                         ("mean_fp32", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000))]:
+                         ("mean_fp32", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000)),
+                         ("bgs_fp64", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="bgs", inner_maxit=2000))]:
             sv = SGSolver(prob, o)
             sv.sg_autotune(3)
             Uv = sv.empty()
@@ -233,6 +235,7 @@ def main():
             log(f"{label}: {extra[f'solve_s_{label}']:.3f} s, outer {sv_st['outer_it']}")
             extra[f"outer_it_{label}"] = sv_st["outer_it"]
             extra[f"inner_it_total_{label}"] = sv_st["inner_it_total"]
+            extra[f"n_blocksolve_{label}"] = sv_st["n_blocksolve"]
             extra[f"true_relres_{label}"] = sv_st["true_relres"]
             extra[f"rel_diff_vs_fp64_hsc_{label}"] = float(torch.linalg.norm(Uv - U64) / torch.linalg.norm(U64))
             if label == "hsc_fp32":

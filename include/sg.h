@@ -59,7 +59,7 @@ enum {
   SG_BREAKDOWN = 2
 };
 
-enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_HSC = 2 };
+enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_HSC = 2, SG_PC_BGS = 3 };
 
 typedef struct sg_ctx* sg_handle;
 
@@ -89,7 +89,7 @@ typedef struct sg_problem {
  *                     preconditioner of the inner PCG (d - 1 products with
  *                     K_0 per application).
  *   inner_maxit       cap on inner PCG iterations per solve (>= 1).
- *   precond           SG_PC_NONE, SG_PC_MEAN or SG_PC_HSC for sg_solve.
+ *   precond           SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC or SG_PC_BGS for sg_solve.
  *   tile              spatial tile edge of the inner solver (16 or 32; 0 = auto).
  *   inner_rtol        relative residual at which an inner solve stops
  *                     (recursive residual, Euclidean norm); <= 0 runs
@@ -151,6 +151,16 @@ int sg_apply_hsc(sg_handle h, const double* R, double* Z);
 /* Z = (I (x) K_0^-1) R approximately: the mean-based preconditioner (Section 6),
  * one inner PCG solve per column. */
 int sg_apply_mean(sg_handle h, const double* R, double* Z);
+
+/* Z = M_bGS R: one action of the block symmetric Gauss-Seidel preconditioner
+ * (the comparator of Section 6) from a zero initial guess, blocks in the
+ * graded chaos order, diagonal blocks K_0 inverted by the inner PCG. Blocks of
+ * equal degree do not couple (linear KL expansion), so each sweep runs level
+ * by level: forward l = 0..p with z_l = D_l^-1 (r_l - C_l z_{l-1}), backward
+ * l = p-1..0 with z_l = D_l^-1 (r_l - C_l z'_{l-1} - B_{l+1} z_{l+1}), where
+ * z' are the forward values (their product is kept, not recomputed) and the
+ * top level keeps its forward value. R and Z are distinct n x P device blocks. */
+int sg_apply_bgs(sg_handle h, const double* R, double* Z);
 
 /* Inner solves on the diagonal blocks (Section 5): for columns c = 0..ncols-1,
  * PCG on K_0 x_c = b_c with the Jacobi-scaled Chebyshev preconditioner, in
@@ -220,8 +230,8 @@ void sg_destroy(sg_handle h);
 /* ---- Multi-problem batch.
  * Many independent problems (each as in sg_setup: its own grid, KL terms and
  * chaos degree) solved together by the flexible CG of Section 5 with the
- * preconditioner opts.precond (SG_PC_HSC, Algorithm 1, or SG_PC_MEAN,
- * Section 6); all problems share the options. One outer iteration of the
+ * preconditioner opts.precond (SG_PC_HSC, Algorithm 1, SG_PC_MEAN or
+ * SG_PC_BGS, Section 6); all problems share the options. One outer iteration of the
  * batch runs, for all problems that have not stopped yet: the diagonal-block
  * solves of each step of Algorithm 1 for every problem in one inner launch,
  * the coupling products and SG matvecs of each problem, and batched vector

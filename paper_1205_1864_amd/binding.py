@@ -20,8 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SGPC_LIBRARY") or os.path.join(_HERE, "libsgpc.so")
 
 SG_OK, SG_EINVAL, SG_EDEVICE, SG_ENOMEM, SG_NOT_CONVERGED, SG_BREAKDOWN = 0, -1, -2, -3, 1, 2
-SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC = 0, 1, 2
-_PC = {"none": SG_PC_NONE, "mean": SG_PC_MEAN, "hsc": SG_PC_HSC}
+SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC, SG_PC_BGS = 0, 1, 2, 3
+_PC = {"none": SG_PC_NONE, "mean": SG_PC_MEAN, "hsc": SG_PC_HSC, "bgs": SG_PC_BGS}
 
 
 class SgProblem(ctypes.Structure):
@@ -74,6 +74,7 @@ def _load():
         "sg_matvec": [VP, VP, VP],
         "sg_apply_hsc": [VP, VP, VP],
         "sg_apply_mean": [VP, VP, VP],
+        "sg_apply_bgs": [VP, VP, VP],
         "sg_inner_solve": [VP, VP, VP, I32, P(I32)],
         "sg_coupling": [VP, I32, I32, VP, VP],
         "sg_solve": [VP, VP, VP, D, I32, I32, P(SgStats)],
@@ -212,6 +213,11 @@ class SGSolver:
     def sg_apply_hsc(self, R, Z=None):
         Z = self.empty() if Z is None else Z
         _check(lib.sg_apply_hsc(self.handle, _dptr(self._block(R)), _dptr(self._block(Z))))
+        return Z
+
+    def sg_apply_bgs(self, R, Z=None):
+        Z = self.empty() if Z is None else Z
+        _check(lib.sg_apply_bgs(self.handle, _dptr(self._block(R)), _dptr(self._block(Z))))
         return Z
 
     def sg_apply_mean(self, R, Z=None):

@@ -239,8 +239,9 @@ __global__ void count_iters_kernel(const int* iters, const int* act, const int* 
 // One block: order-preserving list of the columns whose problem is active and
 // the exclusive prefix sums of their tile counts.
 __global__ void __launch_bounds__(1024) compact_kernel(const int* prob, const int* ntiles, int ncols,
-                                                       const int* active, int* act, int* nact, long* cbase,
-                                                       long* nwork_act) {
+                                                       const int* active, const int* pdeg, int pmin, int* act,
+                                                       int* nact, long* cbase, long* nwork_act) {
+  auto keep = [&](int c) { return active[prob[c]] != 0 && pdeg[prob[c]] >= pmin; };
   __shared__ int cnt[1024];
   __shared__ long tiles[1024];
   const int per = (ncols + 1023) / 1024;
@@ -249,7 +250,7 @@ __global__ void __launch_bounds__(1024) compact_kernel(const int* prob, const in
   int k = 0;
   long t = 0;
   for (int c = c0; c < c1; ++c)
-    if (active[prob[c]]) {
+    if (keep(c)) {
       ++k;
       t += ntiles[c];
     }
@@ -274,7 +275,7 @@ __global__ void __launch_bounds__(1024) compact_kernel(const int* prob, const in
   int pos = cnt[threadIdx.x];
   long base = tiles[threadIdx.x];
   for (int c = c0; c < c1; ++c)
-    if (active[prob[c]]) {
+    if (keep(c)) {
       act[pos] = c;
       cbase[pos] = base;
       ++pos;
@@ -337,11 +338,11 @@ void launch_batch_count_iters(const int* iters, const int* act, const int* nact,
                      sticky_status);
 }
 
-void launch_batch_compact(const int* prob, const int* ntiles, int ncols, const int* active, int* act, int* nact,
-                          long* cbase, long* nwork_act, hipStream_t s) {
+void launch_batch_compact(const int* prob, const int* ntiles, int ncols, const int* active, const int* pdeg, int pmin,
+                          int* act, int* nact, long* cbase, long* nwork_act, hipStream_t s) {
   if (ncols <= 0) return;
-  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, prob, ntiles, ncols, active, act, nact, cbase,
-                     nwork_act);
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, prob, ntiles, ncols, active, pdeg, pmin, act, nact,
+                     cbase, nwork_act);
 }
 
 }  // namespace sgk

@@ -44,6 +44,7 @@ struct sg_batch_ctx {
   std::vector<int> set_ncols;
   sgk::PcgScratch sc{};
   int* sticky = nullptr;  // set if a bounded wait of an inner launch expired
+  int* pdeg = nullptr;    // chaos degree of each problem (device)
   sgk::BatchVecs V{};
   double** x_tab = nullptr;        // device tables of the solution and right-hand-side addresses
   const double** f_tab = nullptr;
@@ -87,7 +88,7 @@ int batch_tile(const sg_opts& op) {
 // shared region. Returns false if a problem is rejected.
 struct BatchPlan {
   std::vector<size_t> ws_off, ws_size;
-  size_t o_N, o_tab, o_sc, o_active, o_part, o_consts, o_sets, o_pcg_part, o_arr, o_iters, o_status, o_sticky;
+  size_t o_N, o_tab, o_sc, o_active, o_pdeg, o_part, o_consts, o_sets, o_pcg_part, o_arr, o_iters, o_status, o_sticky;
   std::vector<int> set_ncols;
   std::vector<long> set_nwork;
   size_t set_bytes = 0;
@@ -104,8 +105,8 @@ size_t set_stride(long ncols) {
 int make_batch_plan(int count, const sg_problem* probs, const sg_opts* op, BatchPlan& bp) {
   if (count <= 0) return fail(SG_EINVAL, "batch needs at least one problem");
   if (!probs || !op) return fail(SG_EINVAL, "null problems or options");
-  if (op->precond != SG_PC_HSC && op->precond != SG_PC_MEAN)
-    return fail(SG_EINVAL, "a batch uses the HSC or the mean-based preconditioner");
+  if (op->precond != SG_PC_HSC && op->precond != SG_PC_MEAN && op->precond != SG_PC_BGS)
+    return fail(SG_EINVAL, "a batch uses the HSC, the mean-based or the block Gauss-Seidel preconditioner");
   Layout L;
   int pmax = 0;
   for (int b = 0; b < count; ++b) {
@@ -139,6 +140,7 @@ int make_batch_plan(int count, const sg_problem* probs, const sg_opts* op, Batch
   bp.o_tab = L.take(sizeof(void*) * 8 * count);
   bp.o_sc = L.take(sizeof(sgk::BatchScal) * count);
   bp.o_active = L.take(sizeof(int) * count);
+  bp.o_pdeg = L.take(sizeof(int) * count);
   bp.o_part = L.take(sizeof(double) * 2 * sgk::kBatchBlocks * count);
   bp.o_consts = L.take(sizeof(sgk::PcgConsts<double>) * count);
   bp.o_sets = L.take(bp.set_bytes);
@@ -235,8 +237,9 @@ std::vector<sgk::PcgCols<double>>& sets<double>(sg_batch_ctx* B) { return B->col
 template <>
 std::vector<sgk::PcgCols<float>>& sets<float>(sg_batch_ctx* B) { return B->cols32; }
 
+// Ragged inner launch over column set s, restricted to problems of degree >= pmin.
 template <typename T>
-int run_set(sg_batch_ctx* B, int s) {
+int run_set(sg_batch_ctx* B, int s, int pmin = 0) {
   const int ncols = B->set_ncols[s];
   if (ncols <= 0) return SG_OK;
   sgk::PcgArgs<T> a{};
@@ -247,7 +250,7 @@ int run_set(sg_batch_ctx* B, int s) {
   a.sc = B->sc;
   const sgk::PcgCols<T>& cols = sets<T>(B)[s];
   // only the columns of problems that still iterate take part in the launch
-  sgk::launch_batch_compact(cols.prob, cols.ntiles, ncols, B->V.active, const_cast<int*>(cols.act),
+  sgk::launch_batch_compact(cols.prob, cols.ntiles, ncols, B->V.active, B->pdeg, pmin, const_cast<int*>(cols.act),
                             const_cast<int*>(cols.nact), const_cast<long*>(cols.cbase),
                             const_cast<long*>(cols.nwork_act), B->stream);
   SG_HIP(sgk::launch_pcg_ragged<T>(a, cols, B->tile, B->stream));
@@ -277,17 +280,40 @@ int batch_hsc(sg_batch_ctx* B) {
   return SG_OK;
 }
 
+// Block symmetric Gauss-Seidel for every active problem, level steps shared
+// across the batch (forward l = 0..pmax, backward l = pmax-1..0).
+template <typename T>
+int batch_bgs(sg_batch_ctx* B) {
+  auto zw = [&](sg_ctx* h) { return B->inner == 32 ? (T*)h->zw : (T*)h->z; };
+  int rc = run_set<T>(B, 0);
+  if (rc) return rc;
+  for (int l = 1; l <= B->pmax; ++l) {
+    for (sg_ctx* h : B->h)
+      if (h->p >= l) sgh::coupling<T>(h, l, 1, (T*)h->rw, zw(h));
+    rc = run_set<T>(B, l);
+    if (rc) return rc;
+  }
+  for (int l = B->pmax - 1; l >= 0; --l) {
+    // problems whose top level is l keep their forward values on level l
+    for (sg_ctx* h : B->h)
+      if (h->p >= l + 1) sgh::coupling<T>(h, l + 1, 0, (T*)h->rw, zw(h));
+    rc = run_set<T>(B, l, l + 1);
+    if (rc) return rc;
+  }
+  return SG_OK;
+}
+
 // One outer iteration of every active problem (no host synchronisation).
 int iteration(sg_batch_ctx* B, int pc) {
   int rc = SG_OK;
   if (B->inner == 32) {
     sgk::launch_batch_to_inner<float>(B->V, B->stream);
-    rc = pc == SG_PC_HSC ? batch_hsc<float>(B) : run_set<float>(B, B->pmax + 1);
+    rc = pc == SG_PC_HSC ? batch_hsc<float>(B) : pc == SG_PC_BGS ? batch_bgs<float>(B) : run_set<float>(B, B->pmax + 1);
     if (rc) return rc;
     sgk::launch_batch_from_inner(B->V, B->stream);
   } else {
     sgk::launch_batch_to_inner<double>(B->V, B->stream);
-    rc = pc == SG_PC_HSC ? batch_hsc<double>(B) : run_set<double>(B, B->pmax + 1);
+    rc = pc == SG_PC_HSC ? batch_hsc<double>(B) : pc == SG_PC_BGS ? batch_bgs<double>(B) : run_set<double>(B, B->pmax + 1);
     if (rc) return rc;
   }
   sgk::launch_batch_dot_zq(B->V, B->stream);
@@ -465,10 +491,14 @@ int sg_batch_setup(int32_t count, const sg_problem* probs, const sg_opts* opts, 
   B->sc.iters = (int*)(w + bp.o_iters);
   B->sc.status = (int*)(w + bp.o_status);
   B->sticky = (int*)(w + bp.o_sticky);
+  B->pdeg = (int*)(w + bp.o_pdeg);
+  std::vector<int> pdeg(count);
+  for (int b = 0; b < count; ++b) pdeg[b] = B->h[b]->p;
   hipStream_t s = B->stream;
   hipError_t e = hipMemcpyAsync(w + bp.o_N, N.data(), sizeof(long) * count, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(tab_d, tab.data(), sizeof(void*) * tab.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(w + bp.o_consts, consts.data(), consts.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(B->pdeg, pdeg.data(), sizeof(int) * count, hipMemcpyHostToDevice, s);
   for (auto& sb : set_blobs)
     if (e == hipSuccess && !sb.second.empty())
       e = hipMemcpyAsync(w + bp.o_sets + sb.first, sb.second.data(), sb.second.size(), hipMemcpyHostToDevice, s);
@@ -542,8 +572,9 @@ int sg_batch_solve(sg_batch B, const double* const* F, double* const* U, double 
     st.inner_it_total = S[b].inner_it;
     long nbmv = 0;
     for (int l = 1; l <= h->p; ++l) nbmv += sgh::coupling_blocks(h, l, 0) + sgh::coupling_blocks(h, l, 1);
-    st.n_blockmv = pc == SG_PC_HSC ? (long)S[b].it * nbmv : 0;
-    st.n_blocksolve = (long)S[b].it * (pc == SG_PC_HSC ? 2L * (h->P - 1) + 1 : (long)h->P);
+    const long top = h->off[h->p + 1] - h->off[h->p];
+    st.n_blockmv = pc == SG_PC_MEAN ? 0 : (long)S[b].it * nbmv;
+    st.n_blocksolve = (long)S[b].it * (pc == SG_PC_HSC ? 2L * (h->P - 1) + 1 : pc == SG_PC_BGS ? 2L * h->P - top : (long)h->P);
     st.relres = S[b].fn2 > 0.0 ? std::sqrt(S[b].rr / S[b].fn2) : 0.0;
     st.ms = ms;
     // true residual ||f - A u|| / ||f|| of the returned iterate

@@ -1,7 +1,8 @@
 // C interface of the SG solver library: setup of the chaos tables and the
 // workspace, and the host drivers of the flexible CG (Section 5), the
 // hierarchical Schur complement preconditioner (Algorithm 1), the mean-based
-// preconditioner (Section 6) and the adjoint gradient.
+// and block symmetric Gauss-Seidel preconditioners (Section 6) and the
+// adjoint gradient.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -108,7 +109,7 @@ int validate(const sg_problem* pr, const sg_opts* op) {
     return fail(SG_EINVAL, "inner_precision must be 32 or 64");
   if (op->cheb_degree < 1 || op->cheb_degree > sgk::kMaxCheb) return fail(SG_EINVAL, "cheb_degree must be 1..16");
   if (op->inner_maxit < 1) return fail(SG_EINVAL, "inner_maxit must be >= 1");
-  if (op->precond < SG_PC_NONE || op->precond > SG_PC_HSC) return fail(SG_EINVAL, "unknown preconditioner");
+  if (op->precond < SG_PC_NONE || op->precond > SG_PC_BGS) return fail(SG_EINVAL, "unknown preconditioner");
   if (op->tile != 0 && op->tile != 16 && op->tile != 32) return fail(SG_EINVAL, "tile must be 0, 16 or 32");
   if (!(op->inner_rtol < 1.0) || std::isnan(op->inner_rtol)) return fail(SG_EINVAL, "inner_rtol must be < 1");
   return SG_OK;
@@ -516,6 +517,51 @@ int hsc_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs) {
   return SG_OK;
 }
 
+// Block symmetric Gauss-Seidel action in inner precision T from a zero initial
+// guess: rw holds a copy of the residual, Zb receives M_bGS r. Forward sweep
+// l = 0..p, backward sweep l = p-1..0; rw keeps r_l - C_l z'_{l-1} from the
+// forward sweep, so the backward sweep only subtracts B_{l+1} z_{l+1}.
+template <typename T>
+int bgs_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs) {
+  const long n = h->n;
+  int rc = run_pcg<T>(h, rw, Zb, 1, 0);  // z'_0 = K_0^-1 r_0
+  if (rc) return rc;
+  *nbs += 1;
+  for (int l = 1; l <= h->p; ++l) {
+    const int lo = h->off[l], hi = h->off[l + 1];
+    coupling<T>(h, l, 1, rw, Zb);  // r_l - C_l z'_{l-1}
+    *nbmv += coupling_blocks(h, l, 1);
+    rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l);  // z'_l
+    if (rc) return rc;
+    *nbs += hi - lo;
+  }
+  for (int l = h->p - 1; l >= 0; --l) {
+    const int lo = h->off[l], hi = h->off[l + 1];
+    coupling<T>(h, l + 1, 0, rw, Zb);  // ... - B_{l+1} z_{l+1}
+    *nbmv += coupling_blocks(h, l + 1, 0);
+    rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l);  // z_l
+    if (rc) return rc;
+    *nbs += hi - lo;
+  }
+  return SG_OK;
+}
+
+int apply_bgs(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
+  const long N = h->n * (long)h->P;
+  if (h->opts.inner_precision == 64) {
+    double* rw = (double*)h->rw;
+    sgk::launch_copy_d2d(rw, R, N, h->stream);
+    return bgs_core<double>(h, rw, Z, nbmv, nbs);
+  }
+  float* rw = (float*)h->rw;
+  float* zw = (float*)h->zw;
+  sgk::launch_copy_d2f(rw, R, N, h->stream);
+  int rc = bgs_core<float>(h, rw, zw, nbmv, nbs);
+  if (rc) return rc;
+  sgk::launch_copy_f2d(Z, zw, N, h->stream);
+  return SG_OK;
+}
+
 int apply_hsc(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
   const long N = h->n * (long)h->P;
   if (h->opts.inner_precision == 64) {
@@ -672,6 +718,8 @@ int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x
       Timer tp;
       if (pc == SG_PC_HSC) {
         rc = apply_hsc(h, r, z, &nbmv, &nbs);
+      } else if (pc == SG_PC_BGS) {
+        rc = apply_bgs(h, r, z, &nbmv, &nbs);
       } else if (pc == SG_PC_MEAN) {
         rc = apply_mean(h, r, z, &nbs);
       } else {
@@ -1149,6 +1197,16 @@ int sg_apply_hsc(sg_handle h, const double* R, double* Z) {
   long a = 0, b = 0;
   for (int l = 0; l < sgk::kMaxLevels; ++l) h->inner_it_max[l] = 0;
   int rc = apply_hsc(h, R, Z, &a, &b);
+  if (rc) return rc;
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_apply_bgs(sg_handle h, const double* R, double* Z) {
+  if (!h || !R || !Z) return fail(SG_EINVAL, "null argument");
+  if (R == Z) return fail(SG_EINVAL, "R and Z must be distinct");
+  long a = 0, b = 0;
+  int rc = apply_bgs(h, R, Z, &a, &b);
   if (rc) return rc;
   SG_HIP(hipGetLastError());
   return SG_OK;

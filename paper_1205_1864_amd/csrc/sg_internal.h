@@ -274,10 +274,11 @@ void launch_batch_to_inner(const BatchVecs& V, hipStream_t s);    // rw = r
 void launch_batch_from_inner(const BatchVecs& V, hipStream_t s);  // z = zw
 void launch_batch_count_iters(const int* iters, const int* act, const int* nact, const int* prob, int ncols,
                               BatchScal* sc, const int* pcg_status, int* sticky_status, hipStream_t s);
-// List of the columns of a ragged set whose problem is still active, with the
-// prefix sums of their tile counts (the partial slots of the next launch).
-void launch_batch_compact(const int* prob, const int* ntiles, int ncols, const int* active, int* act, int* nact,
-                          long* cbase, long* nwork_act, hipStream_t s);
+// List of the columns of a ragged set whose problem is still active and has
+// chaos degree pdeg >= pmin, with the prefix sums of their tile counts (the
+// partial slots of the next launch).
+void launch_batch_compact(const int* prob, const int* ntiles, int ncols, const int* active, const int* pdeg, int pmin,
+                          int* act, int* nact, long* cbase, long* nwork_act, hipStream_t s);
 
 }  // namespace sgk
 

@@ -40,7 +40,7 @@ def _rhs(probs):
     return F
 
 
-@pytest.mark.parametrize("prec,pc", [(64, "hsc"), (32, "hsc"), (64, "mean")])
+@pytest.mark.parametrize("prec,pc", [(64, "hsc"), (32, "hsc"), (64, "mean"), (64, "bgs"), (32, "bgs")])
 def test_batch_matches_single_solves(prec, pc):
     b = _b()
     probs = _problems()
@@ -65,6 +65,9 @@ def test_batch_matches_single_solves(prec, pc):
         if pc == "hsc":
             P = pr.P
             assert st["n_blocksolve"] == st["outer_it"] * (2 * (P - 1) + 1)
+            assert st["n_blockmv"] == ss["n_blockmv"] // max(1, ss["outer_it"]) * st["outer_it"]
+        if pc == "bgs":
+            assert st["n_blocksolve"] == ss["n_blocksolve"] // max(1, ss["outer_it"]) * st["outer_it"]
             assert st["n_blockmv"] == ss["n_blockmv"] // max(1, ss["outer_it"]) * st["outer_it"]
         assert st["inner_it_total"] > 0
 

@@ -7,7 +7,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-from oracle import hsc, krylov, sg, solve  # noqa: E402
+from oracle import bgs, hsc, krylov, sg, solve  # noqa: E402
 from sg_inputs import named_problem, random_block  # noqa: E402
 
 
@@ -118,19 +118,23 @@ def test_coupling_parity(kw):
             assert np.linalg.norm(Rg - Ro.T) <= 1e-13 * np.linalg.norm(Ro)
 
 
-@pytest.mark.parametrize("which", ["hsc", "mean"])
-def test_preconditioner_tight_parity(which):
+@pytest.mark.parametrize("which", ["hsc", "mean", "bgs"])
+@pytest.mark.parametrize("kw", [dict(n_e=24, M=3, p=3), dict(n_e=64, M=4, p=2), dict(n_e=19, M=2, p=4)])
+def test_preconditioner_tight_parity(which, kw):
     b = _b()
-    prob, s = _sys(n_e=24, M=3, p=3)
+    prob, s = _sys(**kw)
     solver = b.SGSolver(prob, b.Options(inner_precision=64, inner_rtol=1e-13, inner_maxit=2000))
     R = random_block(prob.P, prob.n, seed=8)
-    Z = (solver.sg_apply_hsc if which == "hsc" else solver.sg_apply_mean)(_dev(R)).cpu().numpy()
+    apply = {"hsc": solver.sg_apply_hsc, "mean": solver.sg_apply_mean, "bgs": solver.sg_apply_bgs}[which]
+    Z = apply(_dev(R)).cpu().numpy()
     ex = hsc.ExactMeanSolver(s)
-    Zo = (hsc.hsc_apply(s, R.T, ex) if which == "hsc" else hsc.mean_apply(s, R.T, ex)).T
+    ref = {"hsc": lambda: hsc.hsc_apply(s, R.T, ex), "mean": lambda: hsc.mean_apply(s, R.T, ex),
+           "bgs": lambda: bgs.bgs_apply(s, R.T, ex)}[which]
+    Zo = ref().T
     assert np.linalg.norm(Z - Zo) <= 1e-9 * np.linalg.norm(Zo)
 
 
-@pytest.mark.parametrize("prec,pc", [(64, "hsc"), (32, "hsc"), (64, "mean"), (32, "mean")])
+@pytest.mark.parametrize("prec,pc", [(64, "hsc"), (32, "hsc"), (64, "mean"), (32, "mean"), (64, "bgs"), (32, "bgs")])
 def test_solve_small(prec, pc):
     b = _b()
     prob, s = _sys()
@@ -146,11 +150,33 @@ def test_solve_small(prec, pc):
     A = sg.assemble(s).toarray()
     ev = np.linalg.eigvalsh(A)
     assert np.linalg.norm(U.T - Ud) / np.linalg.norm(Ud) <= ev.max() / ev.min() * 1e-8
+    P = prob.P
+    n_b = int(np.count_nonzero(sum(np.abs(G) for G in s.G)))
     if pc == "hsc":
-        P = prob.P
         assert st["n_blocksolve"] == st["outer_it"] * (2 * (P - 1) + 1)
-        n_b = int(np.count_nonzero(sum(np.abs(G) for G in s.G)))
         assert st["n_blockmv"] == st["outer_it"] * (n_b - P)
+    if pc == "bgs":
+        # the top level is solved once; the lower level products of the forward
+        # sweep are kept, so one action costs one pass over the off-diagonal blocks
+        top = int(s.off[prob.p + 1] - s.off[prob.p])
+        assert st["n_blocksolve"] == st["outer_it"] * (2 * P - top)
+        assert st["n_blockmv"] == st["outer_it"] * (n_b - P)
+
+
+def test_solve_bgs_matches_oracle_iterates():
+    """bGS-preconditioned FCG with (nearly) exact inner solves follows the oracle's."""
+    b = _b()
+    prob, s = _sys(n_e=20, M=3, p=3)
+    F = prob.load_block()
+    solver = b.SGSolver(prob, b.Options(inner_precision=64, precond="bgs", inner_rtol=1e-14, inner_maxit=3000))
+    U, st = solver.sg_solve(_dev(F), rtol=1e-10, maxit=80)
+    res, cnt, _ = solve.solve_fcg(s, F.T.copy(), "bgs", "exact", rtol=1e-10, maxit=80)
+    assert st["rc"] == 0
+    assert st["outer_it"] == res.iterations
+    assert np.linalg.norm(U.cpu().numpy().T - res.x) <= 1e-10 * np.linalg.norm(res.x)
+    # the oracle recomputes the lower products in the backward sweep (1.5x) and
+    # solves every block twice; the GPU keeps both the top-level and the lower values
+    assert cnt.block_solves == 2 * prob.P * res.iterations
 
 
 def test_solve_tight_matches_oracle_iterates():
