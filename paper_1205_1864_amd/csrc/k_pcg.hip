@@ -13,12 +13,20 @@
 //   phase A: p = z + beta p (tile plus a 1-node halo), q = K_0 p, partial p.q;
 //   phase B: alpha = gamma / p.q, x += alpha p, r -= alpha q (tile plus the
 //            Chebyshev halo), z = M r, partials r.r and r.z.
-// A column is split into TS x TS tiles; each block owns a contiguous run of
-// tiles (the same tiles in every phase) and works on G tiles at a time, one
-// per 256-thread group. Columns synchronise only among the blocks that share
-// them, through split-phase counters (no grid-wide barrier). Per-column scalars
-// are reduced from per-tile partials in a fixed order, identically in every
-// block, so all owners of a column take the same decisions.
+// A column is split into tiles; each block owns a contiguous run of tiles (the
+// same tiles in every phase) and works on G tiles at a time, one per
+// 256-thread group whose four waves synchronise among themselves only.
+// Columns synchronise only among the blocks that share them, through
+// split-phase counters (no grid-wide barrier). Per-column scalars are reduced
+// from per-tile partials in a fixed order, identically in every block, so all
+// owners of a column take the same decisions.
+//
+// Two tile shapes. Banded tiles (the default) are tsx x 32 nodes with tsx
+// chosen so that the tile plus its halo is at most 64 columns wide: each lane
+// owns one column of the region and each wave one band of its rows, the
+// horizontal stencil neighbours come from the neighbouring lanes (DPP) and the
+// vertical ones from a sliding window of rows, so a node update reads LDS once.
+// Square 16 x 16 tiles serve Chebyshev degrees whose halo is too wide for that.
 //
 // The same kernel runs a ragged set of columns from several problems (grids
 // of different sizes, own constants, a per-problem skip flag): the tiles of
@@ -31,7 +39,7 @@ namespace sgk {
 
 namespace {
 
-constexpr int kGroup = 256;                // threads per tile group
+constexpr int kSquareGroup = 256;          // threads per group of the square tiles
 constexpr long kSpinLimit = 1L << 26;      // bounded waits: a stuck column aborts the launch
 
 enum { PART_BB = 0, PART_PQ = 1, PART_RR0 = 2, PART_RR1 = 3, PART_RZ0 = 4, PART_RZ1 = 5, PART_N = 6 };
@@ -72,32 +80,71 @@ __device__ bool column_wait(const unsigned* arr, unsigned target, int* status, i
   return *sflag != 0;
 }
 
-// Per-group sum of one value per thread, fixed order; the result is returned
-// to every thread of the group. All threads of the block must call it together.
-template <int G>
-__device__ double group_sum(double v, double (*sred)[4]) {
-  v = wave_sum(v);
-  const int g = threadIdx.x / kGroup, wv = (threadIdx.x % kGroup) >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sred[g][wv] = v;
-  __syncthreads();
-  return sred[g][0] + sred[g][1] + sred[g][2] + sred[g][3];
+// Index of this wave within its tile group (uniform, so that values derived
+// from it stay in scalar registers).
+template <int GT>
+__device__ __forceinline__ int wave_in_group() {
+  return __builtin_amdgcn_readfirstlane((threadIdx.x % GT) >> 6);
 }
 
-template <int TS>
-struct Interior {
-  static constexpr int NI = (TS * TS + kGroup - 1) / kGroup;  // interior nodes per thread
+// Barrier of the four waves of one tile group, so the groups of a block do
+// not run in lockstep (one group loads its next tile while another sweeps).
+// `bar` is the group's monotonic arrival counter in LDS; `gen` counts the
+// arrivals this wave has waited for so far (the same in every wave of the
+// group). A wait that does not end within the spin limit sets the status word
+// and returns, so a wrong barrier count ends the launch with an error instead
+// of a hang.
+struct GroupBarrier {
+  unsigned* bar;
+  unsigned gen;
+  unsigned waves;  // waves of the group
+  int* status;
+  bool dead;  // a wait ran out: later barriers of this wave no longer wait
 };
 
-// Chebyshev preconditioner on one tile for one group. `rreg(lx, ly)` gives r
-// on the region (tile plus halo H = degree - 1; only called inside the
-// domain). On return Zi holds z and Ri holds r on this thread's interior
-// nodes; the return value is the thread's partial r.z. With `valid` false the
-// group only takes part in the block-wide synchronisation.
+__device__ __forceinline__ void group_sync(GroupBarrier& gb) {
+  gb.gen += gb.waves;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(gb.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  long spins = 0;
+  while (!gb.dead && __hip_atomic_load(gb.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < gb.gen) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      if ((threadIdx.x & 63) == 0) atomicExch(gb.status, 1);
+      gb.dead = true;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Per-group sums of two values per thread, fixed order; the results are
+// returned to every thread of the group. Only the group's threads take part.
+template <int GT>
+__device__ void group_sum2(double& a, double& b, double (*sred)[GT / 64][2], GroupBarrier& gb) {
+  constexpr int NW = GT / 64;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / GT), wv = wave_in_group<GT>();
+  group_sync(gb);  // earlier readers of sred[g] are done
+  if ((threadIdx.x & 63) == 0) {
+    sred[g][wv][0] = a;
+    sred[g][wv][1] = b;
+  }
+  group_sync(gb);
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    sa += sred[g][w][0];
+    sb += sred[g][w][1];
+  }
+  a = sa;
+  b = sb;
+}
+
 // The grid, state vectors and constants of one column.
 template <typename T>
 struct ColView {
-  int nx, ntx, ntiles;
+  int nx, ntx, ntiles, tsx;  // tsx: width of a banded tile
   long tbase;  // first index of the column's per-tile partials (and of its work items)
   const T* b;
   T *x, *r0, *r1, *p0, *p1, *q, *z;
@@ -106,97 +153,441 @@ struct ColView {
   const T* chebB;
 };
 
-template <typename T, int TS, int NS, typename RF>
-__device__ double cheb_tile(const ColView<T>& A, int degree, bool valid, int x0, int y0, RF rreg, T* W0, T* W1,
-                            T (&Zi)[Interior<TS>::NI], T (&Ri)[Interior<TS>::NI]) {
-  constexpr int NI = Interior<TS>::NI;
-  const int lt = threadIdx.x % kGroup;
-  const int H = degree - 1;
-  const int RS = TS + 2 * H;
-  const int nreg = RS * RS;
-  T S[NS];
-  // step 0: S = D^-1 r, W = S / theta; r parked in W1 for the interior mapping
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int i = lt + s * kGroup;
-    S[s] = T(0);
-    if (valid && i < nreg) {
-      const int lx = i % RS, ly = i / RS;
-      const int gx = x0 - H + lx, gy = y0 - H + ly;
-      const T r = (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) ? rreg(lx, ly) : T(0);
-      S[s] = r * A.inv_diag;
-      W0[i] = S[s] * A.inv_theta;
-      W1[i] = r;
-    }
+// Vectors of one PCG iteration as seen by the tile routines.
+template <typename T>
+struct IterVecs {
+  const T* po;  // p of the previous iteration (phase A)
+  T* pn;        // p of this iteration
+  const T* ro;  // r of the previous iteration (phase B)
+  T* rn;        // r of this iteration
+  T beta;       // phase A: p = z + beta p (first iteration: p = z)
+  T alpha;      // phase B: x += alpha p, r -= alpha q
+  bool first;
+};
+
+// ---------------------------------------------------------------------------
+// Square TS x TS tiles: region (tile plus halo) nodes are spread over the
+// group's threads in row-major order, NS nodes per thread.
+// ---------------------------------------------------------------------------
+template <typename T, int TS, int NS>
+struct SquareTile {
+  static constexpr int kThreads = kSquareGroup;
+  static constexpr int NI = (TS * TS + kThreads - 1) / kThreads;  // interior nodes per thread
+  // elements of T in one group's LDS buffers (two buffers; phase A needs a 1-node halo)
+  static int lds_group(int degree) {
+    const int h = degree - 1 > 1 ? degree - 1 : 1;
+    return 2 * (TS + 2 * h) * (TS + 2 * h);
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NI; ++k) {
-    const int i = lt + k * kGroup;
-    Zi[k] = T(0);
-    Ri[k] = T(0);
-    if (valid && i < TS * TS) {
-      const int j = (i / TS + H) * RS + (i % TS + H);
-      Zi[k] = W0[j];
-      Ri[k] = W1[j];
-    }
+  static bool fits(int degree, int nx, int ntx, int ntiles) {
+    const int H = degree - 1;
+    return (TS + 2 * H) * (TS + 2 * H) <= NS * kThreads && ntx == (nx + TS - 1) / TS && ntiles == ntx * ntx;
   }
-  T* cur = W0;
-  T* nxt = W1;
-  for (int j = 1; j < degree; ++j) {
-    __syncthreads();  // reads of the buffer about to be overwritten are done
-    const T ca = ld_uniform(A.chebA, j), cb = ld_uniform(A.chebB, j);
+  __device__ static void origin(const ColView<T>& v, int t, int& x0, int& y0) {
+    x0 = (t % v.ntx) * TS;
+    y0 = (t / v.ntx) * TS;
+  }
+
+  // Chebyshev preconditioner on one tile. `rreg(gy * nx + gx)` gives r at grid
+  // node (gx, gy) of the region (only called inside the grid). On return Zi holds z and
+  // Ri holds r on this thread's interior nodes; returns the partial r.z.
+  template <typename RF>
+  __device__ static double cheb(const ColView<T>& A, int degree, int x0, int y0, RF rreg, T* W0, T* W1,
+                                T (&Zi)[NI], T (&Ri)[NI], GroupBarrier& gb) {
+    const int lt = threadIdx.x % kThreads;
+    const int H = degree - 1;
+    const int RS = TS + 2 * H;
+    const int nreg = RS * RS;
+    T S[NS];
+    // step 0: S = D^-1 r, W = S / theta; r parked in W1 for the interior mapping
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const int i = lt + s * kGroup;
-      if (valid && i < nreg) {
+      const int i = lt + s * kThreads;
+      S[s] = T(0);
+      if (i < nreg) {
         const int lx = i % RS, ly = i / RS;
-        if (lx >= j && lx < RS - j && ly >= j && ly < RS - j) {  // W_j is valid on [j, RS - j)
-          const int gx = x0 - H + lx, gy = y0 - H + ly;
-          T wn = T(0);
-          if (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) {
-            const T s8 = cur[i - RS - 1] + cur[i - RS] + cur[i - RS + 1] + cur[i - 1] + cur[i + 1] +
-                         cur[i + RS - 1] + cur[i + RS] + cur[i + RS + 1];
-            S[s] = S[s] - (cur[i] - T(0.125) * s8);
-            wn = ca * cur[i] + cb * S[s];
-          }
-          nxt[i] = wn;
-        }
+        const int gx = x0 - H + lx, gy = y0 - H + ly;
+        const T r = (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) ? rreg((unsigned)(gy * A.nx + gx)) : T(0);
+        S[s] = r * A.inv_diag;
+        W0[i] = S[s] * A.inv_theta;
+        W1[i] = r;
       }
     }
-    __syncthreads();
+    group_sync(gb);
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
-      const int i = lt + k * kGroup;
-      if (valid && i < TS * TS) Zi[k] += nxt[(i / TS + H) * RS + (i % TS + H)];
+      const int i = lt + k * kThreads;
+      Zi[k] = T(0);
+      Ri[k] = T(0);
+      if (i < TS * TS) {
+        const int j = (i / TS + H) * RS + (i % TS + H);
+        Zi[k] = W0[j];
+        Ri[k] = W1[j];
+      }
     }
-    T* t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  double rz = 0.0;
+    T* cur = W0;
+    T* nxt = W1;
+    for (int j = 1; j < degree; ++j) {
+      group_sync(gb);  // reads of the buffer about to be overwritten are done
+      const T ca = ld_uniform(A.chebA, j), cb = ld_uniform(A.chebB, j);
 #pragma unroll
-  for (int k = 0; k < NI; ++k) rz += (double)Ri[k] * (double)Zi[k];
-  return rz;
-}
+      for (int s = 0; s < NS; ++s) {
+        const int i = lt + s * kThreads;
+        if (i < nreg) {
+          const int lx = i % RS, ly = i / RS;
+          if (lx >= j && lx < RS - j && ly >= j && ly < RS - j) {  // W_j is valid on [j, RS - j)
+            const int gx = x0 - H + lx, gy = y0 - H + ly;
+            T wn = T(0);
+            if (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) {
+              const T s8 = cur[i - RS - 1] + cur[i - RS] + cur[i - RS + 1] + cur[i - 1] + cur[i + 1] +
+                           cur[i + RS - 1] + cur[i + RS] + cur[i + RS + 1];
+              S[s] = S[s] - (cur[i] - T(0.125) * s8);
+              wn = ca * cur[i] + cb * S[s];
+            }
+            nxt[i] = wn;
+          }
+        }
+      }
+      group_sync(gb);
+#pragma unroll
+      for (int k = 0; k < NI; ++k) {
+        const int i = lt + k * kThreads;
+        if (i < TS * TS) Zi[k] += nxt[(i / TS + H) * RS + (i % TS + H)];
+      }
+      T* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    double rz = 0.0;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) rz += (double)Ri[k] * (double)Zi[k];
+    return rz;
+  }
 
-template <typename T, int TS, int NS, int G, bool RAGGED>
-__global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, const PcgCols<T> C) {
-  constexpr int NI = Interior<TS>::NI;
+  // Start of the iteration: x = 0, z = M b; partials b.z and b.b.
+  __device__ static void start(const ColView<T>& v, int degree, int t, T* W0, T* W1, GroupBarrier& gb, double& rz,
+                               double& bb) {
+    const int lt = threadIdx.x % kThreads;
+    const int nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    T Zi[NI], Ri[NI];
+    auto rreg = [&](unsigned o) { return v.b[o]; };
+    rz = cheb(v, degree, x0, y0, rreg, W0, W1, Zi, Ri, gb);
+    bb = 0.0;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int i = lt + k * kThreads;
+      const int gx = x0 + i % TS, gy = y0 + i / TS;
+      if (i < TS * TS && gx < nx && gy < nx) {
+        const long g = (long)gy * nx + gx;
+        bb += (double)Ri[k] * (double)Ri[k];
+        v.x[g] = T(0);
+        v.z[g] = Zi[k];
+      }
+    }
+  }
+
+  // Phase A: p = z + beta p on the tile plus a 1-node halo, q = K_0 p; partial p.q.
+  __device__ static double phase_a(const ColView<T>& v, int t, const IterVecs<T>& I, T* W0, GroupBarrier& gb) {
+    const int lt = threadIdx.x % kThreads;
+    const int nx = v.nx;
+    constexpr int RS1 = TS + 2;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    for (int i = lt; i < RS1 * RS1; i += kThreads) {
+      const int gx = x0 - 1 + i % RS1, gy = y0 - 1 + i / RS1;
+      T val = T(0);
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < nx) {
+        const long g = (long)gy * nx + gx;
+        val = I.first ? v.z[g] : v.z[g] + I.beta * I.po[g];
+      }
+      W0[i] = val;
+    }
+    group_sync(gb);
+    double pq = 0.0;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int i = lt + k * kThreads;
+      const int lx = i % TS + 1, ly = i / TS + 1;
+      const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+      if (i < TS * TS && gx < nx && gy < nx) {
+        const int q = ly * RS1 + lx;
+        const T pc = W0[q];
+        const T s8 = W0[q - RS1 - 1] + W0[q - RS1] + W0[q - RS1 + 1] + W0[q - 1] + W0[q + 1] + W0[q + RS1 - 1] +
+                     W0[q + RS1] + W0[q + RS1 + 1];
+        const T qv = v.c0 * pc + v.c1 * s8;
+        const long g = (long)gy * nx + gx;
+        I.pn[g] = pc;
+        v.q[g] = qv;
+        pq += (double)pc * (double)qv;
+      }
+    }
+    return pq;
+  }
+
+  // Phase B: x += alpha p, r -= alpha q, z = M r; partials r.z and r.r.
+  __device__ static void phase_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, T* W0, T* W1,
+                                 GroupBarrier& gb, double& rz, double& rr) {
+    const int lt = threadIdx.x % kThreads;
+    const int nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    T Zi[NI], Ri[NI];
+    auto rreg = [&](unsigned o) { return I.ro[o] - I.alpha * v.q[o]; };
+    rz = cheb(v, degree, x0, y0, rreg, W0, W1, Zi, Ri, gb);
+    rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int i = lt + k * kThreads;
+      const int gx = x0 + i % TS, gy = y0 + i / TS;
+      if (i < TS * TS && gx < nx && gy < nx) {
+        const long g = (long)gy * nx + gx;
+        v.x[g] = I.first ? I.alpha * I.pn[g] : v.x[g] + I.alpha * I.pn[g];
+        I.rn[g] = Ri[k];
+        v.z[g] = Zi[k];
+        rr += (double)Ri[k] * (double)Ri[k];
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Banded tiles: tsx x TSY nodes. The region (tile plus halo) has one column
+// per lane (at most 64) and its rows are split into NW bands of BR rows, one
+// per wave of the group. LDS rows are 64 values apart, so a wave reads or writes one region
+// row with one conflict-free access. A stencil update takes the row above and
+// the row below from a sliding window (one LDS read per node) and the column
+// sums of the neighbouring lanes by DPP.
+// ---------------------------------------------------------------------------
+template <typename T, int TSY, int HMAX, int NW>
+struct BandTile {
+  static constexpr int kThreads = 64 * NW;
+  static constexpr int RYMAX = TSY + 2 * HMAX;
+  static constexpr int BR = (RYMAX + NW - 1) / NW;     // region rows per wave (Chebyshev)
+  static constexpr int BRA = (TSY + 2 + NW - 1) / NW;  // region rows per wave (phase A, halo 1)
+  static constexpr int RB = NW * BR;                   // rows of one LDS buffer (bands padded)
+  static constexpr int CH = 4;                         // rows per chunk of a sweep
+  static_assert(NW * BRA <= RB, "phase A rows exceed the buffer");
+  static int lds_group(int) { return 2 * RB * 64; }
+  static bool fits(int degree, int nx, int ntx, int ntiles) {
+    const int H = degree - 1;
+    if (H > HMAX || ntx < 1) return false;
+    const int tsx = (nx + ntx - 1) / ntx;
+    const int h = H > 1 ? H : 1;
+    return tsx + 2 * h <= 64 && ntiles == ntx * ((nx + TSY - 1) / TSY);
+  }
+  __device__ static void origin(const ColView<T>& v, int t, int& x0, int& y0) {
+    x0 = (t % v.ntx) * v.tsx;
+    y0 = (t / v.ntx) * TSY;
+  }
+
+  // Chebyshev preconditioner on one tile; Zi[r], Ri[r] hold z and r at row
+  // wave * BR + r of the region (zero outside the interior of the tile and
+  // outside the grid). Returns the partial r.z.
+  //
+  // Every sweep updates all rows and lanes of the band without branches, so
+  // the rows of a band overlap in the pipeline. Values outside the part of
+  // the region where W_j is valid ([j, R - j) in both directions) are
+  // meaningless but never reach a valid value: a valid node of sweep j + 1
+  // reads only nodes valid in sweep j. Nodes outside the grid hold zero.
+  // `inner(o)` runs once per interior grid node of the tile (offset o) at step
+  // 0, so that its memory accesses overlap those of the region.
+  template <typename RF, typename IF>
+  __device__ static double cheb(const ColView<T>& A, int degree, int x0, int y0, RF rreg, IF inner, T* W0, T* W1,
+                                T (&Zi)[BR], T (&Ri)[BR], GroupBarrier& gb) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    const int H = degree - 1;
+    const int tsx = A.tsx, nx = A.nx;
+    const int RX = tsx + 2 * H, RY = TSY + 2 * H;
+    const int gx = x0 - H + lane;
+    const bool xin = lane < RX && gx >= 0 && gx < nx;          // lane holds a grid column
+    const bool xint = lane >= H && lane < H + tsx && gx < nx;  // interior column of the tile
+    const int yb = wv * BR;                                    // first region row of this wave
+    T S[BR];
+    // step 0: S = D^-1 r, W = S / theta
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int ly = yb + r;
+      const int gy = y0 - H + ly;
+      const bool in = xin && ly < RY && gy >= 0 && gy < nx;
+      T rv = T(0);
+      if (in) rv = rreg((unsigned)(gy * nx + gx));
+      S[r] = rv * A.inv_diag;
+      const T w0 = S[r] * A.inv_theta;
+      W0[ly * 64 + lane] = w0;
+      const bool interior = xint && ly >= H && ly < H + TSY;
+      if (interior && gy < nx) inner((unsigned)(gy * nx + gx));
+      Zi[r] = interior ? w0 : T(0);
+      Ri[r] = interior ? rv : T(0);
+    }
+    T* cur = W0;
+    T* nxt = W1;
+    for (int j = 1; j < degree; ++j) {
+      // all rows of cur are written and every read of nxt (the older buffer) is done
+      group_sync(gb);
+      const T ca = ld_uniform(A.chebA, j), cb = ld_uniform(A.chebB, j);
+      T cm = cur[(yb > 0 ? yb - 1 : 0) * 64 + lane];
+      T c0 = cur[yb * 64 + lane];
+      // rows in chunks of CH: the reads of a chunk are issued together (the
+      // compiler keeps them behind the previous chunk's writes, since it
+      // cannot tell that cur and nxt do not overlap)
+#pragma unroll
+      for (int r0 = 0; r0 < BR; r0 += CH) {
+        T cpv[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int ly = yb + r0 + k;
+          cpv[k] = r0 + k < BR ? cur[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int r = r0 + k;
+          if (r >= BR) break;
+          const int ly = yb + r;
+          const T cp = cpv[k];
+          const T col = (cm + c0) + cp;
+          const T s8 = (from_prev(col) + from_next(col)) + (cm + cp);
+          const int gy = y0 - H + ly;
+          const bool upd = xin && gy >= 0 && gy < nx;
+          const T sn = S[r] - (c0 - T(0.125) * s8);
+          S[r] = upd ? sn : S[r];
+          const T wn = upd ? ca * c0 + cb * sn : T(0);
+          nxt[ly * 64 + lane] = wn;
+          if (xint && ly >= H && ly < H + TSY) Zi[r] += wn;
+          cm = c0;
+          c0 = cp;
+        }
+      }
+      T* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    double rz = 0.0;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) rz += (double)Ri[r] * (double)Zi[r];
+    return rz;
+  }
+
+  __device__ static void start(const ColView<T>& v, int degree, int t, T* W0, T* W1, GroupBarrier& gb, double& rz,
+                               double& bb) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    const int H = degree - 1, nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    T Zi[BR], Ri[BR];
+    auto rreg = [&](unsigned o) { return v.b[o]; };
+    auto inner = [&](unsigned o) { v.x[o] = T(0); };
+    rz = cheb(v, degree, x0, y0, rreg, inner, W0, W1, Zi, Ri, gb);
+    bb = 0.0;
+    const int gx = x0 - H + lane;
+    const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int ly = wv * BR + r;
+      const int gy = y0 - H + ly;
+      if (xint && ly >= H && ly < H + TSY && gy < nx) {
+        const unsigned o = (unsigned)(gy * nx + gx);
+        bb += (double)Ri[r] * (double)Ri[r];
+        v.z[o] = Zi[r];
+      }
+    }
+  }
+
+  __device__ static double phase_a(const ColView<T>& v, int t, const IterVecs<T>& I, T* W0, GroupBarrier& gb) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    const int nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    const int RX = v.tsx + 2;
+    const int gx = x0 - 1 + lane;
+    const bool xin = lane < RX && gx >= 0 && gx < nx;
+    const bool xint = lane >= 1 && lane <= v.tsx && gx < nx;
+    const int yb = wv * BRA;
+    T pc[BRA];
+#pragma unroll
+    for (int r = 0; r < BRA; ++r) {
+      const int ly = yb + r;
+      const int gy = y0 - 1 + ly;
+      pc[r] = T(0);
+      if (xin && ly < TSY + 2 && gy >= 0 && gy < nx) {
+        const unsigned o = (unsigned)(gy * nx + gx);
+        pc[r] = I.first ? v.z[o] : v.z[o] + I.beta * I.po[o];
+      }
+      W0[ly * 64 + lane] = pc[r];
+    }
+    group_sync(gb);
+    double pq = 0.0;
+#pragma unroll
+    for (int r = 0; r < BRA; ++r) {
+      const int ly = yb + r;
+      const T cm = W0[(ly > 0 ? ly - 1 : 0) * 64 + lane];
+      const T cp = W0[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane];
+      const T col = (cm + pc[r]) + cp;
+      const T s8 = (from_prev(col) + from_next(col)) + (cm + cp);
+      const T qv = v.c0 * pc[r] + v.c1 * s8;
+      const int gy = y0 - 1 + ly;
+      if (xint && ly >= 1 && ly <= TSY && gy < nx) {
+        const unsigned o = (unsigned)(gy * nx + gx);
+        I.pn[o] = pc[r];
+        v.q[o] = qv;
+        pq += (double)pc[r] * (double)qv;
+      }
+    }
+    return pq;
+  }
+
+  __device__ static void phase_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, T* W0, T* W1,
+                                 GroupBarrier& gb, double& rz, double& rr) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    const int H = degree - 1, nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    T Zi[BR], Ri[BR];
+    auto rreg = [&](unsigned o) { return I.ro[o] - I.alpha * v.q[o]; };
+    auto inner = [&](unsigned o) { v.x[o] = I.first ? I.alpha * I.pn[o] : v.x[o] + I.alpha * I.pn[o]; };
+    rz = cheb(v, degree, x0, y0, rreg, inner, W0, W1, Zi, Ri, gb);
+    rr = 0.0;
+    const int gx = x0 - H + lane;
+    const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int ly = wv * BR + r;
+      const int gy = y0 - H + ly;
+      if (xint && ly >= H && ly < H + TSY && gy < nx) {
+        const unsigned o = (unsigned)(gy * nx + gx);
+        I.rn[o] = Ri[r];
+        v.z[o] = Zi[r];
+        rr += (double)Ri[r] * (double)Ri[r];
+      }
+    }
+  }
+};
+
+// Tile routines end with a group reduction (two group barriers after the last
+// LDS access of the tile), so the next tile of the group may overwrite the
+// group's buffers without a further barrier.
+template <typename T, typename Tile, int G, bool RAGGED>
+__global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T> A, const PcgCols<T> C,
+                                                                int lds_group) {
+  constexpr int GT = Tile::kThreads;
   extern __shared__ unsigned char smem_raw[];
-  const int grp = threadIdx.x / kGroup;
-  const int lt = threadIdx.x % kGroup;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / GT);  // uniform per wave
+  const int lt = threadIdx.x % GT;
   const int degree = A.degree;
-  const int H = degree - 1;
-  const int RSa = TS + 2 * (H > 1 ? H : 1);  // phase A needs a 1-node halo
-  const int CAP = RSa * RSa;
-  T* W0 = reinterpret_cast<T*>(smem_raw) + (long)grp * 2 * CAP;
-  T* W1 = W0 + CAP;
+  T* W0 = reinterpret_cast<T*>(smem_raw) + (long)grp * lds_group;
+  T* W1 = W0 + lds_group / 2;
   // per-column done flags of this block's columns, after the tile buffers
-  int* sdone = reinterpret_cast<int*>(reinterpret_cast<T*>(smem_raw) + (long)G * 2 * CAP);
-  __shared__ double sred[G][4];
+  int* sdone = reinterpret_cast<int*>(reinterpret_cast<T*>(smem_raw) + (long)G * lds_group);
+  __shared__ double sred[G][GT / 64][2];
   __shared__ double s4[4];
   __shared__ int sflag;
+  __shared__ unsigned sgbar[G];
+  if (threadIdx.x < G) sgbar[threadIdx.x] = 0u;
+  GroupBarrier gb{&sgbar[grp], 0u, GT / 64, A.sc.status, false};
 
   // a compacted ragged launch covers the listed columns only; scratch is indexed by list position
   const bool listed = RAGGED && C.act != nullptr;
@@ -252,6 +643,7 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
       v.chebA = A.chebA;
       v.chebB = A.chebB;
     }
+    v.tsx = (v.nx + v.ntx - 1) / v.ntx;
     return v;
   };
   // column holding work index w
@@ -294,11 +686,7 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
     }
     __syncthreads();
   };
-  auto tile_xy = [&](const ColView<T>& v, int t, int& x0, int& y0) {
-    x0 = (t % v.ntx) * TS;
-    y0 = (t / v.ntx) * TS;
-  };
-  for (int c = c_first + (int)threadIdx.x; c <= c_last; c += kGroup * G) {
+  for (int c = c_first + (int)threadIdx.x; c <= c_last; c += GT * G) {
     int skip = 0;
     if constexpr (RAGGED) {
       if (!listed) skip = C.active[C.prob[c]] == 0;
@@ -306,8 +694,6 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
     sdone[c - c_first] = skip;
   }
   __syncthreads();
-
-  T Zi[NI], Ri[NI];
 
   // ---- start (column phase 1): x = 0, z = M b, partials b.b and b.z
   for (int c = c_first; c <= c_last; ++c) {
@@ -319,30 +705,11 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
     int t0, t1;
     tiles_of(v, t0, t1);
     if (t1 <= t0) continue;
-    const int nx = v.nx;
-    for (int tb = t0; tb < t1; tb += G) {
-      const int t = tb + grp;
-      const bool valid = t < t1;
-      int x0 = 0, y0 = 0;
-      if (valid) tile_xy(v, t, x0, y0);
-      __syncthreads();
-      auto rreg = [&](int lx, int ly) { return v.b[(long)(y0 - H + ly) * nx + (x0 - H + lx)]; };
-      double rz = cheb_tile<T, TS, NS>(v, degree, valid, x0, y0, rreg, W0, W1, Zi, Ri);
-      double bb = 0.0;
-#pragma unroll
-      for (int k = 0; k < NI; ++k) {
-        const int i = lt + k * kGroup;
-        const int gx = x0 + i % TS, gy = y0 + i / TS;
-        if (valid && i < TS * TS && gx < nx && gy < nx) {
-          const long g = (long)gy * nx + gx;
-          bb += (double)Ri[k] * (double)Ri[k];
-          v.x[g] = T(0);
-          v.z[g] = Zi[k];
-        }
-      }
-      rz = group_sum<G>(rz, sred);
-      bb = group_sum<G>(bb, sred);
-      if (valid && lt == 0) {
+    for (int t = t0 + grp; t < t1; t += G) {
+      double rz, bb;
+      Tile::start(v, degree, t, W0, W1, gb, rz, bb);
+      group_sum2<GT>(rz, bb, sred, gb);
+      if (lt == 0) {
         P(PART_RZ1)[v.tbase + t] = rz;
         P(PART_BB)[v.tbase + t] = bb;
       }
@@ -378,52 +745,16 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
         __syncthreads();
         continue;
       }
-      const T beta = it == 0 ? T(0) : (T)(s4[2] / s4[3]);
       any_active = true;
-      const int nx = v.nx;
-      const T* zc = v.z;
-      const T* po = par ? v.p0 : v.p1;
-      T* pn = par ? v.p1 : v.p0;
-      T* qc = v.q;
-      const int RS1 = TS + 2;
-      for (int tb = t0; tb < t1; tb += G) {
-        const int t = tb + grp;
-        const bool valid = t < t1;
-        int x0 = 0, y0 = 0;
-        if (valid) tile_xy(v, t, x0, y0);
-        __syncthreads();
-        if (valid) {
-          for (int i = lt; i < RS1 * RS1; i += kGroup) {
-            const int gx = x0 - 1 + i % RS1, gy = y0 - 1 + i / RS1;
-            T val = T(0);
-            if (gx >= 0 && gx < nx && gy >= 0 && gy < nx) {
-              const long g = (long)gy * nx + gx;
-              val = it == 0 ? zc[g] : zc[g] + beta * po[g];
-            }
-            W0[i] = val;
-          }
-        }
-        __syncthreads();
-        double pq = 0.0;
-#pragma unroll
-        for (int k = 0; k < NI; ++k) {
-          const int i = lt + k * kGroup;
-          const int lx = i % TS + 1, ly = i / TS + 1;
-          const int gx = x0 + lx - 1, gy = y0 + ly - 1;
-          if (valid && i < TS * TS && gx < nx && gy < nx) {
-            const int q = ly * RS1 + lx;
-            const T pc = W0[q];
-            const T s8 = W0[q - RS1 - 1] + W0[q - RS1] + W0[q - RS1 + 1] + W0[q - 1] + W0[q + 1] +
-                         W0[q + RS1 - 1] + W0[q + RS1] + W0[q + RS1 + 1];
-            const T qv = v.c0 * pc + v.c1 * s8;
-            const long g = (long)gy * nx + gx;
-            pn[g] = pc;
-            qc[g] = qv;
-            pq += (double)pc * (double)qv;
-          }
-        }
-        pq = group_sum<G>(pq, sred);
-        if (valid && lt == 0) P(PART_PQ)[v.tbase + t] = pq;
+      IterVecs<T> I{};
+      I.first = it == 0;
+      I.beta = it == 0 ? T(0) : (T)(s4[2] / s4[3]);
+      I.po = par ? v.p0 : v.p1;
+      I.pn = par ? v.p1 : v.p0;
+      for (int t = t0 + grp; t < t1; t += G) {
+        double pq = Tile::phase_a(v, t, I, W0, gb), unused = 0.0;
+        group_sum2<GT>(pq, unused, sred, gb);
+        if (lt == 0) P(PART_PQ)[v.tbase + t] = pq;
       }
       column_arrive(arr + c, (unsigned)(t1 - t0));
     }
@@ -451,41 +782,17 @@ __global__ void __launch_bounds__(kGroup* G) pcg_kernel(const PcgArgs<T> A, cons
         __syncthreads();
         continue;
       }
-      const T alpha = (T)(gam / pq);
-      const int nx = v.nx;
-      const T* pc = par ? v.p1 : v.p0;
-      const T* qc = v.q;
-      const T* ro = it == 0 ? v.b : (par ? v.r1 : v.r0);
-      T* rn = par ? v.r0 : v.r1;
-      T* xc = v.x;
-      T* zc = v.z;
-      for (int tb = t0; tb < t1; tb += G) {
-        const int t = tb + grp;
-        const bool valid = t < t1;
-        int x0 = 0, y0 = 0;
-        if (valid) tile_xy(v, t, x0, y0);
-        __syncthreads();
-        auto rreg = [&](int lx, int ly) {
-          const long g = (long)(y0 - H + ly) * nx + (x0 - H + lx);
-          return ro[g] - alpha * qc[g];
-        };
-        double rz = cheb_tile<T, TS, NS>(v, degree, valid, x0, y0, rreg, W0, W1, Zi, Ri);
-        double rr = 0.0;
-#pragma unroll
-        for (int k = 0; k < NI; ++k) {
-          const int i = lt + k * kGroup;
-          const int gx = x0 + i % TS, gy = y0 + i / TS;
-          if (valid && i < TS * TS && gx < nx && gy < nx) {
-            const long g = (long)gy * nx + gx;
-            xc[g] = it == 0 ? alpha * pc[g] : xc[g] + alpha * pc[g];
-            rn[g] = Ri[k];
-            zc[g] = Zi[k];
-            rr += (double)Ri[k] * (double)Ri[k];
-          }
-        }
-        rz = group_sum<G>(rz, sred);
-        rr = group_sum<G>(rr, sred);
-        if (valid && lt == 0) {
+      IterVecs<T> I{};
+      I.first = it == 0;
+      I.alpha = (T)(gam / pq);
+      I.pn = par ? v.p1 : v.p0;
+      I.ro = it == 0 ? v.b : (par ? v.r1 : v.r0);
+      I.rn = par ? v.r0 : v.r1;
+      for (int t = t0 + grp; t < t1; t += G) {
+        double rz, rr;
+        Tile::phase_b(v, degree, t, I, W0, W1, gb, rz, rr);
+        group_sum2<GT>(rz, rr, sred, gb);
+        if (lt == 0) {
           P(par ? PART_RZ1 : PART_RZ0)[v.tbase + t] = rz;
           P(par ? PART_RR1 : PART_RR0)[v.tbase + t] = rr;
         }
@@ -507,13 +814,12 @@ __global__ void pcg_reset_kernel(unsigned* arr, int ncols, int* status) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
 }
 
-template <typename T, int TS, int NS, int G, bool RAGGED>
+template <typename T, typename Tile, int G, bool RAGGED>
 hipError_t launch_cfg(const PcgArgs<T>& args, const PcgCols<T>& cols, int max_blocks, hipStream_t s) {
-  const int H = args.degree - 1;
-  const int RSa = TS + 2 * (H > 1 ? H : 1);
-  if ((TS + 2 * H) * (TS + 2 * H) > NS * kGroup) return hipErrorInvalidValue;
-  const size_t tiles_bytes = sizeof(T) * 2 * (size_t)RSa * RSa * G;
-  auto kfn = pcg_kernel<T, TS, NS, G, RAGGED>;
+  if (!RAGGED && !Tile::fits(args.degree, args.nx, args.ntx, args.ntiles)) return hipErrorInvalidValue;
+  const int lds_group = Tile::lds_group(args.degree);
+  const size_t tiles_bytes = sizeof(T) * (size_t)lds_group * G;
+  auto kfn = pcg_kernel<T, Tile, G, RAGGED>;
   const long nwork = RAGGED ? cols.nwork : (long)args.ncols * args.ntiles;
   if (nwork <= 0) return hipSuccess;
   int dev = 0;
@@ -540,7 +846,7 @@ hipError_t launch_cfg(const PcgArgs<T>& args, const PcgCols<T>& cols, int max_bl
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kGroup * G, sm);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, Tile::kThreads * G, sm);
     if (e != hipSuccess) return e;
     const long cap = (long)per_cu * ncu;
     if (cap < 1) return hipErrorInvalidValue;
@@ -550,27 +856,35 @@ hipError_t launch_cfg(const PcgArgs<T>& args, const PcgCols<T>& cols, int max_bl
   }
   PcgArgs<T> a = args;
   PcgCols<T> c = cols;
+  int lg = lds_group;
   hipLaunchKernelGGL(pcg_reset_kernel, dim3(1), dim3(256), 0, s, a.sc.arrivals, a.ncols, a.sc.status);
   if (!RAGGED) {
-    void* kargs[] = {&a, &c};
+    void* kargs[] = {&a, &c, &lg};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3((unsigned)grid),
-                                      dim3(kGroup * G), kargs, (unsigned)sm, s);
+                                      dim3(Tile::kThreads * G), kargs, (unsigned)sm, s);
   }
-  hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(kGroup * G), sm, s, a, c);
+  hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(Tile::kThreads * G), sm, s, a, c, lg);
   return hipGetLastError();
 }
 
-constexpr int slots(int ts, int maxh) { return ((ts + 2 * maxh) * (ts + 2 * maxh) + kGroup - 1) / kGroup; }
+constexpr int slots(int ts, int maxh) {
+  return ((ts + 2 * maxh) * (ts + 2 * maxh) + kSquareGroup - 1) / kSquareGroup;
+}
 
 template <typename T, bool RAGGED>
 hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile, int max_blocks, hipStream_t s) {
   if (args.ncols <= 0) return hipSuccess;
   const int H = args.degree - 1;
-  if (tile == 32) {
-    if (H <= 3) return launch_cfg<T, 32, slots(32, 3), 4, RAGGED>(args, cols, max_blocks, s);
-    if (H <= 7) return launch_cfg<T, 32, slots(32, 7), 3, RAGGED>(args, cols, max_blocks, s);
+  if (tile != 16) {
+    // banded tiles: FP64 in two groups of eight waves per block, FP32 in four
+    // groups of four waves (measured fastest for each)
+    constexpr int NW = sizeof(T) == 8 ? 8 : 4;
+    constexpr int G = sizeof(T) == 8 ? 2 : 4;
+    if (H <= 3) return launch_cfg<T, BandTile<T, kBandRows, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
+    if (H <= 7) return launch_cfg<T, BandTile<T, kBandRows, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);
+    return hipErrorInvalidValue;
   }
-  return launch_cfg<T, 16, slots(16, 15), 4, RAGGED>(args, cols, max_blocks, s);
+  return launch_cfg<T, SquareTile<T, 16, slots(16, 15)>, 4, RAGGED>(args, cols, max_blocks, s);
 }
 
 }  // namespace

@@ -105,24 +105,6 @@ __global__ void __launch_bounds__(256) sgop_kernel(const SgOpArgs<T> A) {
 #endif
 constexpr int kStripR = SG_STRIP_R;
 
-__device__ __forceinline__ int dpp_from_next(int v) {  // lane i receives lane i + 1
-  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true);
-}
-__device__ __forceinline__ int dpp_from_prev(int v) {  // lane i receives lane i - 1
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);
-}
-__device__ __forceinline__ double from_next(double v) {
-  const int lo = dpp_from_next(__double2loint(v));
-  const int hi = dpp_from_next(__double2hiint(v));
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double from_prev(double v) {
-  const int lo = dpp_from_prev(__double2loint(v));
-  const int hi = dpp_from_prev(__double2hiint(v));
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float from_next(float v) { return __int_as_float(dpp_from_next(__float_as_int(v))); }
-__device__ __forceinline__ float from_prev(float v) { return __int_as_float(dpp_from_prev(__float_as_int(v))); }
 
 // Node values of column gx for node rows gy0 .. gy0 + R + 1 (grid coordinates; zero outside).
 template <typename T, int R>

@@ -122,14 +122,14 @@ int make_batch_plan(int count, const sg_problem* probs, const sg_opts* op, Batch
   bp.set_nwork.assign(pmax + 2, 0);
   for (int b = 0; b < count; ++b) {
     const std::vector<int> off = level_offsets(probs[b].M, probs[b].p);
-    const long nx = probs[b].n_e - 1;
-    const long ntx = (nx + tile - 1) / tile;
+    int ntx = 0, nt = 0;
+    sgk::pcg_tiling(probs[b].n_e - 1, op->cheb_degree, tile, ntx, nt);
     for (int l = 0; l <= probs[b].p; ++l) {
       bp.set_ncols[l] += off[l + 1] - off[l];
-      bp.set_nwork[l] += (long)(off[l + 1] - off[l]) * ntx * ntx;
+      bp.set_nwork[l] += (long)(off[l + 1] - off[l]) * nt;
     }
     bp.set_ncols[pmax + 1] += off.back();
-    bp.set_nwork[pmax + 1] += (long)off.back() * ntx * ntx;
+    bp.set_nwork[pmax + 1] += (long)off.back() * nt;
   }
   for (int s = 0; s <= pmax + 1; ++s) {
     bp.ncols_max = std::max<long>(bp.ncols_max, bp.set_ncols[s]);
@@ -174,16 +174,17 @@ int build_set(sg_batch_ctx* B, int s, char* base, std::vector<char>& host, sgk::
       j1 = h->P;
     }
     const long n = h->n;
-    const int t = (h->nx + B->tile - 1) / B->tile;
+    int t = 0, nt = 0;
+    sgk::pcg_tiling(h->nx, B->degree, B->tile, t, nt);
     T* rw = (T*)h->rw;
     T* zw = B->inner == 32 ? (T*)h->zw : (T*)h->z;
     for (int j = j0; j < j1; ++j) {
       const long slot = j - j0;
       nx.push_back(h->nx);
       ntx.push_back(t);
-      ntiles.push_back(t * t);
+      ntiles.push_back(nt);
       tbase.push_back(w);
-      w += (long)t * t;
+      w += nt;
       prob.push_back(b);
       pb.push_back(rw + (long)j * n);
       px.push_back(zw + (long)j * n);
@@ -479,6 +480,7 @@ int sg_batch_setup(int32_t count, const sg_problem* probs, const sg_opts* opts, 
       c.active = V.active;
       B->cols64.push_back(c);
     }
+    if (rc == SG_OK && nwork > bp.set_nwork[s]) rc = fail(SG_EINVAL, "inner tiling exceeds the planned work list");
     if (rc) {
       sg_batch_destroy(B);
       return rc;

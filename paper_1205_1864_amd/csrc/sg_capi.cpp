@@ -368,8 +368,8 @@ template void fill_pcg_consts<float>(const sg_ctx*, sgk::PcgArgs<float>&);
 int effective_degree(const sg_ctx* h) { return h->lmax - h->lmin > 0.0 ? h->opts.cheb_degree : 1; }
 
 int choose_tile(const sg_ctx* h, int degree) {
-  // 32 x 32 tiles (four per block up to degree 4, two up to degree 8); the
-  // halo of larger degrees makes 16 x 16 tiles the better choice.
+  // banded tiles (code 32) up to degree 8; the halo of larger degrees does not
+  // fit one wavefront, so they take 16 x 16 tiles
   if (h->opts.tile == 16) return 16;
   return degree <= 8 ? 32 : 16;
 }
@@ -394,8 +394,7 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.Q = (T*)h->pQ;
   a.Z = (T*)h->pZ;
   a.sc = h->pcgsc;
-  a.ntx = (h->nx + tile - 1) / tile;
-  a.ntiles = a.ntx * a.ntx;
+  sgk::pcg_tiling(h->nx, degree, tile, a.ntx, a.ntiles);
   a.degree = degree;
   a.maxit = h->opts.inner_maxit;
   a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;

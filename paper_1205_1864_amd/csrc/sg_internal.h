@@ -15,6 +15,24 @@ constexpr int kMaxCheb = 16;     // largest supported Chebyshev degree
 constexpr int kMaxLevels = 16;   // largest supported chaos degree + 1
 constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 
+// Tiles of the inner PCG on an nx x nx grid. tile == 16: square 16 x 16 tiles.
+// Otherwise banded tiles of tsx x kBandRows nodes, tsx = ceil(nx / ntx), sized
+// so that the tile plus its Chebyshev halo (degree - 1 nodes, at least one)
+// spans at most one wavefront of 64 columns. Tiles are numbered row-major:
+// tile t covers columns (t % ntx) * tsx ... and rows (t / ntx) * tile height ...
+constexpr int kBandRows = 32;
+inline void pcg_tiling(int nx, int degree, int tile, int& ntx, int& ntiles) {
+  if (tile == 16) {
+    ntx = (nx + 15) / 16;
+    ntiles = ntx * ntx;
+    return;
+  }
+  const int h = degree - 1 > 1 ? degree - 1 : 1;
+  const int wmax = 64 - 2 * h;
+  ntx = (nx + wmax - 1) / wmax;
+  ntiles = ntx * ((nx + kBandRows - 1) / kBandRows);
+}
+
 // Chaos neighbour lists of the Hermite Galerkin matrices G_k (k >= 1): for
 // each chaos row a, the entries (k, b, g) with (G_k)_{ab} = g != 0 split into
 // lower neighbours (b = a - e_k, g = sqrt(a_k)) and upper neighbours
