@@ -1,11 +1,21 @@
-"""Hermite polynomial chaos (Section 2, eq. (gPC-u), eq. (global-system)).
+"""Polynomial chaos (Section 2, eq. (gPC-u), eq. (global-system)).
 
 The chaos basis is the tensor product of univariate polynomials of total
-degree at most p in M standard Gaussian variables; there are
-``(M + p)! / (M! p!)`` of them (Section 2). The basis is normalised,
-``psi_a = prod_k He_{a_k}(xi_k) / sqrt(a_k!)`` (probabilists' Hermite), so
-``E[psi_a psi_b] = delta_ab`` and every diagonal block of the global matrix
-is exactly K_0.
+degree at most p in M independent variables; there are
+``(M + p)! / (M! p!)`` of them (Section 2). Two families:
+
+* ``"hermite"``: standard Gaussian variables and the normalised probabilists'
+  Hermite polynomials ``He_a(xi) / sqrt(a!)``;
+* ``"legendre"``: variables uniform on ``[-1, 1]`` and the normalised
+  Legendre polynomials ``sqrt(2a + 1) P_a(xi)`` (Section 2; the examples of
+  Section 7). Reading: the support [-1, 1] is the one under which the
+  paper's remark that ellipticity is no longer guaranteed above a
+  coefficient of variation of 55 % holds for its setup, and it reproduces
+  the iteration counts and condition estimates of its Tables 1-4 (a test
+  pins this); CoV = sigma / theta0 is then a nominal value.
+
+Both bases are orthonormal, ``E[psi_a psi_b] = delta_ab``, so every diagonal
+block of the global matrix is exactly K_0.
 
 Ordering reading: indices are graded by total degree (the level structure of
 Section 3 needs degree-l functions to follow all lower degrees); within one
@@ -18,7 +28,9 @@ import math
 from functools import lru_cache
 
 import numpy as np
-from numpy.polynomial import hermite_e
+from numpy.polynomial import hermite_e, legendre
+
+FAMILIES = ("hermite", "legendre")
 
 
 def multi_indices(M: int, p: int) -> np.ndarray:
@@ -62,19 +74,38 @@ def he(a: int, x: np.ndarray) -> np.ndarray:
     return hermite_e.hermeval(x, c)
 
 
-def normalized_moment(exponent: int, a: int, b: int) -> float:
-    """E[xi^exponent psi_a(xi) psi_b(xi)] for the 1D normalised Hermite basis.
+@lru_cache(maxsize=None)
+def _gauss_legendre(nq: int):
+    t, w = legendre.leggauss(nq)
+    return t, w / w.sum()
 
-    Gauss-Hermite quadrature (probability-normalised weights) with enough
-    points to integrate the polynomial of degree exponent + a + b exactly.
+
+def normalized_legendre(a: int, xi: np.ndarray) -> np.ndarray:
+    """sqrt(2a + 1) P_a(xi): orthonormal for xi uniform on [-1, 1]."""
+    c = np.zeros(a + 1)
+    c[a] = 1.0
+    return math.sqrt(2 * a + 1) * legendre.legval(np.asarray(xi), c)
+
+
+def normalized_moment(exponent: int, a: int, b: int, family: str = "hermite") -> float:
+    """E[xi^exponent psi_a(xi) psi_b(xi)] for the 1D normalised basis of a family.
+
+    Gauss quadrature of the family's own measure (probability-normalised
+    weights) with enough points to integrate the polynomial of degree
+    exponent + a + b exactly.
     """
     nq = (exponent + a + b) // 2 + 2
-    x, w = _gauss_hermite(nq)
-    val = np.sum(w * x ** exponent * he(a, x) * he(b, x))
-    return float(val / math.sqrt(math.factorial(a) * math.factorial(b)))
+    if family == "hermite":
+        x, w = _gauss_hermite(nq)
+        val = np.sum(w * x ** exponent * he(a, x) * he(b, x))
+        return float(val / math.sqrt(math.factorial(a) * math.factorial(b)))
+    if family == "legendre":
+        x, w = _gauss_legendre(nq)
+        return float(np.sum(w * x ** exponent * normalized_legendre(a, x) * normalized_legendre(b, x)))
+    raise ValueError(family)
 
 
-def galerkin_matrices(M: int, p: int, snap: float = 1e-12):
+def galerkin_matrices(M: int, p: int, snap: float = 1e-12, family: str = "hermite"):
     """G_0..G_M with (G_k)_{ab} = E[xi_k psi_a psi_b], xi_0 = 1 (eq. (global-system)).
 
     The expectation factorises over the independent variables: the factor of
@@ -92,7 +123,7 @@ def galerkin_matrices(M: int, p: int, snap: float = 1e-12):
     m1 = np.zeros((p + 1, p + 1))
     for a in range(p + 1):
         for b in range(a, p + 1):
-            m1[a, b] = m1[b, a] = normalized_moment(1, a, b)
+            m1[a, b] = m1[b, a] = normalized_moment(1, a, b, family)
     Gs = []
     for k in range(M + 1):
         G = np.ones((P, P))

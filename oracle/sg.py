@@ -47,7 +47,8 @@ def build_system(problem) -> SGSystem:
 
     K_0 is the stiffness of the mean coefficient theta0; K_k (k >= 1) is the
     stiffness of the KL term sigma * s_k * phi_k (eq. (KL-expansion) with
-    k_i = sqrt(lambda_i) v_i, scaled by sigma).
+    k_i = sqrt(lambda_i) v_i, scaled by sigma). The G_k belong to the
+    problem's chaos family (Hermite if the problem names none).
     """
     n_e, M, p = problem.n_e, problem.M, problem.p
     K = [fe.assemble_stiffness(np.full((n_e, n_e), problem.theta0), n_e)]
@@ -55,9 +56,10 @@ def build_system(problem) -> SGSystem:
     for k in range(M):
         K.append(fe.assemble_stiffness(problem.sigma * problem.s[k] * problem.phi[k], n_e))
         K_phi.append(fe.assemble_stiffness(problem.sigma * problem.phi[k], n_e))
+    family = getattr(problem, "family", "hermite")
     return SGSystem(
         n_e=n_e, M=M, p=p, theta0=problem.theta0, K=K,
-        G=chaos.galerkin_matrices(M, p), alpha=chaos.multi_indices(M, p),
+        G=chaos.galerkin_matrices(M, p, family=family), alpha=chaos.multi_indices(M, p),
         off=chaos.level_offsets(M, p), K_phi=K_phi,
     )
 

@@ -19,7 +19,10 @@ Conventions shared by every consumer:
 * element ``(ex, ey)``, ``0 <= ex, ey < n_e``, has corners
   ``(ex, ey) .. (ex + 1, ey + 1)``; element arrays are ``[ey, ex]``;
 * the coefficient is ``a(x, xi) = theta0 + sigma * sum_k s_k phi_k(x) xi_k``
-  with ``s_k = sqrt(lambda_k)`` and ``xi_k`` i.i.d. standard Gaussian;
+  with ``s_k = sqrt(lambda_k)`` and ``xi_k`` i.i.d.: standard Gaussian
+  (``family = "hermite"``, the default) or uniform on ``[-1, 1]``
+  (``family = "legendre"``, the paper's examples; sigma is then the nominal
+  coefficient of variation);
 * a block of chaos coefficients is stored as an array of shape ``(P, n)``:
   row ``j`` is the nodal vector of chaos coefficient ``j`` (column-major
   ``n x P``, the paper's stacked vector ``[u_0; ...; u_M]``).
@@ -31,7 +34,7 @@ import math
 from dataclasses import dataclass, field
 
 import numpy as np
-from numpy.polynomial import hermite_e
+from numpy.polynomial import hermite_e, legendre
 
 
 def n_chaos(M: int, p: int) -> int:
@@ -52,6 +55,7 @@ class Problem:
     phi: np.ndarray          # (M, n_e, n_e) element values of the KL modes, [k, ey, ex]
     f_nodal: np.ndarray      # (n,) f at the interior nodes
     modes: list = field(default_factory=list)  # (i, j) 1D mode pairs of each KL term
+    family: str = "hermite"  # distribution of xi and chaos family: "hermite" or "legendre"
 
     @property
     def n(self) -> int:
@@ -80,19 +84,26 @@ class Problem:
         return self.sigma * self.s[:, None, None] * self.phi
 
     def coefficient_margin(self) -> float:
-        """Exact lower bound of the element chaos matrices theta0 I + sum_k a_k(e) G_k.
+        """Lower bound of the element chaos matrices theta0 I + sum_k a_k(e) G_k.
 
-        By rotation invariance of the Gaussian measure, the total-degree-p
-        chaos space is mapped onto itself by orthogonal changes of xi, so the
-        extreme eigenvalue of multiplication by ``sum_k a_k xi_k`` on it is
-        ``||a||_2`` times the largest zero of He_{p+1}. If the returned margin
-        is positive every element matrix is SPD, hence the global SG matrix is
-        SPD. Uses only the Gauss-Hermite nodes of a library routine.
+        Hermite (exact): by rotation invariance of the Gaussian measure, the
+        total-degree-p chaos space is mapped onto itself by orthogonal changes
+        of xi, so the extreme eigenvalue of multiplication by
+        ``sum_k a_k xi_k`` on it is ``||a||_2`` times the largest zero of
+        He_{p+1}. Legendre (a bound): the space lies in the tensor space of
+        degree p per variable, where that multiplication has the eigenvalues
+        ``sum_k a_k x_k`` over the (p+1)-point Gauss nodes of each variable,
+        so ``sum_k |a_k|`` times the largest node bounds it. If the returned
+        margin is positive every element matrix is SPD, hence the global SG
+        matrix is SPD. Uses only Gauss nodes of library routines.
         """
         if self.M == 0 or self.p == 0:
             return float(self.theta0)
-        xmax = float(np.max(hermite_e.hermegauss(self.p + 1)[0]))
         a = self.element_coefficients()
+        if self.family == "legendre":
+            xmax = float(np.max(legendre.leggauss(self.p + 1)[0]))
+            return float(self.theta0 - xmax * np.abs(a).sum(axis=0).max())
+        xmax = float(np.max(hermite_e.hermegauss(self.p + 1)[0]))
         anorm = np.sqrt(np.sum(a * a, axis=0))
         return float(self.theta0 - xmax * anorm.max())
 
@@ -183,11 +194,12 @@ def qoi_weights(n_e: int, lo: float = 0.4, hi: float = 0.6):
     return w / w.sum(), w
 
 
-def make_problem(name, n_e, M, p, sigma, L, theta0=1.0, bump=None) -> Problem:
+def make_problem(name, n_e, M, p, sigma, L, theta0=1.0, bump=None, family="hermite") -> Problem:
     lam, phi, modes = kl_2d(n_e, L, M)
     return Problem(
         name=name, n_e=n_e, M=M, p=p, theta0=float(theta0), sigma=float(sigma),
         L=float(L), s=np.sqrt(lam), phi=phi, f_nodal=nodal_rhs(n_e, bump), modes=modes,
+        family=family,
     )
 
 
@@ -198,6 +210,11 @@ _NAMED = {
     "scale": dict(n_e=256, M=10, p=3, sigma=0.25, L=0.3),
     "grad": dict(n_e=512, M=8, p=3, sigma=0.2, L=0.4),
     "grad_small": dict(n_e=32, M=8, p=3, sigma=0.2, L=0.4),
+    # the examples of Section 7: uniform variables with Legendre chaos on a
+    # 10 x 10 mesh, mean 1, L = 0.5, CoV = sigma = 50 %, N = 4, degree 4
+    "paper_legendre": dict(n_e=10, M=4, p=4, sigma=0.5, L=0.5, family="legendre"),
+    # the 256^2 scale case with Legendre chaos
+    "scale_legendre": dict(n_e=256, M=10, p=3, sigma=0.25, L=0.3, family="legendre"),
 }
 
 
