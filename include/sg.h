@@ -68,13 +68,20 @@ typedef struct sg_ctx* sg_handle;
  * scale, s[M] the KL amplitudes sqrt(lambda_k) and phi[M][n_e][n_e] the
  * element values of the KL modes (both host arrays, copied by sg_setup).
  * The element coefficient of KL term k is a_k(e) = sigma * s[k] * phi[k][e];
- * coefficients are constant per element. Requires n_e >= 3, M >= 0, p >= 0,
- * P <= 2^20. */
+ * coefficients are constant per element. family selects the distribution of
+ * the random variables and the chaos basis (Section 2):
+ *   SG_FAMILY_HERMITE   standard Gaussian variables, normalised Hermite
+ *                       polynomials He_a / sqrt(a!);
+ *   SG_FAMILY_LEGENDRE  variables uniform on [-1, 1], normalised Legendre
+ *                       polynomials sqrt(2a + 1) P_a (the examples of Section 7).
+ * Requires n_e >= 3, M >= 0, p >= 0, P <= 2^20. */
+enum { SG_FAMILY_HERMITE = 0, SG_FAMILY_LEGENDRE = 1 };
+
 typedef struct sg_problem {
   int32_t n_e;
   int32_t M;
   int32_t p;
-  int32_t reserved;
+  int32_t family;
   double theta0;
   double sigma;
   const double* s;

@@ -22,11 +22,12 @@ LIB_PATH = os.environ.get("SGPC_LIBRARY") or os.path.join(_HERE, "libsgpc.so")
 SG_OK, SG_EINVAL, SG_EDEVICE, SG_ENOMEM, SG_NOT_CONVERGED, SG_BREAKDOWN = 0, -1, -2, -3, 1, 2
 SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC, SG_PC_BGS = 0, 1, 2, 3
 _PC = {"none": SG_PC_NONE, "mean": SG_PC_MEAN, "hsc": SG_PC_HSC, "bgs": SG_PC_BGS}
+SG_FAMILY_HERMITE, SG_FAMILY_LEGENDRE = 0, 1
 
 
 class SgProblem(ctypes.Structure):
     _fields_ = [("n_e", ctypes.c_int32), ("M", ctypes.c_int32), ("p", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("theta0", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("family", ctypes.c_int32), ("theta0", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("s", ctypes.POINTER(ctypes.c_double)), ("phi", ctypes.POINTER(ctypes.c_double))]
 
 
@@ -141,7 +142,8 @@ def make_c_problem(problem):
     s = np.ascontiguousarray(np.asarray(problem.s, dtype=np.float64).reshape(-1))
     phi = np.ascontiguousarray(np.asarray(problem.phi, dtype=np.float64).reshape(-1))
     dp = ctypes.POINTER(ctypes.c_double)
-    cp = SgProblem(int(problem.n_e), int(problem.M), int(problem.p), 0, float(problem.theta0),
+    family = {"hermite": SG_FAMILY_HERMITE, "legendre": SG_FAMILY_LEGENDRE}[getattr(problem, "family", "hermite")]
+    cp = SgProblem(int(problem.n_e), int(problem.M), int(problem.p), family, float(problem.theta0),
                    float(problem.sigma), s.ctypes.data_as(dp) if s.size else None,
                    phi.ctypes.data_as(dp) if phi.size else None)
     return cp, (s, phi)

@@ -99,10 +99,15 @@ struct GroupBarrier {
   unsigned gen;
   unsigned waves;  // waves of the group
   int* status;
-  bool dead;  // a wait ran out: later barriers of this wave no longer wait
+  bool dead;   // a wait ran out: later barriers of this wave no longer wait
+  bool block;  // the group is the whole block: use the hardware barrier
 };
 
 __device__ __forceinline__ void group_sync(GroupBarrier& gb) {
+  if (gb.block) {
+    __syncthreads();
+    return;
+  }
   gb.gen += gb.waves;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(gb.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -587,7 +592,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
   __shared__ int sflag;
   __shared__ unsigned sgbar[G];
   if (threadIdx.x < G) sgbar[threadIdx.x] = 0u;
-  GroupBarrier gb{&sgbar[grp], 0u, GT / 64, A.sc.status, false};
+  GroupBarrier gb{&sgbar[grp], 0u, GT / 64, A.sc.status, false, G == 1};
 
   // a compacted ragged launch covers the listed columns only; scratch is indexed by list position
   const bool listed = RAGGED && C.act != nullptr;
@@ -878,8 +883,12 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
   if (tile != 16) {
     // banded tiles: FP64 in two groups of eight waves per block, FP32 in four
     // groups of four waves (measured fastest for each)
-    constexpr int NW = sizeof(T) == 8 ? 8 : 4;
-    constexpr int G = sizeof(T) == 8 ? 2 : 4;
+#ifndef SGPC_BAND_NW
+#define SGPC_BAND_NW (sizeof(T) == 8 ? 8 : 4)
+#define SGPC_BAND_G (sizeof(T) == 8 ? 2 : 4)
+#endif
+    constexpr int NW = SGPC_BAND_NW;
+    constexpr int G = SGPC_BAND_G;
     if (H <= 3) return launch_cfg<T, BandTile<T, kBandRows, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
     if (H <= 7) return launch_cfg<T, BandTile<T, kBandRows, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);
     return hipErrorInvalidValue;

@@ -104,6 +104,8 @@ int validate(const sg_problem* pr, const sg_opts* op) {
   if (pr->M > 2047) return fail(SG_EINVAL, "M must be < 2048");
   if (!(pr->theta0 > 0.0) || !std::isfinite(pr->theta0)) return fail(SG_EINVAL, "theta0 must be positive");
   if (!(pr->sigma >= 0.0) || !std::isfinite(pr->sigma)) return fail(SG_EINVAL, "sigma must be >= 0");
+  if (pr->family != SG_FAMILY_HERMITE && pr->family != SG_FAMILY_LEGENDRE)
+    return fail(SG_EINVAL, "family must be SG_FAMILY_HERMITE or SG_FAMILY_LEGENDRE");
   if (pr->M > 0 && (!pr->s || !pr->phi)) return fail(SG_EINVAL, "null s or phi");
   if (op->inner_precision != 32 && op->inner_precision != 64)
     return fail(SG_EINVAL, "inner_precision must be 32 or 64");
@@ -929,6 +931,7 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   h->n_e = pr->n_e;
   h->M = pr->M;
   h->p = pr->p;
+  h->family = pr->family;
   h->P = pl.P;
   h->nx = pl.nx;
   h->n = pl.n;
@@ -978,6 +981,13 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   std::vector<double> lo_g, up_g;
   std::vector<std::vector<std::pair<int, int>>> pairs(M);  // per k: (a, b)
   std::vector<std::vector<double>> pairg(M);
+  // (G_k)_{a, a+e_k} = E[xi psi_n psi_{n+1}] with n = a_k: sqrt(n + 1) for the
+  // normalised Hermite basis, (n + 1) / sqrt((2n + 1)(2n + 3)) for the
+  // normalised Legendre basis (three-term recurrences of the two families)
+  const bool leg = h->family == SG_FAMILY_LEGENDRE;
+  auto up_weight = [&](int n) {
+    return leg ? (n + 1.0) / std::sqrt((2.0 * n + 1.0) * (2.0 * n + 3.0)) : std::sqrt(n + 1.0);
+  };
   for (int a = 0; a < P; ++a) {
     std::vector<int> al(h->alpha.begin() + (long)a * M, h->alpha.begin() + (long)(a + 1) * M);
     int deg = 0;
@@ -988,9 +998,9 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
         b[k] -= 1;
         const int bi = index.at(b);
         lo_ent.push_back(bi | ((k + 1) << 20));
-        lo_g.push_back(std::sqrt((double)al[k]));
+        lo_g.push_back(up_weight(al[k] - 1));
         pairs[k].push_back({a, bi});
-        pairg[k].push_back(std::sqrt((double)al[k]));
+        pairg[k].push_back(up_weight(al[k] - 1));
       }
     }
     lo_ptr[a + 1] = (int)lo_ent.size();
@@ -1000,9 +1010,9 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
         b[k] += 1;
         const int bi = index.at(b);
         up_ent.push_back(bi | ((k + 1) << 20));
-        up_g.push_back(std::sqrt((double)al[k] + 1.0));
+        up_g.push_back(up_weight(al[k]));
         pairs[k].push_back({a, bi});
-        pairg[k].push_back(std::sqrt((double)al[k] + 1.0));
+        pairg[k].push_back(up_weight(al[k]));
       }
     }
     up_ptr[a + 1] = (int)up_ent.size();

@@ -303,6 +303,7 @@ void launch_batch_compact(const int* prob, const int* ntiles, int ncols, const i
 // Host-side context behind sg_handle.
 struct sg_ctx {
   int n_e, M, p, P, nx;
+  int family;  // SG_FAMILY_*
   long n;
   double theta0, sigma;
   double lmin, lmax;  // spectrum of D^-1 K_0

@@ -17,11 +17,12 @@ def _b():
 
 
 # grids that take every SG-operator path (generic tiles, y-marching kernel at
-# multiples of 64) and chaos degrees 0..3, one zero right-hand side
+# multiples of 64), chaos degrees 0..3, both chaos families, one zero right-hand side
 MIXED = [dict(n_e=16, M=4, p=2, sigma=0.2, L=0.5), dict(n_e=64, M=3, p=3, sigma=0.25, L=0.3),
          dict(n_e=21, M=2, p=1, sigma=0.2, L=0.6), dict(n_e=32, M=5, p=2, sigma=0.15, L=0.4),
          dict(n_e=12, M=3, p=0, sigma=0.2, L=0.5), dict(n_e=128, M=2, p=2, sigma=0.2, L=0.8),
-         dict(n_e=24, M=3, p=3, sigma=0.2, L=0.5)]
+         dict(n_e=24, M=3, p=3, sigma=0.2, L=0.5),
+         dict(n_e=20, M=3, p=3, sigma=0.4, L=0.5, family="legendre")]
 ZERO_RHS = 4
 
 
