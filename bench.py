@@ -8,7 +8,7 @@ and synthetic and resident in HBM before timing starts.
 
 Also reported (outside the timed steps): the SG matvec bandwidth (cold and
 warm Infinity Cache), the FP32-inner, mean-preconditioned and block symmetric
-Gauss-Seidel-preconditioned solves, the
+Gauss-Seidel-preconditioned solves, the same solve with Legendre chaos, the
 adjoint gradient of the 512^2 differentiation case, the 48-problem uneven
 batch (FP32 inner / FP64 outer, graph replay) against the same problems
 solved one after another, the roofline of the dominant kernel, and the CPU
@@ -246,6 +246,25 @@ def main():
                 extra["hsc_action_rel_err_fp32"] = float(torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64))
             del sv, Uv
             torch.cuda.empty_cache()
+
+        # Legendre chaos (uniform variables on [-1, 1]) on the same grid and KL data
+        pl = named_problem("scale_legendre")
+        sl = SGSolver(pl, Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="hsc", inner_maxit=2000))
+        sl.sg_autotune(3)
+        Fl = to_device_block(pl.load_block())
+        Ul = sl.empty()
+        sl.sg_solve(Fl, Ul, rtol=1e-8, maxit=200)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, lst = sl.sg_solve(Fl, Ul, rtol=1e-8, maxit=200)
+        torch.cuda.synchronize()
+        extra["solve_s_hsc_legendre"] = time.perf_counter() - t1
+        extra["outer_it_hsc_legendre"] = lst["outer_it"]
+        extra["kappa_est_hsc_legendre"] = lst["kappa_est"]
+        extra["true_relres_hsc_legendre"] = lst["true_relres"]
+        log(f"hsc legendre: {extra['solve_s_hsc_legendre']:.3f} s, outer {lst['outer_it']}")
+        del sl, Ul, Fl
+        torch.cuda.empty_cache()
 
         # adjoint gradient, 512^2, M = 8, p = 3
         pg = named_problem("grad")
