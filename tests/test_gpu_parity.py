@@ -78,6 +78,30 @@ def test_inner_solve_fixed_iterations(prec, tol, degree, tile):
         assert np.linalg.norm(X[c] - Xo[c]) <= tol * np.linalg.norm(Xo[c])
 
 
+@pytest.mark.parametrize("prec,tol", [(64, 1e-11), (32, 2e-5)])
+@pytest.mark.parametrize("n_e", [4, 51, 52, 130])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4, 5, 8])
+def test_inner_solve_band_geometry(prec, tol, n_e, degree):
+    """Banded inner tiles at the edges of their geometry: a grid smaller than
+    the halo (n_e = 4), a tile plus halo exactly one wavefront wide (n_e = 51
+    at degree 8), one column more (n_e = 52) and several ragged tiles
+    (n_e = 130), for both halo capacities (degree <= 4 and <= 8)."""
+    b = _b()
+    prob, s = _sys(n_e=n_e, M=2, p=1)
+    print(f"inner band prec={prec} n_e={n_e} degree={degree}", flush=True)
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=degree, inner_maxit=7,
+                                        inner_rtol=0.0, tile=32))
+    B = random_block(3, prob.n, seed=n_e + degree)
+    X, its = solver.sg_inner_solve(_dev(B))
+    X = X.cpu().numpy()
+    prec_o = krylov.make_chebyshev(s.K[0], prob.n_e, prob.theta0, degree)
+    st = krylov.InnerStats()
+    Xo = krylov.pcg_columns(s.K[0], B.T, prec_o, 0.0, 7, st).T
+    assert list(its) == list(st.iterations)
+    for c in range(3):
+        assert np.linalg.norm(X[c] - Xo[c]) <= tol * np.linalg.norm(Xo[c])
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_inner_solve_to_tolerance(prec):
     b = _b()
