@@ -428,6 +428,41 @@ __device__ __forceinline__ void march_body(const SgOpArgs<T>& A, const StripTabl
   const T* __restrict__ in = A.in;
   const T* __restrict__ acoef = A.a;
 
+  // Neighbour columns and weights of the group's rows (uniform, read once).
+  // A missing neighbour gets column 0 and weight 0, so every load of a step is
+  // issued without waiting for a table read and contributes nothing.
+  int cl[RG][NK], cu[RG][NK];
+  T wl[RG][NK], wu[RG][NK];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    const int row = rows[j];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      int lo = -1, up = -1;
+      T gl = T(0), gu = T(0);
+      if (row >= 0) {
+        if constexpr (LK) {
+          lo = ld_uniform(job.lcol, (g * kMarchRGL + j) * kMarchNS + s);
+          if (lo >= 0) gl = T(ld_uniform(job.lw, (g * kMarchRGL + j) * kMarchNS + s));
+        } else {
+          if (A.use_lower) {
+            lo = ld_uniform(tab.lo, row * M + s);
+            if (lo >= 0) gl = ld_uniform(tab.glo, row * M + s);
+          }
+          if (A.use_upper) {
+            up = ld_uniform(tab.up, row * M + s);
+            if (up >= 0) gu = ld_uniform(tab.gup, row * M + s);
+          }
+        }
+      }
+      cl[j][s] = lo >= 0 ? lo : 0;
+      cu[j][s] = up >= 0 ? up : 0;
+      wl[j][s] = gl;
+      wu[j][s] = gu;
+    }
+  }
+  const bool has_diag = A.diag != T(0);
+
   T ac[NK], acp[NK], an[NK], anp[NK];
 #pragma unroll
   for (int s = 0; s < NK; ++s) ac[s] = acp[s] = T(0);
@@ -450,24 +485,30 @@ __device__ __forceinline__ void march_body(const SgOpArgs<T>& A, const StripTabl
       an[s] = use ? acoef[(long)ks[s] * ne2 + abase] : T(0);
       al0[s] = (use && xl >= 0) ? ld_uniform(acoef, (long)ks[s] * ne2 + (long)gy * ne + xl) : T(0);
     }
+    // off-grid lanes read node 0 and discard it
+    const long nid = nin ? nidx : 0;
     T ud[RG], ul[RG][NK], uu[RG][NK];
 #pragma unroll
     for (int j = 0; j < RG; ++j) {
       const int row = rows[j];
-      ud[j] = (row >= 0 && A.diag != T(0) && nin) ? in[(long)row * n + nidx] : T(0);
+      ud[j] = T(0);
+      if (has_diag && row >= 0) ud[j] = in[(long)row * n + nid];
 #pragma unroll
       for (int s = 0; s < NK; ++s) {
-        int lo = -1, up = -1;
+        ul[j][s] = T(0);
+        uu[j][s] = T(0);
         if (row >= 0) {
-          if constexpr (LK) {
-            lo = ld_uniform(job.lcol, (g * kMarchRGL + j) * kMarchNS + s);
-          } else {
-            lo = A.use_lower ? ld_uniform(tab.lo, row * M + s) : -1;
-            up = A.use_upper ? ld_uniform(tab.up, row * M + s) : -1;
-          }
+          if (LK || A.use_lower) ul[j][s] = in[(long)cl[j][s] * n + nid];
+          if (!LK && A.use_upper) uu[j][s] = in[(long)cu[j][s] * n + nid];
         }
-        ul[j][s] = (lo >= 0 && nin) ? in[(long)lo * n + nidx] : T(0);
-        uu[j][s] = (!LK && up >= 0 && nin) ? in[(long)up * n + nidx] : T(0);
+      }
+    }
+    if (!nin) {
+#pragma unroll
+      for (int j = 0; j < RG; ++j) {
+        ud[j] = T(0);
+#pragma unroll
+        for (int s = 0; s < NK; ++s) ul[j][s] = uu[j][s] = T(0);
       }
     }
     // ---- corner sums
@@ -490,15 +531,9 @@ __device__ __forceinline__ void march_body(const SgOpArgs<T>& A, const StripTabl
       for (int s = 0; s < NK; ++s) {
         T w;
         if constexpr (LK) {
-          const int lo = ld_uniform(job.lcol, (g * kMarchRGL + j) * kMarchNS + s);
-          if (lo < 0) continue;
-          w = T(ld_uniform(job.lw, (g * kMarchRGL + j) * kMarchNS + s)) * ul[j][s];
+          w = wl[j][s] * ul[j][s];
         } else {
-          const int lo = A.use_lower ? ld_uniform(tab.lo, row * M + s) : -1;
-          const int up = A.use_upper ? ld_uniform(tab.up, row * M + s) : -1;
-          if (lo < 0 && up < 0) continue;
-          w = (lo >= 0 ? ld_uniform(tab.glo, row * M + s) * ul[j][s] : T(0)) +
-              (up >= 0 ? ld_uniform(tab.gup, row * M + s) * uu[j][s] : T(0));
+          w = wl[j][s] * ul[j][s] + wu[j][s] * uu[j][s];
         }
         t += ac[s] * w;
         rt += acp[s] * w;
