@@ -10,9 +10,13 @@
 // application reads r and q once and writes z once.
 //
 // Per PCG iteration every column passes two phases:
-//   phase A: p = z + beta p (tile plus a 1-node halo), q = K_0 p, partial p.q;
-//   phase B: alpha = gamma / p.q, x += alpha p, r -= alpha q (tile plus the
-//            Chebyshev halo), z = M r, partials r.r and r.z.
+//   phase A: x += alpha' p' (the update of the previous iteration, deferred
+//            so that it reuses the p that phase A reads anyway),
+//            p = z + beta p' (tile plus a 1-node halo), q = K_0 p, partial p.q;
+//   phase B: alpha = gamma / p.q, r -= alpha q (tile plus the Chebyshev
+//            halo), z = M r, partials r.r and r.z.
+// A column that stops (converged, or out of iterations) applies the pending
+// x update to its tiles first.
 // A column is split into tiles; each block owns a contiguous run of tiles (the
 // same tiles in every phase) and works on G tiles at a time, one per
 // 256-thread group whose four waves synchronise among themselves only.
@@ -42,7 +46,10 @@ namespace {
 constexpr int kSquareGroup = 256;          // threads per group of the square tiles
 constexpr long kSpinLimit = 1L << 26;      // bounded waits: a stuck column aborts the launch
 
-enum { PART_BB = 0, PART_PQ = 1, PART_RR0 = 2, PART_RR1 = 3, PART_RZ0 = 4, PART_RZ1 = 5, PART_N = 6 };
+// Per-tile partial sums: b.b, p.q of even / odd iterations, r.r and r.z of
+// even / odd iterations.
+enum { PART_BB = 0, PART_PQ0 = 1, PART_PQ1 = 2, PART_RR0 = 3, PART_RR1 = 4, PART_RZ0 = 5, PART_RZ1 = 6, PART_N = 7 };
+static_assert(PART_N == kPcgPartials, "partial arrays of the inner solver");
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -166,7 +173,8 @@ struct IterVecs {
   const T* ro;  // r of the previous iteration (phase B)
   T* rn;        // r of this iteration
   T beta;       // phase A: p = z + beta p (first iteration: p = z)
-  T alpha;      // phase B: x += alpha p, r -= alpha q
+  T alpha_prev; // phase A: x += alpha_prev po (not in the first iteration)
+  T alpha;      // phase B: r -= alpha q
   bool first;
 };
 
@@ -322,6 +330,7 @@ struct SquareTile {
                      W0[q + RS1] + W0[q + RS1 + 1];
         const T qv = v.c0 * pc + v.c1 * s8;
         const long g = (long)gy * nx + gx;
+        if (!I.first) v.x[g] += I.alpha_prev * I.po[g];
         I.pn[g] = pc;
         v.q[g] = qv;
         pq += (double)pc * (double)qv;
@@ -330,7 +339,24 @@ struct SquareTile {
     return pq;
   }
 
-  // Phase B: x += alpha p, r -= alpha q, z = M r; partials r.z and r.r.
+  // x += alpha p on the interior of a tile (the update a stopping column still owes).
+  __device__ static void finalize(const ColView<T>& v, int t, T alpha, const T* p) {
+    const int lt = threadIdx.x % kThreads;
+    const int nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int i = lt + k * kThreads;
+      const int gx = x0 + i % TS, gy = y0 + i / TS;
+      if (i < TS * TS && gx < nx && gy < nx) {
+        const long g = (long)gy * nx + gx;
+        v.x[g] += alpha * p[g];
+      }
+    }
+  }
+
+  // Phase B: r -= alpha q, z = M r; partials r.z and r.r.
   __device__ static void phase_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, T* W0, T* W1,
                                  GroupBarrier& gb, double& rz, double& rr) {
     const int lt = threadIdx.x % kThreads;
@@ -347,7 +373,6 @@ struct SquareTile {
       const int gx = x0 + i % TS, gy = y0 + i / TS;
       if (i < TS * TS && gx < nx && gy < nx) {
         const long g = (long)gy * nx + gx;
-        v.x[g] = I.first ? I.alpha * I.pn[g] : v.x[g] + I.alpha * I.pn[g];
         I.rn[g] = Ri[k];
         v.z[g] = Zi[k];
         rr += (double)Ri[k] * (double)Ri[k];
@@ -519,7 +544,13 @@ struct BandTile {
       pc[r] = T(0);
       if (xin && ly < TSY + 2 && gy >= 0 && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
-        pc[r] = I.first ? v.z[o] : v.z[o] + I.beta * I.po[o];
+        if (I.first) {
+          pc[r] = v.z[o];
+        } else {
+          const T po = I.po[o];
+          pc[r] = v.z[o] + I.beta * po;
+          if (xint && ly >= 1 && ly <= TSY) v.x[o] += I.alpha_prev * po;
+        }
       }
       W0[ly * 64 + lane] = pc[r];
     }
@@ -544,6 +575,26 @@ struct BandTile {
     return pq;
   }
 
+  // x += alpha p on the interior of a tile (the update a stopping column still owes).
+  __device__ static void finalize(const ColView<T>& v, int t, T alpha, const T* p) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    const int nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    const int gx = x0 + lane;
+    constexpr int rows = (TSY + NW - 1) / NW;
+#pragma unroll
+    for (int r = 0; r < rows; ++r) {
+      const int ly = wv * rows + r;
+      const int gy = y0 + ly;
+      if (lane < v.tsx && gx < nx && ly < TSY && gy < nx) {
+        const unsigned o = (unsigned)(gy * nx + gx);
+        v.x[o] += alpha * p[o];
+      }
+    }
+  }
+
   __device__ static void phase_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, T* W0, T* W1,
                                  GroupBarrier& gb, double& rz, double& rr) {
     const int lane = threadIdx.x & 63;
@@ -553,7 +604,7 @@ struct BandTile {
     origin(v, t, x0, y0);
     T Zi[BR], Ri[BR];
     auto rreg = [&](unsigned o) { return I.ro[o] - I.alpha * v.q[o]; };
-    auto inner = [&](unsigned o) { v.x[o] = I.first ? I.alpha * I.pn[o] : v.x[o] + I.alpha * I.pn[o]; };
+    auto inner = [&](unsigned) {};
     rz = cheb(v, degree, x0, y0, rreg, inner, W0, W1, Zi, Ri, gb);
     rr = 0.0;
     const int gx = x0 - H + lane;
@@ -588,7 +639,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
   // per-column done flags of this block's columns, after the tile buffers
   int* sdone = reinterpret_cast<int*>(reinterpret_cast<T*>(smem_raw) + (long)G * lds_group);
   __shared__ double sred[G][GT / 64][2];
-  __shared__ double s4[4];
+  __shared__ double s4[5];
+  static_assert(Tile::kThreads * G >= 5 * 64, "column sums take five waves");
   __shared__ int sflag;
   __shared__ unsigned sgbar[G];
   if (threadIdx.x < G) sgbar[threadIdx.x] = 0u;
@@ -678,12 +730,13 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
     t1 = (int)(hi - v.tbase);
   };
   auto owner = [&](const ColView<T>& v) { return v.tbase >= w_begin; };  // this block holds tile 0
-  // Fixed-order sums of up to four per-tile partial arrays of a column, one wave each.
-  auto col_sums = [&](const ColView<T>& v, const double* q0, const double* q1, const double* q2, const double* q3) {
+  // Fixed-order sums of up to five per-tile partial arrays of a column, one wave each.
+  auto col_sums = [&](const ColView<T>& v, const double* q0, const double* q1, const double* q2, const double* q3,
+                      const double* q4) {
     __syncthreads();
     const int wv = threadIdx.x >> 6;
-    const double* src = wv == 0 ? q0 : wv == 1 ? q1 : wv == 2 ? q2 : q3;
-    if (wv < 4 && src) {
+    const double* src = wv == 0 ? q0 : wv == 1 ? q1 : wv == 2 ? q2 : wv == 3 ? q3 : q4;
+    if (wv < 5 && src) {
       double s = 0.0;
       for (int t = threadIdx.x & 63; t < v.ntiles; t += 64) s += src[v.tbase + t];
       s = wave_sum(s);
@@ -723,10 +776,11 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
   }
 
   bool aborted = false;
-  for (int it = 0; it < A.maxit && !aborted; ++it) {
+  // iteration A.maxit only applies the x update of the last iteration
+  for (int it = 0; it <= A.maxit && !aborted; ++it) {
     const int par = it & 1;
     bool any_active = false;
-    // ---- phase A (column phase 2 + 2 it): p = z + beta p, q = K_0 p, partial p.q
+    // ---- phase A (column phase 2 + 2 it): x += alpha' p', p = z + beta p', q = K_0 p, partial p.q
     for (int c = c_first; c <= c_last && !aborted; ++c) {
       if (sdone[c - c_first]) continue;
       const ColView<T> v = view(c);
@@ -737,11 +791,22 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         aborted = true;
         break;
       }
-      col_sums(v, P(PART_BB), it == 0 ? nullptr : P(par ? PART_RR0 : PART_RR1),
-               it == 0 ? nullptr : P(par ? PART_RZ0 : PART_RZ1), it == 0 ? nullptr : P(par ? PART_RZ1 : PART_RZ0));
+      const bool first = it == 0;
+      col_sums(v, P(PART_BB), first ? nullptr : P(par ? PART_RR0 : PART_RR1),
+               first ? nullptr : P(par ? PART_RZ0 : PART_RZ1), first ? nullptr : P(par ? PART_RZ1 : PART_RZ0),
+               first ? nullptr : P(par ? PART_PQ0 : PART_PQ1));
       const double bb = s4[0];
-      const double rr = it == 0 ? s4[0] : s4[1];
-      if (sqrt(rr) <= A.rtol * sqrt(bb)) {
+      const double rr = first ? s4[0] : s4[1];
+      IterVecs<T> I{};
+      I.first = first;
+      I.po = par ? v.p0 : v.p1;
+      I.pn = par ? v.p1 : v.p0;
+      I.beta = first ? T(0) : (T)(s4[2] / s4[3]);
+      I.alpha_prev = first ? T(0) : (T)(s4[3] / s4[4]);
+      if (it == A.maxit || sqrt(rr) <= A.rtol * sqrt(bb)) {
+        // stop: apply the pending update x += alpha' p'
+        if (!first)
+          for (int t = t0 + grp; t < t1; t += G) Tile::finalize(v, t, I.alpha_prev, I.po);
         __syncthreads();
         if (threadIdx.x == 0) {
           sdone[c - c_first] = 1;
@@ -751,20 +816,15 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         continue;
       }
       any_active = true;
-      IterVecs<T> I{};
-      I.first = it == 0;
-      I.beta = it == 0 ? T(0) : (T)(s4[2] / s4[3]);
-      I.po = par ? v.p0 : v.p1;
-      I.pn = par ? v.p1 : v.p0;
       for (int t = t0 + grp; t < t1; t += G) {
         double pq = Tile::phase_a(v, t, I, W0, gb), unused = 0.0;
         group_sum2<GT>(pq, unused, sred, gb);
-        if (lt == 0) P(PART_PQ)[v.tbase + t] = pq;
+        if (lt == 0) P(par ? PART_PQ1 : PART_PQ0)[v.tbase + t] = pq;
       }
       column_arrive(arr + c, (unsigned)(t1 - t0));
     }
     if (!any_active || aborted) break;
-    // ---- phase B (column phase 3 + 2 it): x += alpha p, r -= alpha q, z = M r, partials r.r, r.z
+    // ---- phase B (column phase 3 + 2 it): r -= alpha q, z = M r, partials r.r, r.z
     for (int c = c_first; c <= c_last && !aborted; ++c) {
       if (sdone[c - c_first]) continue;
       const ColView<T> v = view(c);
@@ -775,10 +835,10 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         aborted = true;
         break;
       }
-      col_sums(v, P(PART_PQ), P(par ? PART_RZ0 : PART_RZ1), nullptr, nullptr);
+      col_sums(v, P(par ? PART_PQ1 : PART_PQ0), P(par ? PART_RZ0 : PART_RZ1), nullptr, nullptr, nullptr);
       const double pq = s4[0], gam = s4[1];
       if (!(pq > 0.0) || !isfinite(pq)) {
-        // breakdown: keep the current iterate
+        // breakdown: keep the current iterate (phase A of this iteration applied the last update)
         __syncthreads();
         if (threadIdx.x == 0) {
           sdone[c - c_first] = 1;

@@ -144,7 +144,7 @@ int make_batch_plan(int count, const sg_problem* probs, const sg_opts* op, Batch
   bp.o_part = L.take(sizeof(double) * 2 * sgk::kBatchBlocks * count);
   bp.o_consts = L.take(sizeof(sgk::PcgConsts<double>) * count);
   bp.o_sets = L.take(bp.set_bytes);
-  bp.o_pcg_part = L.take(sizeof(double) * 6 * std::max<long>(1, bp.nwork_max));
+  bp.o_pcg_part = L.take(sizeof(double) * sgk::kPcgPartials * std::max<long>(1, bp.nwork_max));
   bp.o_arr = L.take(sizeof(unsigned) * std::max<long>(1, bp.ncols_max));
   bp.o_iters = L.take(sizeof(int) * std::max<long>(1, bp.ncols_max));
   bp.o_status = L.take(sizeof(int));

@@ -181,7 +181,7 @@ void make_plan(const sg_problem* pr, const sg_opts* op, Plan& pl) {
   pl.o_rw = L.take(isz * nP);
   pl.o_zw = L.take(op->inner_precision == 32 ? isz * nP : 0);
   for (int i = 0; i < 6; ++i) pl.o_pcg[i] = L.take(isz * pl.n * (long)pl.maxcols);
-  pl.o_part = L.take(sizeof(double) * 6 * (long)pl.maxcols * pl.ntiles_max);
+  pl.o_part = L.take(sizeof(double) * sgk::kPcgPartials * (long)pl.maxcols * pl.ntiles_max);
   pl.o_arr = L.take(sizeof(unsigned) * pl.maxcols);
   pl.o_iters = L.take(sizeof(int) * pl.maxcols);
   pl.o_status = L.take(sizeof(int));
@@ -418,9 +418,10 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   int mx = 0;
   for (int v : it) {
     h->inner_it_acc += v;
-    // phase A reads z, p and writes p, q; phase B reads x, p, r, q and writes x, r, z;
-    // the start reads b and writes z and x
-    h->inner_bytes_acc += (11.0 * v + 3.0) * (double)h->n * sizeof(T);
+    // phase A reads z, p and x and writes p, q and x; phase B reads r and q and writes r
+    // and z; the start reads b and writes z and x; a column that stops after at least
+    // one iteration reads x and p and writes x once more
+    h->inner_bytes_acc += (10.0 * v + (v > 0 ? 6.0 : 3.0)) * (double)h->n * sizeof(T);
     mx = std::max(mx, v);
   }
   if (level_for_stats >= 0 && level_for_stats < sgk::kMaxLevels)

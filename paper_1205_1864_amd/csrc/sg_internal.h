@@ -13,6 +13,7 @@ namespace sgk {
 
 constexpr int kMaxCheb = 16;     // largest supported Chebyshev degree
 constexpr int kMaxLevels = 16;   // largest supported chaos degree + 1
+constexpr int kPcgPartials = 7;  // per-tile partial-sum arrays of the inner solver
 constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 
 // Tiles of the inner PCG on an nx x nx grid. tile == 16: square 16 x 16 tiles.
@@ -126,7 +127,7 @@ bool march_supported(int n_e, int M);
 
 // Persistent batched PCG on K_0 = theta0 * K_Lap (one independent solve per column).
 struct PcgScratch {
-  double* part;        // [6][ncols][ntiles] per-tile partial sums
+  double* part;        // [kPcgPartials][ncols][ntiles] per-tile partial sums
   unsigned* arrivals;  // [ncols] monotonic per-column arrival counters
   int* iters;          // [ncols]
   int* status;         // [1] nonzero if a bounded wait expired
