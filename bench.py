@@ -37,7 +37,7 @@ CHEB_DEGREE = 8  # updates of the Chebyshev preconditioner of the inner PCG
 # runs of this benchmark, scaled by the same counters of a 512 MiB elementwise
 # kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Set to None when the
 # kernel changes.
-PCG_TRAFFIC_BYTES = 26.90e9     # pcg_kernel<double, BandTile<double, 32, 7, 8>, 2>, average over a solve's launches
+PCG_TRAFFIC_BYTES = None        # re-measure after a kernel change (profiles/hbm_traffic_solve_256sq_M10_p3.txt)
 MATVEC_TRAFFIC_BYTES = 544.3e6  # sgop_march_kernel<double, 10>, one SG matvec
 
 

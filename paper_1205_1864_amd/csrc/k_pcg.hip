@@ -200,8 +200,8 @@ struct SquareTile {
     y0 = (t / v.ntx) * TS;
   }
 
-  // Chebyshev preconditioner on one tile. `rreg(gy * nx + gx)` gives r at grid
-  // node (gx, gy) of the region (only called inside the grid). On return Zi holds z and
+  // Chebyshev preconditioner on one tile. `rreg(s, gy * nx + gx)` gives r at
+  // grid node (gx, gy) of the region (only called inside the grid). On return Zi holds z and
   // Ri holds r on this thread's interior nodes; returns the partial r.z.
   template <typename RF>
   __device__ static double cheb(const ColView<T>& A, int degree, int x0, int y0, RF rreg, T* W0, T* W1,
@@ -219,7 +219,7 @@ struct SquareTile {
       if (i < nreg) {
         const int lx = i % RS, ly = i / RS;
         const int gx = x0 - H + lx, gy = y0 - H + ly;
-        const T r = (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) ? rreg((unsigned)(gy * A.nx + gx)) : T(0);
+        const T r = (gx >= 0 && gx < A.nx && gy >= 0 && gy < A.nx) ? rreg(s, (unsigned)(gy * A.nx + gx)) : T(0);
         S[s] = r * A.inv_diag;
         W0[i] = S[s] * A.inv_theta;
         W1[i] = r;
@@ -284,7 +284,7 @@ struct SquareTile {
     int x0, y0;
     origin(v, t, x0, y0);
     T Zi[NI], Ri[NI];
-    auto rreg = [&](unsigned o) { return v.b[o]; };
+    auto rreg = [&](int, unsigned o) { return v.b[o]; };
     rz = cheb(v, degree, x0, y0, rreg, W0, W1, Zi, Ri, gb);
     bb = 0.0;
 #pragma unroll
@@ -364,7 +364,7 @@ struct SquareTile {
     int x0, y0;
     origin(v, t, x0, y0);
     T Zi[NI], Ri[NI];
-    auto rreg = [&](unsigned o) { return I.ro[o] - I.alpha * v.q[o]; };
+    auto rreg = [&](int, unsigned o) { return I.ro[o] - I.alpha * v.q[o]; };
     rz = cheb(v, degree, x0, y0, rreg, W0, W1, Zi, Ri, gb);
     rr = 0.0;
 #pragma unroll
@@ -376,6 +376,29 @@ struct SquareTile {
         I.rn[g] = Ri[k];
         v.z[g] = Zi[k];
         rr += (double)Ri[k] * (double)Ri[k];
+      }
+    }
+  }
+
+  __device__ static void run_a(const ColView<T>& v, int t_begin, int t_end, int step, const IterVecs<T>& I, T* W0,
+                               GroupBarrier& gb, double (*sred)[kThreads / 64][2], double* part) {
+    for (int t = t_begin; t < t_end; t += step) {
+      double pq = phase_a(v, t, I, W0, gb), unused = 0.0;
+      group_sum2<kThreads>(pq, unused, sred, gb);
+      if ((threadIdx.x % kThreads) == 0) part[t] = pq;
+    }
+  }
+
+  __device__ static void run_b(const ColView<T>& v, int degree, int t_begin, int t_end, int step,
+                               const IterVecs<T>& I, T* W0, T* W1, GroupBarrier& gb,
+                               double (*sred)[kThreads / 64][2], double* part_rz, double* part_rr) {
+    for (int t = t_begin; t < t_end; t += step) {
+      double rz, rr;
+      phase_b(v, degree, t, I, W0, W1, gb, rz, rr);
+      group_sum2<kThreads>(rz, rr, sred, gb);
+      if ((threadIdx.x % kThreads) == 0) {
+        part_rz[t] = rz;
+        part_rr[t] = rr;
       }
     }
   }
@@ -396,7 +419,7 @@ struct BandTile {
   static constexpr int BR = (RYMAX + NW - 1) / NW;     // region rows per wave (Chebyshev)
   static constexpr int BRA = (TSY + 2 + NW - 1) / NW;  // region rows per wave (phase A, halo 1)
   static constexpr int RB = NW * BR;                   // rows of one LDS buffer (bands padded)
-  static constexpr int CH = 4;                         // rows per chunk of a sweep
+  static constexpr int CH = 2;                         // rows per chunk of a sweep (registers)
   static_assert(NW * BRA <= RB, "phase A rows exceed the buffer");
   static int lds_group(int) { return 2 * RB * 64; }
   static bool fits(int degree, int nx, int ntx, int ntiles) {
@@ -420,10 +443,10 @@ struct BandTile {
   // the region where W_j is valid ([j, R - j) in both directions) are
   // meaningless but never reach a valid value: a valid node of sweep j + 1
   // reads only nodes valid in sweep j. Nodes outside the grid hold zero.
-  // `inner(o)` runs once per interior grid node of the tile (offset o) at step
-  // 0, so that its memory accesses overlap those of the region.
-  template <typename RF, typename IF>
-  __device__ static double cheb(const ColView<T>& A, int degree, int x0, int y0, RF rreg, IF inner, T* W0, T* W1,
+  // `val(r, o)` gives r at band row r (grid offset o) of the region; it is only
+  // called for nodes inside the grid.
+  template <typename VF>
+  __device__ static double cheb(const ColView<T>& A, int degree, int x0, int y0, VF val, T* W0, T* W1,
                                 T (&Zi)[BR], T (&Ri)[BR], GroupBarrier& gb) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
@@ -442,12 +465,11 @@ struct BandTile {
       const int gy = y0 - H + ly;
       const bool in = xin && ly < RY && gy >= 0 && gy < nx;
       T rv = T(0);
-      if (in) rv = rreg((unsigned)(gy * nx + gx));
+      if (in) rv = val(r, (unsigned)(gy * nx + gx));
       S[r] = rv * A.inv_diag;
       const T w0 = S[r] * A.inv_theta;
       W0[ly * 64 + lane] = w0;
       const bool interior = xint && ly >= H && ly < H + TSY;
-      if (interior && gy < nx) inner((unsigned)(gy * nx + gx));
       Zi[r] = interior ? w0 : T(0);
       Ri[r] = interior ? rv : T(0);
     }
@@ -507,9 +529,8 @@ struct BandTile {
     int x0, y0;
     origin(v, t, x0, y0);
     T Zi[BR], Ri[BR];
-    auto rreg = [&](unsigned o) { return v.b[o]; };
-    auto inner = [&](unsigned o) { v.x[o] = T(0); };
-    rz = cheb(v, degree, x0, y0, rreg, inner, W0, W1, Zi, Ri, gb);
+    auto val = [&](int, unsigned o) { return v.b[o]; };
+    rz = cheb(v, degree, x0, y0, val, W0, W1, Zi, Ri, gb);
     bb = 0.0;
     const int gx = x0 - H + lane;
     const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
@@ -520,20 +541,49 @@ struct BandTile {
       if (xint && ly >= H && ly < H + TSY && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
         bb += (double)Ri[r] * (double)Ri[r];
+        v.x[o] = T(0);
         v.z[o] = Zi[r];
       }
     }
   }
 
-  __device__ static double phase_a(const ColView<T>& v, int t, const IterVecs<T>& I, T* W0, GroupBarrier& gb) {
+  // Inputs of phase A on this wave's rows of the region (tile plus a 1-node halo).
+  struct InA {
+    T z[BRA], po[BRA], x[BRA];
+  };
+  __device__ static void load_a(const ColView<T>& v, int t, const IterVecs<T>& I, InA& in) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
     int x0, y0;
     origin(v, t, x0, y0);
-    const int RX = v.tsx + 2;
     const int gx = x0 - 1 + lane;
-    const bool xin = lane < RX && gx >= 0 && gx < nx;
+    const bool xin = lane < v.tsx + 2 && gx >= 0 && gx < nx;
+    const bool xint = lane >= 1 && lane <= v.tsx && gx < nx;
+#pragma unroll
+    for (int r = 0; r < BRA; ++r) {
+      const int ly = wv * BRA + r;
+      const int gy = y0 - 1 + ly;
+      in.z[r] = in.po[r] = in.x[r] = T(0);
+      if (xin && ly < TSY + 2 && gy >= 0 && gy < nx) {
+        const unsigned o = (unsigned)(gy * nx + gx);
+        in.z[r] = v.z[o];
+        if (!I.first) {
+          in.po[r] = I.po[o];
+          if (xint && ly >= 1 && ly <= TSY) in.x[r] = v.x[o];
+        }
+      }
+    }
+  }
+
+  __device__ static double compute_a(const ColView<T>& v, int t, const IterVecs<T>& I, const InA& in, T* W0,
+                                     GroupBarrier& gb) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    const int nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    const int gx = x0 - 1 + lane;
     const bool xint = lane >= 1 && lane <= v.tsx && gx < nx;
     const int yb = wv * BRA;
     T pc[BRA];
@@ -541,18 +591,10 @@ struct BandTile {
     for (int r = 0; r < BRA; ++r) {
       const int ly = yb + r;
       const int gy = y0 - 1 + ly;
-      pc[r] = T(0);
-      if (xin && ly < TSY + 2 && gy >= 0 && gy < nx) {
-        const unsigned o = (unsigned)(gy * nx + gx);
-        if (I.first) {
-          pc[r] = v.z[o];
-        } else {
-          const T po = I.po[o];
-          pc[r] = v.z[o] + I.beta * po;
-          if (xint && ly >= 1 && ly <= TSY) v.x[o] += I.alpha_prev * po;
-        }
-      }
-      W0[ly * 64 + lane] = pc[r];
+      pc[r] = I.first ? in.z[r] : in.z[r] + I.beta * in.po[r];
+      if (!I.first && xint && ly >= 1 && ly <= TSY && gy < nx)
+        v.x[(unsigned)(gy * nx + gx)] = in.x[r] + I.alpha_prev * in.po[r];
+      if (ly < TSY + 2) W0[ly * 64 + lane] = pc[r];
     }
     group_sync(gb);
     double pq = 0.0;
@@ -575,6 +617,24 @@ struct BandTile {
     return pq;
   }
 
+  // Phase A over tiles t_begin, t_begin + step, ... < t_end of a column; the
+  // inputs of the next tile are loaded while the current one is computed.
+  __device__ static void run_a(const ColView<T>& v, int t_begin, int t_end, int step, const IterVecs<T>& I, T* W0,
+                               GroupBarrier& gb, double (*sred)[kThreads / 64][2], double* part) {
+    if (t_begin >= t_end) return;
+    InA cur;
+    load_a(v, t_begin, I, cur);
+    for (int t = t_begin; t < t_end; t += step) {
+      InA nxt;
+      const bool more = t + step < t_end;
+      if (more) load_a(v, t + step, I, nxt);
+      double pq = compute_a(v, t, I, cur, W0, gb), unused = 0.0;
+      group_sum2<kThreads>(pq, unused, sred, gb);
+      if ((threadIdx.x % kThreads) == 0) part[t] = pq;
+      if (more) cur = nxt;
+    }
+  }
+
   // x += alpha p on the interior of a tile (the update a stopping column still owes).
   __device__ static void finalize(const ColView<T>& v, int t, T alpha, const T* p) {
     const int lane = threadIdx.x & 63;
@@ -595,17 +655,41 @@ struct BandTile {
     }
   }
 
-  __device__ static void phase_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, T* W0, T* W1,
-                                 GroupBarrier& gb, double& rz, double& rr) {
+  // Inputs of phase B on this wave's rows of the region (tile plus the Chebyshev halo).
+  struct InB {
+    T r[BR], q[BR];
+  };
+  __device__ static void load_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, InB& in) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    const int H = degree - 1, nx = v.nx;
+    int x0, y0;
+    origin(v, t, x0, y0);
+    const int gx = x0 - H + lane;
+    const bool xin = lane < v.tsx + 2 * H && gx >= 0 && gx < nx;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int ly = wv * BR + r;
+      const int gy = y0 - H + ly;
+      in.r[r] = in.q[r] = T(0);
+      if (xin && ly < TSY + 2 * H && gy >= 0 && gy < nx) {
+        const unsigned o = (unsigned)(gy * nx + gx);
+        in.r[r] = I.ro[o];
+        in.q[r] = v.q[o];
+      }
+    }
+  }
+
+  __device__ static void compute_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, const InB& in,
+                                   T* W0, T* W1, GroupBarrier& gb, double& rz, double& rr) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int H = degree - 1, nx = v.nx;
     int x0, y0;
     origin(v, t, x0, y0);
     T Zi[BR], Ri[BR];
-    auto rreg = [&](unsigned o) { return I.ro[o] - I.alpha * v.q[o]; };
-    auto inner = [&](unsigned) {};
-    rz = cheb(v, degree, x0, y0, rreg, inner, W0, W1, Zi, Ri, gb);
+    auto val = [&](int r, unsigned) { return in.r[r] - I.alpha * in.q[r]; };
+    rz = cheb(v, degree, x0, y0, val, W0, W1, Zi, Ri, gb);
     rr = 0.0;
     const int gx = x0 - H + lane;
     const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
@@ -619,6 +703,29 @@ struct BandTile {
         v.z[o] = Zi[r];
         rr += (double)Ri[r] * (double)Ri[r];
       }
+    }
+  }
+
+  // Phase B over tiles t_begin, t_begin + step, ... < t_end of a column; the
+  // inputs of the next tile are loaded while the current one is computed.
+  __device__ static void run_b(const ColView<T>& v, int degree, int t_begin, int t_end, int step,
+                               const IterVecs<T>& I, T* W0, T* W1, GroupBarrier& gb,
+                               double (*sred)[kThreads / 64][2], double* part_rz, double* part_rr) {
+    if (t_begin >= t_end) return;
+    InB cur;
+    load_b(v, degree, t_begin, I, cur);
+    for (int t = t_begin; t < t_end; t += step) {
+      InB nxt;
+      const bool more = t + step < t_end;
+      if (more) load_b(v, degree, t + step, I, nxt);
+      double rz, rr;
+      compute_b(v, degree, t, I, cur, W0, W1, gb, rz, rr);
+      group_sum2<kThreads>(rz, rr, sred, gb);
+      if ((threadIdx.x % kThreads) == 0) {
+        part_rz[t] = rz;
+        part_rr[t] = rr;
+      }
+      if (more) cur = nxt;
     }
   }
 };
@@ -816,11 +923,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         continue;
       }
       any_active = true;
-      for (int t = t0 + grp; t < t1; t += G) {
-        double pq = Tile::phase_a(v, t, I, W0, gb), unused = 0.0;
-        group_sum2<GT>(pq, unused, sred, gb);
-        if (lt == 0) P(par ? PART_PQ1 : PART_PQ0)[v.tbase + t] = pq;
-      }
+      Tile::run_a(v, t0 + grp, t1, G, I, W0, gb, sred, P(par ? PART_PQ1 : PART_PQ0) + v.tbase);
       column_arrive(arr + c, (unsigned)(t1 - t0));
     }
     if (!any_active || aborted) break;
@@ -853,15 +956,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       I.pn = par ? v.p1 : v.p0;
       I.ro = it == 0 ? v.b : (par ? v.r1 : v.r0);
       I.rn = par ? v.r0 : v.r1;
-      for (int t = t0 + grp; t < t1; t += G) {
-        double rz, rr;
-        Tile::phase_b(v, degree, t, I, W0, W1, gb, rz, rr);
-        group_sum2<GT>(rz, rr, sred, gb);
-        if (lt == 0) {
-          P(par ? PART_RZ1 : PART_RZ0)[v.tbase + t] = rz;
-          P(par ? PART_RR1 : PART_RR0)[v.tbase + t] = rr;
-        }
-      }
+      Tile::run_b(v, degree, t0 + grp, t1, G, I, W0, W1, gb, sred, P(par ? PART_RZ1 : PART_RZ0) + v.tbase,
+                  P(par ? PART_RR1 : PART_RR0) + v.tbase);
       column_arrive(arr + c, (unsigned)(t1 - t0));
     }
   }
@@ -941,11 +1037,11 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
   if (args.ncols <= 0) return hipSuccess;
   const int H = args.degree - 1;
   if (tile != 16) {
-    // banded tiles: FP64 in two groups of eight waves per block, FP32 in four
-    // groups of four waves (measured fastest for each)
+    // banded tiles: two groups of eight waves per block (16 waves per CU; the
+    // next tile's inputs prefetched in registers)
 #ifndef SGPC_BAND_NW
-#define SGPC_BAND_NW (sizeof(T) == 8 ? 8 : 4)
-#define SGPC_BAND_G (sizeof(T) == 8 ? 2 : 4)
+#define SGPC_BAND_NW 8
+#define SGPC_BAND_G 2
 #endif
     constexpr int NW = SGPC_BAND_NW;
     constexpr int G = SGPC_BAND_G;
