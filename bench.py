@@ -37,8 +37,8 @@ CHEB_DEGREE = 8  # updates of the Chebyshev preconditioner of the inner PCG
 # runs of this benchmark, scaled by the same counters of a 512 MiB elementwise
 # kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Set to None when the
 # kernel changes.
-PCG_TRAFFIC_BYTES = None        # re-measure after a kernel change (profiles/hbm_traffic_solve_256sq_M10_p3.txt)
-MATVEC_TRAFFIC_BYTES = 544.3e6  # sgop_march_kernel<double, 10>, one SG matvec
+PCG_TRAFFIC_BYTES = 25.30e9     # pcg_kernel<double, BandTile<double, 32, 7, 8>, 2>, average over a solve's launches
+MATVEC_TRAFFIC_BYTES = {(2, 2): 572.1e6}  # sgop_march_kernel<double, 10>, one SG matvec, by schedule
 
 
 def log(msg):
@@ -295,7 +295,7 @@ def main():
     achieved = bytes_inner / (ms_inner * 1e-3) / 1e9 if ms_inner > 0 else 0.0
     # the counter traffic belongs to the schedules it was measured with
     pcg_traffic = PCG_TRAFFIC_BYTES if (schedule["pcg_tile"], schedule["pcg_max_blocks"]) == (32, 0) else None
-    mv_traffic = MATVEC_TRAFFIC_BYTES if (schedule["mv_variant"], schedule["mv_param"]) == (2, 0) else None
+    mv_traffic = MATVEC_TRAFFIC_BYTES.get((schedule["mv_variant"], schedule["mv_param"]))
     mv_kernel = {2: "sgop_march_kernel<double>", 1: "sgop_strip_dyn_kernel<double>",
                  0: "sgop_strip_kernel<double>"}[schedule["mv_variant"]]
     roofline = {
