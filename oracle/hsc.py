@@ -81,14 +81,16 @@ class PCGMeanSolver:
         return X
 
 
-def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = None) -> np.ndarray:
+def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = None, ptop: int = None) -> np.ndarray:
     """One action of M_P (Algorithm 1) on a residual block R of shape (n, P).
 
     ``solve_mean(V)`` applies the inverse of the K_0 diagonal blocks to each
-    column of V.
+    column of V. With ``ptop`` < p the levels run only up to ptop and R has
+    the ``off[ptop + 1]`` columns of degree <= ptop (the preconditioner
+    M_{P-1} of the reduced system of Section 5).
     """
     off = sys.off
-    p = sys.p
+    p = sys.p if ptop is None else ptop
     r = np.array(R, dtype=np.float64, copy=True)
     u = np.zeros_like(r)
     cnt = counters if counters is not None else Counters()
