@@ -8,7 +8,8 @@ and synthetic and resident in HBM before timing starts.
 
 Also reported (outside the timed steps): the SG matvec bandwidth (cold and
 warm Infinity Cache), the FP32-inner, mean-preconditioned and block symmetric
-Gauss-Seidel-preconditioned solves, the same solve with Legendre chaos, the
+Gauss-Seidel-preconditioned solves, the solve through the a-priori Schur
+reduction of the top degree, the same solve with Legendre chaos, the
 adjoint gradient of the 512^2 differentiation case, the 48-problem uneven
 batch (FP32 inner / FP64 outer, graph replay) against the same problems
 solved one after another, the roofline of the dominant kernel, and the CPU
@@ -246,6 +247,24 @@ def main():
                 extra["hsc_action_rel_err_fp32"] = float(torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64))
             del sv, Uv
             torch.cuda.empty_cache()
+
+        # a-priori reduction to the Schur complement of the top degree (Section 5):
+        # the same problem, top-degree solves of the reduced operator to 1e-11
+        sr = SGSolver(prob, Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="hsc", inner_maxit=3000))
+        sr.sg_autotune(3)
+        Ur = sr.empty()
+        sr.sg_solve_reduced(F, Ur, rtol=1e-8, maxit=200, op_rtol=1e-11)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, rst = sr.sg_solve_reduced(F, Ur, rtol=1e-8, maxit=200, op_rtol=1e-11)
+        torch.cuda.synchronize()
+        extra["solve_s_hsc_reduced"] = time.perf_counter() - t1
+        extra["outer_it_hsc_reduced"] = rst["outer_it"]
+        extra["true_relres_hsc_reduced"] = rst["true_relres"]
+        extra["rel_diff_vs_fp64_hsc_hsc_reduced"] = float(torch.linalg.norm(Ur - U64) / torch.linalg.norm(U64))
+        log(f"hsc reduced: {extra['solve_s_hsc_reduced']:.3f} s, outer {rst['outer_it']}")
+        del sr, Ur
+        torch.cuda.empty_cache()
 
         # Legendre chaos (uniform variables on [-1, 1]) on the same grid and KL data
         pl = named_problem("scale_legendre")

@@ -191,6 +191,22 @@ int sg_coupling(sg_handle h, int32_t level, int32_t dir, double* R, const double
 int sg_solve(sg_handle h, const double* F, double* U, double rtol, int32_t maxit, int32_t use_x0,
              sg_stats* stats);
 
+/* Solve A U = F through the a-priori reduction to the Schur complement of the
+ * top chaos degree (Section 5, eq. (global-Schur-system)): flexible CG on
+ *   S u_low = f_low - B_p D_p^-1 f_top,  S = A_{P-1} - B_p D_p^-1 C_p,
+ * over the columns of degree < p, preconditioned by Algorithm 1 over the
+ * levels 1..p-1 (opts.precond = SG_PC_HSC) or by the mean-based preconditioner
+ * (SG_PC_MEAN), to ||g - S u_low||_2 <= rtol ||g||_2 or maxit iterations; then
+ * u_top = D_p^-1 (f_top - C_p u_low). The D_p solves of the operator, of the
+ * right-hand side and of the recovery run the inner PCG to op_rtol (0 < op_rtol
+ * < 1; the reduction is exact only for exact D_p solves), the preconditioner's
+ * to opts.inner_rtol. Needs p >= 1 and opts.inner_precision = 64. F and U are
+ * distinct n x P device blocks; U is overwritten (zero start). stats (host, may
+ * be NULL) counts the reduced iteration; its true_relres is that of the full
+ * system. */
+int sg_solve_reduced(sg_handle h, const double* F, double* U, double rtol, int32_t maxit, double op_rtol,
+                     sg_stats* stats);
+
 /* Quantity of interest Q = w_mean . U[:,0] + sum_{j>=1} w_var . U[:,j]^2
  * (w_mean, w_var: n-vectors on the device); result to *Q (host). */
 int sg_qoi(sg_handle h, const double* U, const double* w_mean, const double* w_var, double* Q);

@@ -79,6 +79,7 @@ def _load():
         "sg_inner_solve": [VP, VP, VP, I32, P(I32)],
         "sg_coupling": [VP, I32, I32, VP, VP],
         "sg_solve": [VP, VP, VP, D, I32, I32, P(SgStats)],
+        "sg_solve_reduced": [VP, VP, VP, D, I32, D, P(SgStats)],
         "sg_qoi": [VP, VP, VP, VP, P(D)],
         "sg_adjoint_grad": [VP, VP, VP, VP, D, I32, P(D), P(D), VP, P(SgStats)],
         "sg_autotune": [VP, I32, P(SgTuneReport)],
@@ -245,6 +246,15 @@ class SGSolver:
         st = SgStats()
         rc = _check(lib.sg_solve(self.handle, _dptr(self._block(F)), _dptr(self._block(U)), float(rtol),
                                  int(maxit), int(bool(use_x0)), ctypes.byref(st)), allow_positive=True)
+        d = st.as_dict()
+        d["rc"] = rc
+        return U, d
+
+    def sg_solve_reduced(self, F, U=None, rtol=1e-8, maxit=200, op_rtol=1e-12):
+        U = self.empty() if U is None else U
+        st = SgStats()
+        rc = _check(lib.sg_solve_reduced(self.handle, _dptr(self._block(F)), _dptr(self._block(U)), float(rtol),
+                                         int(maxit), float(op_rtol), ctypes.byref(st)), allow_positive=True)
         d = st.as_dict()
         d["rc"] = rc
         return U, d

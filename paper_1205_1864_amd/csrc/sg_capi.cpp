@@ -493,11 +493,13 @@ long coupling_blocks(const sg_ctx* h, int l, int dir) {
   return ptr[h->off[rl + 1]] - ptr[h->off[rl]];
 }
 
-// Algorithm 1 in inner precision T: rw holds a copy of the residual, Zb receives M_P r.
+// Algorithm 1 in inner precision T over the levels 0..ptop: rw holds a copy of
+// the residual, Zb receives M_P r (ptop = p) or M_{P-1} r of the reduced system
+// (ptop = p - 1; only the columns of degree <= ptop are read and written).
 template <typename T>
-int hsc_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs) {
+int hsc_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs, int ptop) {
   const long n = h->n;
-  for (int l = h->p; l >= 1; --l) {
+  for (int l = ptop; l >= 1; --l) {
     const int lo = h->off[l], hi = h->off[l + 1];
     int rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l);  // y_l = D_l^-1 r_l^l
     if (rc) return rc;
@@ -508,7 +510,7 @@ int hsc_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs) {
   int rc = run_pcg<T>(h, rw, Zb, 1, 0);  // A_0 u_0 = g_0
   if (rc) return rc;
   *nbs += 1;
-  for (int l = 1; l <= h->p; ++l) {
+  for (int l = 1; l <= ptop; ++l) {
     const int lo = h->off[l], hi = h->off[l + 1];
     coupling<T>(h, l, 1, rw, Zb);  // w = r_l^l - C_l u_{l-1}
     *nbmv += coupling_blocks(h, l, 1);
@@ -569,12 +571,12 @@ int apply_hsc(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
   if (h->opts.inner_precision == 64) {
     double* rw = (double*)h->rw;
     sgk::launch_copy_d2d(rw, R, N, h->stream);
-    return hsc_core<double>(h, rw, Z, nbmv, nbs);
+    return hsc_core<double>(h, rw, Z, nbmv, nbs, h->p);
   }
   float* rw = (float*)h->rw;
   float* zw = (float*)h->zw;
   sgk::launch_copy_d2f(rw, R, N, h->stream);
-  int rc = hsc_core<float>(h, rw, zw, nbmv, nbs);
+  int rc = hsc_core<float>(h, rw, zw, nbmv, nbs, h->p);
   if (rc) return rc;
   sgk::launch_copy_f2d(Z, zw, N, h->stream);
   return SG_OK;
@@ -621,12 +623,17 @@ int read_out(sg_ctx* h, int count) {
   return SG_OK;
 }
 
-int dots(sg_ctx* h, int nd, const double* a0, const double* b0, const double* a1, const double* b1,
-         const double* a2, const double* b2) {
+int dots_n(sg_ctx* h, long N, int nd, const double* a0, const double* b0, const double* a1 = nullptr,
+           const double* b1 = nullptr, const double* a2 = nullptr, const double* b2 = nullptr) {
   const double* A[3] = {a0, a1, a2};
   const double* B[3] = {b0, b1, b2};
-  sgk::launch_dots(A, B, nd, h->n * (long)h->P, h->red_part, h->red_out, h->stream);
+  sgk::launch_dots(A, B, nd, N, h->red_part, h->red_out, h->stream);
   return read_out(h, nd);
+}
+
+int dots(sg_ctx* h, int nd, const double* a0, const double* b0, const double* a1, const double* b1,
+         const double* a2, const double* b2) {
+  return dots_n(h, h->n * (long)h->P, nd, a0, b0, a1, b1, a2, b2);
 }
 
 double lanczos_kappa(const std::vector<double>& al, const std::vector<double>& be) {
@@ -676,124 +683,228 @@ struct Timer {
   }
 };
 
-// Flexible CG with one stored direction; preconditioner kind pc.
-int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x0, int pc, sg_stats* st) {
-  Timer total;
-  const long N = h->n * (long)h->P;
-  sg_stats S{};
-  h->inner_it_acc = 0;
-  h->inner_ms_acc = 0.0;
-  h->inner_bytes_acc = 0.0;
-  h->inner_launch_acc = 0;
-  for (int l = 0; l < sgk::kMaxLevels; ++l) h->inner_it_max[l] = 0;
-  long nbmv = 0, nbs = 0;
+// Outcome of a flexible CG run.
+struct FcgRun {
+  int status = SG_NOT_CONVERGED;
+  int its = 0;
+  double fn2 = 0.0, relres = 0.0;
   double ms_pc = 0.0, ms_mv = 0.0;
-  int rc = dots(h, 1, F, F);
+  std::vector<double> alphas, betas;
+};
+
+// Flexible CG with one stored direction on vectors of length N (prefixes of
+// the handle's n x P vectors): op(x, y) sets y = A x, prec(r, z) sets z = M r.
+// The vectors r, z, p and q of the handle hold the iteration.
+int fcg_core(sg_ctx* h, long N, const double* F, double* U, double rtol, int maxit, int use_x0,
+             const std::function<int(const double*, double*)>& op,
+             const std::function<int(const double*, double*)>& prec, FcgRun& out) {
+  int rc = dots_n(h, N, 1, F, F);
   if (rc) return rc;
   const double fn2 = h->host_out[0];
+  out.fn2 = fn2;
   if (!std::isfinite(fn2)) return fail(SG_EINVAL, "right-hand side is not finite");
   double* r = h->r;
   double* z = h->z;
   double* p = h->pv;
   double* q = h->q;
   if (use_x0) {
-    matvec(h, U, h->tmp);
+    rc = op(U, h->tmp);
+    if (rc) return rc;
     sgk::launch_sub(r, F, h->tmp, N, h->stream);
   } else {
     sgk::launch_fill(U, 0.0, N, h->stream);
     sgk::launch_copy_d2d(r, F, N, h->stream);
   }
-  int status = SG_NOT_CONVERGED;
-  std::vector<double> alphas, betas;
-  double relres = 0.0;
-  int its = 0;
   if (fn2 == 0.0) {
     sgk::launch_fill(U, 0.0, N, h->stream);
-    status = SG_OK;
-  } else {
-    rc = dots(h, 1, r, r);
+    out.status = SG_OK;
+    return SG_OK;
+  }
+  rc = dots_n(h, N, 1, r, r);
+  if (rc) return rc;
+  out.relres = std::sqrt(h->host_out[0] / fn2);
+  if (out.relres <= rtol) out.status = SG_OK;
+  double pq_prev = 0.0;
+  for (int it = 0; it < maxit && out.status == SG_NOT_CONVERGED; ++it) {
+    Timer tp;
+    rc = prec(r, z);
     if (rc) return rc;
-    relres = std::sqrt(h->host_out[0] / fn2);
-    if (relres <= rtol) status = SG_OK;
-    double pq_prev = 0.0;
-    for (int it = 0; it < maxit && status == SG_NOT_CONVERGED; ++it) {
-      Timer tp;
-      if (pc == SG_PC_HSC) {
-        rc = apply_hsc(h, r, z, &nbmv, &nbs);
-      } else if (pc == SG_PC_BGS) {
-        rc = apply_bgs(h, r, z, &nbmv, &nbs);
-      } else if (pc == SG_PC_MEAN) {
-        rc = apply_mean(h, r, z, &nbs);
-      } else {
-        sgk::launch_copy_d2d(z, r, N, h->stream);
-        rc = SG_OK;
-      }
+    if (it == 0) {
+      sgk::launch_copy_d2d(p, z, N, h->stream);
+    } else {
+      rc = dots_n(h, N, 1, z, q);
       if (rc) return rc;
-      if (it == 0) {
-        sgk::launch_copy_d2d(p, z, N, h->stream);
-      } else {
-        rc = dots(h, 1, z, q);
-        if (rc) return rc;
-        const double beta = -h->host_out[0] / pq_prev;
-        betas.push_back(beta);
-        sgk::launch_xpby(p, z, beta, N, h->stream);
-      }
-      SG_HIP(hipStreamSynchronize(h->stream));
-      ms_pc += tp.ms();
-      Timer tm;
-      matvec(h, p, q);
-      SG_HIP(hipStreamSynchronize(h->stream));
-      ms_mv += tm.ms();
-      rc = dots(h, 2, p, q, p, r);
-      if (rc) return rc;
-      const double pq = h->host_out[0], pr = h->host_out[1];
-      if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(pr)) {
-        status = SG_BREAKDOWN;
-        break;
-      }
-      const double alpha = pr / pq;
-      alphas.push_back(alpha);
-      sgk::launch_fcg_update(U, r, p, q, alpha, N, h->red_part, h->red_out, h->stream);
-      rc = read_out(h, 1);
-      if (rc) return rc;
-      pq_prev = pq;
-      its = it + 1;
-      relres = std::sqrt(h->host_out[0] / fn2);
-      if (!std::isfinite(relres)) {
-        status = SG_BREAKDOWN;
-        break;
-      }
-      if (relres <= rtol) status = SG_OK;
+      const double beta = -h->host_out[0] / pq_prev;
+      out.betas.push_back(beta);
+      sgk::launch_xpby(p, z, beta, N, h->stream);
     }
-  }
-  // true residual
-  double true_rel = 0.0;
-  if (fn2 > 0.0) {
-    matvec(h, U, h->tmp);
-    sgk::launch_sub(h->tmp, F, h->tmp, N, h->stream);
-    rc = dots(h, 1, h->tmp, h->tmp);
+    SG_HIP(hipStreamSynchronize(h->stream));
+    out.ms_pc += tp.ms();
+    Timer tm;
+    rc = op(p, q);
     if (rc) return rc;
-    true_rel = std::sqrt(h->host_out[0] / fn2);
+    SG_HIP(hipStreamSynchronize(h->stream));
+    out.ms_mv += tm.ms();
+    rc = dots_n(h, N, 2, p, q, p, r);
+    if (rc) return rc;
+    const double pq = h->host_out[0], pr = h->host_out[1];
+    if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(pr)) {
+      out.status = SG_BREAKDOWN;
+      break;
+    }
+    const double alpha = pr / pq;
+    out.alphas.push_back(alpha);
+    sgk::launch_fcg_update(U, r, p, q, alpha, N, h->red_part, h->red_out, h->stream);
+    rc = read_out(h, 1);
+    if (rc) return rc;
+    pq_prev = pq;
+    out.its = it + 1;
+    out.relres = std::sqrt(h->host_out[0] / fn2);
+    if (!std::isfinite(out.relres)) {
+      out.status = SG_BREAKDOWN;
+      break;
+    }
+    if (out.relres <= rtol) out.status = SG_OK;
   }
-  S.outer_it = its;
-  S.status = status;
+  return SG_OK;
+}
+
+void reset_inner_stats(sg_ctx* h) {
+  h->inner_it_acc = 0;
+  h->inner_ms_acc = 0.0;
+  h->inner_bytes_acc = 0.0;
+  h->inner_launch_acc = 0;
+  for (int l = 0; l < sgk::kMaxLevels; ++l) h->inner_it_max[l] = 0;
+}
+
+// Relative true residual ||F - A U|| / ||F|| of the full system (uses tmp).
+int full_true_relres(sg_ctx* h, const double* F, const double* U, double fn2, double* out) {
+  const long N = h->n * (long)h->P;
+  *out = 0.0;
+  if (!(fn2 > 0.0)) return SG_OK;
+  matvec(h, U, h->tmp);
+  sgk::launch_sub(h->tmp, F, h->tmp, N, h->stream);
+  int rc = dots(h, 1, h->tmp, h->tmp);
+  if (rc) return rc;
+  *out = std::sqrt(h->host_out[0] / fn2);
+  return SG_OK;
+}
+
+int finish_stats(sg_ctx* h, const FcgRun& run, double true_rel, long nbmv, long nbs, const Timer& total,
+                 sg_stats* st) {
+  sg_stats S{};
+  S.outer_it = run.its;
+  S.status = run.status;
   S.inner_it_total = h->inner_it_acc;
   S.n_blockmv = nbmv;
   S.n_blocksolve = nbs;
   for (int l = 0; l < 16; ++l) S.inner_it_max[l] = h->inner_it_max[l];
-  S.relres = relres;
+  S.relres = run.relres;
   S.true_relres = true_rel;
-  S.kappa_est = lanczos_kappa(alphas, betas);
+  S.kappa_est = lanczos_kappa(run.alphas, run.betas);
   S.ms_inner = h->inner_ms_acc;
   S.inner_bytes = h->inner_bytes_acc;
   S.inner_launches = h->inner_launch_acc;
-  S.ms_precond = ms_pc;
-  S.ms_matvec = ms_mv;
+  S.ms_precond = run.ms_pc;
+  S.ms_matvec = run.ms_mv;
   S.ms = total.ms();
   if (st) *st = S;
-  if (status == SG_NOT_CONVERGED) g_last_error = "outer iteration did not converge";
-  if (status == SG_BREAKDOWN) g_last_error = "breakdown: non-positive or non-finite curvature";
-  return status;
+  if (run.status == SG_NOT_CONVERGED) g_last_error = "outer iteration did not converge";
+  if (run.status == SG_BREAKDOWN) g_last_error = "breakdown: non-positive or non-finite curvature";
+  return run.status;
+}
+
+// Flexible CG on the full system; preconditioner kind pc.
+int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x0, int pc, sg_stats* st) {
+  Timer total;
+  const long N = h->n * (long)h->P;
+  reset_inner_stats(h);
+  long nbmv = 0, nbs = 0;
+  auto op = [&](const double* x, double* y) {
+    matvec(h, x, y);
+    return SG_OK;
+  };
+  auto prec = [&](const double* r, double* z) {
+    if (pc == SG_PC_HSC) return apply_hsc(h, r, z, &nbmv, &nbs);
+    if (pc == SG_PC_BGS) return apply_bgs(h, r, z, &nbmv, &nbs);
+    if (pc == SG_PC_MEAN) return apply_mean(h, r, z, &nbs);
+    sgk::launch_copy_d2d(z, r, N, h->stream);
+    return (int)SG_OK;
+  };
+  FcgRun run;
+  int rc = fcg_core(h, N, F, U, rtol, maxit, use_x0, op, prec, run);
+  if (rc) return rc;
+  double true_rel = 0.0;
+  rc = full_true_relres(h, F, U, run.fn2, &true_rel);
+  if (rc) return rc;
+  return finish_stats(h, run, true_rel, nbmv, nbs, total, st);
+}
+
+// Flexible CG on the Schur complement of the top degree (Section 5): the
+// reduced unknown and right-hand side are the first off[p] columns; D_p^-1 of
+// the operator, of the right-hand side and of the recovery runs the inner PCG
+// (FP64) to op_rtol.
+int solve_reduced(sg_ctx* h, const double* F, double* U, double rtol, int maxit, double op_rtol, sg_stats* st) {
+  Timer total;
+  const long n = h->n;
+  const int p = h->p;
+  const int lo = h->off[p], ntop = h->off[p + 1] - h->off[p];
+  const long NP = n * (long)h->P, Nr = n * (long)lo;
+  reset_inner_stats(h);
+  long nbmv = 0, nbs = 0;
+  const double pc_rtol = h->opts.inner_rtol;
+  auto top_solve = [&](const double* B, double* X) {  // X_top = D_p^-1 B_top (tight)
+    h->opts.inner_rtol = op_rtol;
+    const int rc = run_pcg<double>(h, B + lo * n, X + lo * n, ntop, p);
+    h->opts.inner_rtol = pc_rtol;
+    nbs += ntop;
+    return rc;
+  };
+  double* g = h->rhs;
+  double* w = h->lam;
+  // g = f_low - B_p D_p^-1 f_top
+  int rc = top_solve(F, w);
+  if (rc) return rc;
+  sgk::launch_copy_d2d(g, F, Nr, h->stream);
+  coupling<double>(h, p, 0, g, w);
+  nbmv += coupling_blocks(h, p, 0);
+  // the iteration vectors are prefixes; their top columns stay zero
+  sgk::launch_fill(h->pv, 0.0, NP, h->stream);
+  sgk::launch_fill(U, 0.0, NP, h->stream);
+  // S x = A_low x - B_p D_p^-1 C_p x: the full product of [x; 0] gives A_low x on
+  // the low columns and C_p x on the top ones
+  auto op = [&](const double* x, double* y) {
+    matvec(h, x, y);
+    int rc2 = top_solve(y, w);
+    if (rc2) return rc2;
+    coupling<double>(h, p, 0, y, w);
+    nbmv += coupling_blocks(h, p, 0);
+    return (int)SG_OK;
+  };
+  auto prec = [&](const double* r, double* z) {
+    if (h->opts.precond == SG_PC_MEAN) {
+      nbs += lo;
+      return run_pcg<double>(h, r, z, lo, -1);
+    }
+    sgk::launch_copy_d2d((double*)h->rw, r, Nr, h->stream);
+    return hsc_core<double>(h, (double*)h->rw, z, &nbmv, &nbs, p - 1);
+  };
+  FcgRun run;
+  rc = fcg_core(h, Nr, g, U, rtol, maxit, 0, op, prec, run);
+  if (rc) return rc;
+  // recovery: u_top = D_p^-1 (f_top - C_p u_low)
+  sgk::launch_copy_d2d(w + lo * n, F + lo * n, n * (long)ntop, h->stream);
+  coupling<double>(h, p, 1, w, U);
+  nbmv += coupling_blocks(h, p, 1);
+  rc = top_solve(w, U);
+  if (rc) return rc;
+  double fn2 = 0.0, true_rel = 0.0;
+  rc = dots(h, 1, F, F);
+  if (rc) return rc;
+  fn2 = h->host_out[0];
+  rc = full_true_relres(h, F, U, fn2, &true_rel);
+  if (rc) return rc;
+  return finish_stats(h, run, true_rel, nbmv, nbs, total, st);
 }
 
 // Schedule autotuner (sg_autotune).
@@ -1270,6 +1381,19 @@ int sg_solve(sg_handle h, const double* F, double* U, double rtol, int32_t maxit
   if (F == U) return fail(SG_EINVAL, "F and U must be distinct");
   if (!(rtol >= 0.0) || maxit < 0) return fail(SG_EINVAL, "rtol must be >= 0 and maxit >= 0");
   return fcg(h, F, U, rtol, maxit, use_x0, h->opts.precond, stats);
+}
+
+int sg_solve_reduced(sg_handle h, const double* F, double* U, double rtol, int32_t maxit, double op_rtol,
+                     sg_stats* stats) {
+  if (!h || !F || !U) return fail(SG_EINVAL, "null argument");
+  if (F == U) return fail(SG_EINVAL, "F and U must be distinct");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(SG_EINVAL, "rtol must be >= 0 and maxit >= 0");
+  if (!(op_rtol > 0.0 && op_rtol < 1.0)) return fail(SG_EINVAL, "op_rtol must be in (0, 1)");
+  if (h->p < 1) return fail(SG_EINVAL, "the reduction needs chaos degree p >= 1");
+  if (h->opts.inner_precision != 64) return fail(SG_EINVAL, "the reduced solve needs FP64 inner solves");
+  if (h->opts.precond != SG_PC_HSC && h->opts.precond != SG_PC_MEAN)
+    return fail(SG_EINVAL, "the reduced solve takes the HSC or the mean-based preconditioner");
+  return solve_reduced(h, F, U, rtol, maxit, op_rtol, stats);
 }
 
 int sg_qoi(sg_handle h, const double* U, const double* w_mean, const double* w_var, double* Q) {
