@@ -97,7 +97,9 @@ typedef struct sg_problem {
  *                     K_0 per application).
  *   inner_maxit       cap on inner PCG iterations per solve (>= 1).
  *   precond           SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC or SG_PC_BGS for sg_solve.
- *   tile              spatial tile edge of the inner solver (16 or 32; 0 = auto).
+ *   tile              spatial tiles of the inner solver: 32 = banded tiles (up to
+ *                     64 columns including the Chebyshev halo, 32 rows; for
+ *                     degrees <= 8), 16 = 16 x 16 tiles, 0 = automatic.
  *   inner_rtol        relative residual at which an inner solve stops
  *                     (recursive residual, Euclidean norm); <= 0 runs
  *                     exactly inner_maxit iterations. */
@@ -226,7 +228,7 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
  *   flags bit 0: the SG operator (y-marching kernel with 1, 2 or 4 grid
  *                segments per XCD or the automatic count; band kernels with
  *                32..128 row chunks per band, where the grid shape allows them);
- *   flags bit 1: the inner PCG (tile edge 16 or 32 where the Chebyshev halo
+ *   flags bit 1: the inner PCG (tile kind 16 or 32 where the Chebyshev halo
  *                allows 32; block count automatic or half the CUs), timed on
  *                the columns of the largest chaos level with a constant
  *                right-hand side.
@@ -237,7 +239,7 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
 typedef struct sg_tune_report {
   int32_t mv_variant;      /* 0, 1: band kernels; 2: y-marching kernel */
   int32_t mv_param;        /* row chunks per band (variants 0, 1) or segments per XCD (2; 0 = automatic) */
-  int32_t pcg_tile;        /* inner tile edge */
+  int32_t pcg_tile;        /* inner tile kind (32 banded, 16 square) */
   int32_t pcg_max_blocks;  /* cap on the blocks of an inner launch (0 = as many as fit) */
   double mv_ms;            /* median time of one SG matvec with the chosen schedule */
   double pcg_ms;           /* time of the inner test solve with the chosen schedule */

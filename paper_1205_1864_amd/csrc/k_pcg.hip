@@ -18,8 +18,8 @@
 // A column that stops (converged, or out of iterations) applies the pending
 // x update to its tiles first.
 // A column is split into tiles; each block owns a contiguous run of tiles (the
-// same tiles in every phase) and works on G tiles at a time, one per
-// 256-thread group whose four waves synchronise among themselves only.
+// same tiles in every phase) and works on G tiles at a time, one per group of
+// waves; the waves of a group synchronise among themselves only.
 // Columns synchronise only among the blocks that share them, through
 // split-phase counters (no grid-wide barrier). Per-column scalars are reduced
 // from per-tile partials in a fixed order, identically in every block, so all
@@ -94,8 +94,8 @@ __device__ __forceinline__ int wave_in_group() {
   return __builtin_amdgcn_readfirstlane((threadIdx.x % GT) >> 6);
 }
 
-// Barrier of the four waves of one tile group, so the groups of a block do
-// not run in lockstep (one group loads its next tile while another sweeps).
+// Barrier of the waves of one tile group, so the groups of a block do not run
+// in lockstep (one group loads its next tile while another sweeps).
 // `bar` is the group's monotonic arrival counter in LDS; `gen` counts the
 // arrivals this wave has waited for so far (the same in every wave of the
 // group). A wait that does not end within the spin limit sets the status word
