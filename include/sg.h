@@ -6,9 +6,9 @@
  * methods"): -div(a(x, xi) grad u) = f on the unit square, u = 0 on the
  * boundary, with a linear Karhunen-Loeve coefficient
  *     a(x, xi) = theta0 + sigma * sum_{k=1..M} s_k phi_k(x) xi_k,
- * xi_k i.i.d. standard Gaussian, Q1 elements on an n_e x n_e grid and a
- * normalised Hermite chaos of total degree <= p (P = (M+p)!/(M! p!)
- * functions). The discrete system is sum_k (G_k (x) K_k) vec(U) = vec(F)
+ * xi_k independent (standard Gaussian or uniform on [-1, 1]), Q1 elements on
+ * an n_e x n_e grid and a normalised chaos of total degree <= p
+ * (P = (M+p)!/(M! p!) functions). The discrete system is sum_k (G_k (x) K_k) vec(U) = vec(F)
  * (eq. (global-system), eq. (global-matrix)).
  *
  * Layout conventions used by every call
@@ -100,6 +100,12 @@ typedef struct sg_problem {
  *   tile              spatial tiles of the inner solver: 32 = banded tiles (up to
  *                     64 columns including the Chebyshev halo, 32 rows; for
  *                     degrees <= 8), 16 = 16 x 16 tiles, 0 = automatic.
+ *   warm_start        0: every inner solve starts from zero. 1: the inner
+ *                     solves of the up sweep of Algorithm 1 start from the
+ *                     down-sweep solution of the same level, and those of the
+ *                     backward sweep of block Gauss-Seidel from the forward
+ *                     sweep's (banded tiles; 16 x 16 tiles start from zero).
+ *                     The stopping test stays relative to the right-hand side.
  *   inner_rtol        relative residual at which an inner solve stops
  *                     (recursive residual, Euclidean norm); <= 0 runs
  *                     exactly inner_maxit iterations. */
@@ -109,7 +115,7 @@ typedef struct sg_opts {
   int32_t inner_maxit;
   int32_t precond;
   int32_t tile;
-  int32_t reserved;
+  int32_t warm_start;
   double inner_rtol;
 } sg_opts;
 
@@ -128,7 +134,8 @@ typedef struct sg_stats {
   double ms_precond;          /* time in preconditioner actions */
   double ms_matvec;           /* time in SG matvecs */
   double ms_inner;            /* device time of the inner PCG launches (HIP events on the stream) */
-  double inner_bytes;         /* algorithmic bytes of those launches: per column (11 its + 3) n w */
+  double inner_bytes;         /* algorithmic bytes of those launches: per column (10 its + 6) n w
+                                 (3 n w when it stops at once; n w more from a warm start) */
   int64_t inner_launches;     /* number of inner PCG launches */
 } sg_stats;
 

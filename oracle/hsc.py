@@ -58,7 +58,8 @@ class ExactMeanSolver:
     def __init__(self, sys: SGSystem):
         self.lu = spla.splu(sys.K[0].tocsc())
 
-    def __call__(self, B: np.ndarray) -> np.ndarray:
+    def __call__(self, B: np.ndarray, X0=None) -> np.ndarray:
+        # a direct solve has no use for an initial guess
         if B.shape[1] == 0:
             return B.copy()
         return self.lu.solve(np.asarray(B, dtype=np.float64))
@@ -74,30 +75,35 @@ class PCGMeanSolver:
         self.maxit = maxit
         self.iterations = []
 
-    def __call__(self, B: np.ndarray) -> np.ndarray:
+    def __call__(self, B: np.ndarray, X0=None) -> np.ndarray:
         st = krylov.InnerStats()
-        X = krylov.pcg_columns(self.K0, B, self.prec, self.rtol, self.maxit, st)
+        X = krylov.pcg_columns(self.K0, B, self.prec, self.rtol, self.maxit, st, X0)
         self.iterations.append(st.iterations)
         return X
 
 
-def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = None, ptop: int = None) -> np.ndarray:
+def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = None, ptop: int = None,
+              warm: bool = False) -> np.ndarray:
     """One action of M_P (Algorithm 1) on a residual block R of shape (n, P).
 
-    ``solve_mean(V)`` applies the inverse of the K_0 diagonal blocks to each
-    column of V. With ``ptop`` < p the levels run only up to ptop and R has
-    the ``off[ptop + 1]`` columns of degree <= ptop (the preconditioner
-    M_{P-1} of the reduced system of Section 5).
+    ``solve_mean(V, X0=None)`` applies the inverse of the K_0 diagonal blocks
+    to each column of V (an iterative solver starts from X0 if given). With
+    ``ptop`` < p the levels run only up to ptop and R has the
+    ``off[ptop + 1]`` columns of degree <= ptop (the preconditioner M_{P-1}
+    of the reduced system of Section 5). ``warm``: each solve of the up sweep
+    starts from the down-sweep solution y_l of its level (the algorithm fixes
+    what is solved, not the inner solver's initial guess).
     """
     off = sys.off
     p = sys.p if ptop is None else ptop
     r = np.array(R, dtype=np.float64, copy=True)
     u = np.zeros_like(r)
     cnt = counters if counters is not None else Counters()
+    ys = {}
     # Down sweep: pre-corrections on levels p..1.
     for l in range(p, 0, -1):
         lo, hi = int(off[l]), int(off[l + 1])
-        y = solve_mean(r[:, lo:hi])
+        y = ys[l] = solve_mean(r[:, lo:hi])
         cnt.block_solves += hi - lo
         B_l = level_block(sys, slice(0, lo), slice(lo, hi))
         r[:, :lo] -= B_l(y)
@@ -111,7 +117,7 @@ def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = Non
         C_l = level_block(sys, slice(lo, hi), slice(0, lo))
         w = r[:, lo:hi] - C_l(u[:, :lo])
         cnt.block_matvecs += count_blocks(sys, slice(lo, hi), slice(0, lo))
-        u[:, lo:hi] = solve_mean(w)
+        u[:, lo:hi] = solve_mean(w, ys[l]) if warm else solve_mean(w)
         cnt.block_solves += hi - lo
     return u
 

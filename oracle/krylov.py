@@ -95,14 +95,16 @@ class InnerStats:
     iterations: np.ndarray = None   # per column
 
 
-def pcg_columns(K0, B: np.ndarray, prec: Chebyshev, rtol: float, maxit: int, stats=None):
+def pcg_columns(K0, B: np.ndarray, prec: Chebyshev, rtol: float, maxit: int, stats=None, X0=None):
     """Independent PCG solves K_0 x_j = b_j, one per column of B (shape (n, m)).
 
-    Zero initial guess. Column j stops once its recursive residual satisfies
+    Initial guess zero, or the columns of X0 (then r = b - K_0 x0, and a
+    column whose initial residual already passes the test returns x0 without
+    iterating). Column j stops once its recursive residual satisfies
     ||r_j|| <= rtol ||b_j|| (checked after each update, before the next
     preconditioner application) or after ``maxit`` products with K_0.
-    A zero column gives x_j = 0 without iterating. rtol <= 0 runs exactly
-    ``maxit`` iterations.
+    A zero column gives x_j = 0 without iterating, whatever the initial
+    guess. rtol <= 0 runs exactly ``maxit`` iterations.
     """
     n, m = B.shape
     X = np.zeros_like(B)
@@ -112,8 +114,15 @@ def pcg_columns(K0, B: np.ndarray, prec: Chebyshev, rtol: float, maxit: int, sta
         bn = math.sqrt(dot(b, b))
         if bn == 0.0:
             continue
-        x = np.zeros(n)
-        r = b.copy()
+        if X0 is None:
+            x = np.zeros(n)
+            r = b.copy()
+        else:
+            x = np.array(X0[:, j], dtype=np.float64)
+            r = b - K0 @ x
+            if math.sqrt(dot(r, r)) <= rtol * bn:
+                X[:, j] = x
+                continue
         z = prec.apply(r[:, None])[:, 0]
         p = z.copy()
         gamma = dot(r, z)

@@ -34,7 +34,7 @@ class SgProblem(ctypes.Structure):
 class SgOpts(ctypes.Structure):
     _fields_ = [("inner_precision", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
                 ("inner_maxit", ctypes.c_int32), ("precond", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+                ("warm_start", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
 
 
 class SgStats(ctypes.Structure):
@@ -128,10 +128,11 @@ class Options:
     precond: str = "hsc"
     tile: int = 0
     inner_rtol: float = 1e-4
+    warm_start: bool = False
 
     def to_c(self) -> SgOpts:
         return SgOpts(self.inner_precision, self.cheb_degree, self.inner_maxit, _PC[self.precond],
-                      self.tile, 0, float(self.inner_rtol))
+                      self.tile, int(bool(self.warm_start)), float(self.inner_rtol))
 
 
 def _dptr(t: torch.Tensor) -> int:

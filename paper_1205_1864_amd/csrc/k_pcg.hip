@@ -16,7 +16,9 @@
 //   phase B: alpha = gamma / p.q, r -= alpha q (tile plus the Chebyshev
 //            halo), z = M r, partials r.r and r.z.
 // A column that stops (converged, or out of iterations) applies the pending
-// x update to its tiles first.
+// x update to its tiles first. A launch may start every column from the
+// contents of X (warm start, banded tiles): the start phase then forms
+// r = b - K_0 x on the region grown by one more node.
 // A column is split into tiles; each block owns a contiguous run of tiles (the
 // same tiles in every phase) and works on G tiles at a time, one per group of
 // waves; the waves of a group synchronise among themselves only.
@@ -160,7 +162,7 @@ struct ColView {
   long tbase;  // first index of the column's per-tile partials (and of its work items)
   const T* b;
   T *x, *r0, *r1, *p0, *p1, *q, *z;
-  T c0, c1, inv_diag, inv_theta;
+  T c0, c1, inv_diag, inv_theta, w8;
   const T* chebA;
   const T* chebB;
 };
@@ -276,9 +278,11 @@ struct SquareTile {
     return rz;
   }
 
-  // Start of the iteration: x = 0, z = M b; partials b.z and b.b.
-  __device__ static void start(const ColView<T>& v, int degree, int t, T* W0, T* W1, GroupBarrier& gb, double& rz,
-                               double& bb) {
+  __device__ static bool warm_fits(const ColView<T>&, int) { return false; }
+
+  // Start of the iteration: x = 0, z = M b; partials b.z, b.b and r.r = b.b.
+  __device__ static void start(const ColView<T>& v, int degree, int t, bool, T* W0, T* W1, GroupBarrier& gb,
+                               double& rz, double& bb, double& rr) {
     const int lt = threadIdx.x % kThreads;
     const int nx = v.nx;
     int x0, y0;
@@ -298,6 +302,7 @@ struct SquareTile {
         v.z[g] = Zi[k];
       }
     }
+    rr = bb;
   }
 
   // Phase A: p = z + beta p on the tile plus a 1-node halo, q = K_0 p; partial p.q.
@@ -339,8 +344,9 @@ struct SquareTile {
     return pq;
   }
 
-  // x += alpha p on the interior of a tile (the update a stopping column still owes).
-  __device__ static void finalize(const ColView<T>& v, int t, T alpha, const T* p) {
+  // x += alpha p on the interior of a tile, the update a stopping column still
+  // owes (zero: x = 0 instead).
+  __device__ static void finalize(const ColView<T>& v, int t, T alpha, const T* p, bool zero) {
     const int lt = threadIdx.x % kThreads;
     const int nx = v.nx;
     int x0, y0;
@@ -351,7 +357,11 @@ struct SquareTile {
       const int gx = x0 + i % TS, gy = y0 + i / TS;
       if (i < TS * TS && gx < nx && gy < nx) {
         const long g = (long)gy * nx + gx;
-        v.x[g] += alpha * p[g];
+        if (zero) {
+          v.x[g] = T(0);
+        } else {
+          v.x[g] += alpha * p[g];
+        }
       }
     }
   }
@@ -434,23 +444,25 @@ struct BandTile {
     y0 = (t / v.ntx) * TSY;
   }
 
-  // Chebyshev preconditioner on one tile; Zi[r], Ri[r] hold z and r at row
-  // wave * BR + r of the region (zero outside the interior of the tile and
-  // outside the grid). Returns the partial r.z.
+  // Chebyshev preconditioner on one tile: Zi[r] receives z and Ri[r] r at
+  // row wave * BR + r of the region. Ri is zero outside the interior of the
+  // tile; Zi is meaningful only there (callers mask it).
   //
   // Every sweep updates all rows and lanes of the band without branches, so
   // the rows of a band overlap in the pipeline. Values outside the part of
   // the region where W_j is valid ([j, R - j) in both directions) are
   // meaningless but never reach a valid value: a valid node of sweep j + 1
-  // reads only nodes valid in sweep j. Nodes outside the grid hold zero.
+  // reads only nodes valid in sweep j. Nodes outside the grid hold zero
+  // (homogeneous Dirichlet values); S is meaningful only inside the grid.
   // `val(r, o)` gives r at band row r (grid offset o) of the region; it is only
   // called for nodes inside the grid.
+  // H is the halo of the region: degree - 1, or degree when r is valid only
+  // off the outermost ring of the region (warm start).
   template <typename VF>
-  __device__ static double cheb(const ColView<T>& A, int degree, int x0, int y0, VF val, T* W0, T* W1,
-                                T (&Zi)[BR], T (&Ri)[BR], GroupBarrier& gb) {
+  __device__ static void cheb(const ColView<T>& A, int degree, int H, int x0, int y0, VF val, T* W0, T* W1,
+                              T (&Zi)[BR], T (&Ri)[BR], GroupBarrier& gb) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
-    const int H = degree - 1;
     const int tsx = A.tsx, nx = A.nx;
     const int RX = tsx + 2 * H, RY = TSY + 2 * H;
     const int gx = x0 - H + lane;
@@ -470,9 +482,10 @@ struct BandTile {
       const T w0 = S[r] * A.inv_theta;
       W0[ly * 64 + lane] = w0;
       const bool interior = xint && ly >= H && ly < H + TSY;
-      Zi[r] = interior ? w0 : T(0);
+      Zi[r] = w0;
       Ri[r] = interior ? rv : T(0);
     }
+    const T w8 = A.w8;
     T* cur = W0;
     T* nxt = W1;
     for (int j = 1; j < degree; ++j) {
@@ -498,15 +511,16 @@ struct BandTile {
           if (r >= BR) break;
           const int ly = yb + r;
           const T cp = cpv[k];
-          const T col = (cm + c0) + cp;
-          const T s8 = (from_prev(col) + from_next(col)) + (cm + cp);
+          const T vs = cm + cp;
+          const T col = vs + c0;
+          const T s8 = (from_prev(col) + from_next(col)) + vs;
+          // S - D^-1 K_0 W, with D^-1 K_0 W = W - s8 / 8
+          const T sn = S[r] - (c0 - w8 * s8);
+          S[r] = sn;
           const int gy = y0 - H + ly;
-          const bool upd = xin && gy >= 0 && gy < nx;
-          const T sn = S[r] - (c0 - T(0.125) * s8);
-          S[r] = upd ? sn : S[r];
-          const T wn = upd ? ca * c0 + cb * sn : T(0);
+          const T wn = xin && gy >= 0 && gy < nx ? ca * c0 + cb * sn : T(0);
           nxt[ly * 64 + lane] = wn;
-          if (xint && ly >= H && ly < H + TSY) Zi[r] += wn;
+          Zi[r] += wn;
           cm = c0;
           c0 = cp;
         }
@@ -515,33 +529,80 @@ struct BandTile {
       cur = nxt;
       nxt = t;
     }
-    double rz = 0.0;
-#pragma unroll
-    for (int r = 0; r < BR; ++r) rz += (double)Ri[r] * (double)Zi[r];
-    return rz;
   }
 
-  __device__ static void start(const ColView<T>& v, int degree, int t, T* W0, T* W1, GroupBarrier& gb, double& rz,
-                               double& bb) {
+  // Whether a column can start from the contents of X: the region grown by
+  // one more node must fit one wavefront and the LDS buffers.
+  __device__ static bool warm_fits(const ColView<T>& v, int degree) {
+    const int H1 = degree;  // (degree - 1) + 1
+    return v.tsx + 2 * H1 <= 64 && TSY + 2 * H1 <= RB;
+  }
+
+  // Start of the iteration: z = M r with r = b (x = 0), or r = b - K_0 x from
+  // the contents of x (warm). Partials r.z, b.b and r.r; a warm start stores r.
+  __device__ static void start(const ColView<T>& v, int degree, int t, bool warm, T* W0, T* W1, GroupBarrier& gb,
+                               double& rz, double& bb, double& rr) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
-    const int H = degree - 1, nx = v.nx;
+    const int nx = v.nx;
+    const int H = warm ? degree : degree - 1;
     int x0, y0;
     origin(v, t, x0, y0);
-    T Zi[BR], Ri[BR];
-    auto val = [&](int, unsigned o) { return v.b[o]; };
-    rz = cheb(v, degree, x0, y0, val, W0, W1, Zi, Ri, gb);
-    bb = 0.0;
+    const int RX = v.tsx + 2 * H, RY = TSY + 2 * H;
     const int gx = x0 - H + lane;
+    const bool xin = lane < RX && gx >= 0 && gx < nx;
+    const int yb = wv * BR;
+    T bv[BR], rv[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int ly = yb + r;
+      const int gy = y0 - H + ly;
+      bv[r] = T(0);
+      if (xin && ly < RY && gy >= 0 && gy < nx) bv[r] = v.b[(unsigned)(gy * nx + gx)];
+      rv[r] = bv[r];
+    }
+    if (warm) {
+      // r = b - K_0 x, valid off the outermost ring of the region
+      T xv[BR];
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        const int ly = yb + r;
+        const int gy = y0 - H + ly;
+        xv[r] = T(0);
+        if (xin && ly < RY && gy >= 0 && gy < nx) xv[r] = v.x[(unsigned)(gy * nx + gx)];
+        W1[ly * 64 + lane] = xv[r];
+      }
+      group_sync(gb);
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        const int ly = yb + r;
+        const T cm = W1[(ly > 0 ? ly - 1 : 0) * 64 + lane];
+        const T cp = W1[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane];
+        const T col = (cm + xv[r]) + cp;
+        const T s8 = (from_prev(col) + from_next(col)) + (cm + cp);
+        rv[r] = bv[r] - (v.c0 * xv[r] + v.c1 * s8);
+      }
+      // cheb's first sweep, which overwrites W1, begins with a group barrier
+    }
+    T Zi[BR], Ri[BR];
+    auto val = [&](int r, unsigned) { return rv[r]; };
+    cheb(v, degree, H, x0, y0, val, W0, W1, Zi, Ri, gb);
+    rz = bb = rr = 0.0;
     const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
-      const int ly = wv * BR + r;
+      const int ly = yb + r;
       const int gy = y0 - H + ly;
       if (xint && ly >= H && ly < H + TSY && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
-        bb += (double)Ri[r] * (double)Ri[r];
-        v.x[o] = T(0);
+        bb += (double)bv[r] * (double)bv[r];
+        rr += (double)Ri[r] * (double)Ri[r];
+        rz += (double)Ri[r] * (double)Zi[r];
+        if (warm) {
+          v.r0[o] = Ri[r];
+        } else {
+          v.x[o] = T(0);
+        }
         v.z[o] = Zi[r];
       }
     }
@@ -635,8 +696,9 @@ struct BandTile {
     }
   }
 
-  // x += alpha p on the interior of a tile (the update a stopping column still owes).
-  __device__ static void finalize(const ColView<T>& v, int t, T alpha, const T* p) {
+  // x += alpha p on the interior of a tile, the update a stopping column still
+  // owes (zero: x = 0 instead).
+  __device__ static void finalize(const ColView<T>& v, int t, T alpha, const T* p, bool zero) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
@@ -650,7 +712,11 @@ struct BandTile {
       const int gy = y0 + ly;
       if (lane < v.tsx && gx < nx && ly < TSY && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
-        v.x[o] += alpha * p[o];
+        if (zero) {
+          v.x[o] = T(0);
+        } else {
+          v.x[o] += alpha * p[o];
+        }
       }
     }
   }
@@ -689,8 +755,8 @@ struct BandTile {
     origin(v, t, x0, y0);
     T Zi[BR], Ri[BR];
     auto val = [&](int r, unsigned) { return in.r[r] - I.alpha * in.q[r]; };
-    rz = cheb(v, degree, x0, y0, val, W0, W1, Zi, Ri, gb);
-    rr = 0.0;
+    cheb(v, degree, H, x0, y0, val, W0, W1, Zi, Ri, gb);
+    rz = rr = 0.0;
     const int gx = x0 - H + lane;
     const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
 #pragma unroll
@@ -702,6 +768,7 @@ struct BandTile {
         I.rn[o] = Ri[r];
         v.z[o] = Zi[r];
         rr += (double)Ri[r] * (double)Ri[r];
+        rz += (double)Ri[r] * (double)Zi[r];
       }
     }
   }
@@ -784,6 +851,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       v.c1 = ld_uniform(&k->c1, 0);
       v.inv_diag = ld_uniform(&k->inv_diag, 0);
       v.inv_theta = ld_uniform(&k->inv_theta, 0);
+      v.w8 = ld_uniform(&k->w8, 0);
       v.chebA = k->chebA;
       v.chebB = k->chebB;
     } else {
@@ -804,6 +872,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       v.c1 = A.c1;
       v.inv_diag = A.inv_diag;
       v.inv_theta = A.inv_theta;
+      v.w8 = A.w8;
       v.chebA = A.chebA;
       v.chebB = A.chebB;
     }
@@ -837,6 +906,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
     t1 = (int)(hi - v.tbase);
   };
   auto owner = [&](const ColView<T>& v) { return v.tbase >= w_begin; };  // this block holds tile 0
+  // the column starts from the contents of its x
+  auto warm_of = [&](const ColView<T>& v) { return A.warm && Tile::warm_fits(v, degree); };
   // Fixed-order sums of up to five per-tile partial arrays of a column, one wave each.
   auto col_sums = [&](const ColView<T>& v, const double* q0, const double* q1, const double* q2, const double* q3,
                       const double* q4) {
@@ -860,7 +931,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
   }
   __syncthreads();
 
-  // ---- start (column phase 1): x = 0, z = M b, partials b.b and b.z
+  // ---- start (column phase 1): z = M r with r = b (x = 0) or r = b - K_0 x (warm); partials b.b, r.z, r.r
   for (int c = c_first; c <= c_last; ++c) {
     const ColView<T> v = view(c);
     if (sdone[c - c_first]) {
@@ -870,13 +941,16 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
     int t0, t1;
     tiles_of(v, t0, t1);
     if (t1 <= t0) continue;
+    const bool warm = warm_of(v);
     for (int t = t0 + grp; t < t1; t += G) {
-      double rz, bb;
-      Tile::start(v, degree, t, W0, W1, gb, rz, bb);
+      double rz, bb, rr, unused = 0.0;
+      Tile::start(v, degree, t, warm, W0, W1, gb, rz, bb, rr);
       group_sum2<GT>(rz, bb, sred, gb);
+      group_sum2<GT>(rr, unused, sred, gb);
       if (lt == 0) {
         P(PART_RZ1)[v.tbase + t] = rz;
         P(PART_BB)[v.tbase + t] = bb;
+        P(PART_RR1)[v.tbase + t] = rr;
       }
     }
     column_arrive(arr + c, (unsigned)(t1 - t0));
@@ -899,21 +973,22 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         break;
       }
       const bool first = it == 0;
-      col_sums(v, P(PART_BB), first ? nullptr : P(par ? PART_RR0 : PART_RR1),
-               first ? nullptr : P(par ? PART_RZ0 : PART_RZ1), first ? nullptr : P(par ? PART_RZ1 : PART_RZ0),
-               first ? nullptr : P(par ? PART_PQ0 : PART_PQ1));
+      col_sums(v, P(PART_BB), P(par ? PART_RR0 : PART_RR1), first ? nullptr : P(par ? PART_RZ0 : PART_RZ1),
+               first ? nullptr : P(par ? PART_RZ1 : PART_RZ0), first ? nullptr : P(par ? PART_PQ0 : PART_PQ1));
       const double bb = s4[0];
-      const double rr = first ? s4[0] : s4[1];
+      const double rr = s4[1];
       IterVecs<T> I{};
       I.first = first;
       I.po = par ? v.p0 : v.p1;
       I.pn = par ? v.p1 : v.p0;
       I.beta = first ? T(0) : (T)(s4[2] / s4[3]);
       I.alpha_prev = first ? T(0) : (T)(s4[3] / s4[4]);
-      if (it == A.maxit || sqrt(rr) <= A.rtol * sqrt(bb)) {
-        // stop: apply the pending update x += alpha' p'
-        if (!first)
-          for (int t = t0 + grp; t < t1; t += G) Tile::finalize(v, t, I.alpha_prev, I.po);
+      if (it == A.maxit || bb == 0.0 || sqrt(rr) <= A.rtol * sqrt(bb)) {
+        // stop: apply the pending update x += alpha' p' (a zero right-hand side
+        // gives x = 0 also from a warm start)
+        const bool zero = first && bb == 0.0 && warm_of(v);
+        if (!first || zero)
+          for (int t = t0 + grp; t < t1; t += G) Tile::finalize(v, t, I.alpha_prev, I.po, zero);
         __syncthreads();
         if (threadIdx.x == 0) {
           sdone[c - c_first] = 1;
@@ -954,7 +1029,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       I.first = it == 0;
       I.alpha = (T)(gam / pq);
       I.pn = par ? v.p1 : v.p0;
-      I.ro = it == 0 ? v.b : (par ? v.r1 : v.r0);
+      I.ro = it == 0 ? (warm_of(v) ? v.r0 : v.b) : (par ? v.r1 : v.r0);
       I.rn = par ? v.r0 : v.r1;
       Tile::run_b(v, degree, t0 + grp, t1, G, I, W0, W1, gb, sred, P(par ? PART_RZ1 : PART_RZ0) + v.tbase,
                   P(par ? PART_RR1 : PART_RR0) + v.tbase);

@@ -238,9 +238,10 @@ std::vector<sgk::PcgCols<double>>& sets<double>(sg_batch_ctx* B) { return B->col
 template <>
 std::vector<sgk::PcgCols<float>>& sets<float>(sg_batch_ctx* B) { return B->cols32; }
 
-// Ragged inner launch over column set s, restricted to problems of degree >= pmin.
+// Ragged inner launch over column set s, restricted to problems of degree >= pmin;
+// warm: start from the contents of X where the options allow it.
 template <typename T>
-int run_set(sg_batch_ctx* B, int s, int pmin = 0) {
+int run_set(sg_batch_ctx* B, int s, int pmin = 0, bool warm = false) {
   const int ncols = B->set_ncols[s];
   if (ncols <= 0) return SG_OK;
   sgk::PcgArgs<T> a{};
@@ -248,6 +249,7 @@ int run_set(sg_batch_ctx* B, int s, int pmin = 0) {
   a.degree = B->degree;
   a.maxit = B->opts.inner_maxit;
   a.rtol = B->opts.inner_rtol > 0.0 ? B->opts.inner_rtol : 0.0;
+  a.warm = warm && B->opts.warm_start && B->tile != 16;
   a.sc = B->sc;
   const sgk::PcgCols<T>& cols = sets<T>(B)[s];
   // only the columns of problems that still iterate take part in the launch
@@ -275,7 +277,7 @@ int batch_hsc(sg_batch_ctx* B) {
   for (int l = 1; l <= B->pmax; ++l) {
     for (sg_ctx* h : B->h)
       if (h->p >= l) sgh::coupling<T>(h, l, 1, (T*)h->rw, zw(h));  // w = r_l^l - C_l u_{l-1}
-    rc = run_set<T>(B, l);  // u_l^l = D_l^-1 w
+    rc = run_set<T>(B, l, 0, true);  // u_l^l = D_l^-1 w, warm from y_l
     if (rc) return rc;
   }
   return SG_OK;
@@ -298,7 +300,7 @@ int batch_bgs(sg_batch_ctx* B) {
     // problems whose top level is l keep their forward values on level l
     for (sg_ctx* h : B->h)
       if (h->p >= l + 1) sgh::coupling<T>(h, l + 1, 0, (T*)h->rw, zw(h));
-    rc = run_set<T>(B, l, l + 1);
+    rc = run_set<T>(B, l, l + 1, true);  // z_l, warm from z'_l
     if (rc) return rc;
   }
   return SG_OK;
@@ -442,6 +444,7 @@ int sg_batch_setup(int32_t count, const sg_problem* probs, const sg_opts* opts, 
       k.c1 = a.c1;
       k.inv_diag = a.inv_diag;
       k.inv_theta = a.inv_theta;
+      k.w8 = a.w8;
       std::copy(a.chebA, a.chebA + sgk::kMaxCheb, k.chebA);
       std::copy(a.chebB, a.chebB + sgk::kMaxCheb, k.chebB);
       std::memcpy(consts.data() + sizeof(k) * b, &k, sizeof(k));
@@ -453,6 +456,7 @@ int sg_batch_setup(int32_t count, const sg_problem* probs, const sg_opts* opts, 
       k.c1 = a.c1;
       k.inv_diag = a.inv_diag;
       k.inv_theta = a.inv_theta;
+      k.w8 = a.w8;
       std::copy(a.chebA, a.chebA + sgk::kMaxCheb, k.chebA);
       std::copy(a.chebB, a.chebB + sgk::kMaxCheb, k.chebB);
       std::memcpy(consts.data() + sizeof(k) * b, &k, sizeof(k));

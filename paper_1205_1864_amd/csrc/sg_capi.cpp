@@ -113,6 +113,7 @@ int validate(const sg_problem* pr, const sg_opts* op) {
   if (op->inner_maxit < 1) return fail(SG_EINVAL, "inner_maxit must be >= 1");
   if (op->precond < SG_PC_NONE || op->precond > SG_PC_BGS) return fail(SG_EINVAL, "unknown preconditioner");
   if (op->tile != 0 && op->tile != 16 && op->tile != 32) return fail(SG_EINVAL, "tile must be 0, 16 or 32");
+  if (op->warm_start != 0 && op->warm_start != 1) return fail(SG_EINVAL, "warm_start must be 0 or 1");
   if (!(op->inner_rtol < 1.0) || std::isnan(op->inner_rtol)) return fail(SG_EINVAL, "inner_rtol must be < 1");
   return SG_OK;
 }
@@ -348,6 +349,7 @@ void fill_pcg_consts(const sg_ctx* h, sgk::PcgArgs<T>& a) {
   a.c1 = (T)(-h->theta0 / 3.0);
   a.inv_diag = (T)(1.0 / diag);
   a.inv_theta = (T)(1.0 / theta);
+  a.w8 = (T)0.125;
   for (int j = 0; j < sgk::kMaxCheb; ++j) {
     a.chebA[j] = T(0);
     a.chebB[j] = T(0);
@@ -376,9 +378,11 @@ int choose_tile(const sg_ctx* h, int degree) {
   return degree <= 8 ? 32 : 16;
 }
 
-// Batched inner PCG on `ncols` contiguous columns (inner precision T).
+// Batched inner PCG on `ncols` contiguous columns (inner precision T). warm:
+// start from the contents of X where the options allow it, else from zero.
 template <typename T>
-int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::vector<int>* iters_out = nullptr) {
+int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::vector<int>* iters_out = nullptr,
+            bool warm = false) {
   if (ncols <= 0) return SG_OK;
   if (ncols > h->pcg_maxcols) return fail(SG_EINVAL, "too many columns for the inner solver");
   sgk::PcgArgs<T> a{};
@@ -400,8 +404,8 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.degree = degree;
   a.maxit = h->opts.inner_maxit;
   a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;
+  a.warm = warm && h->opts.warm_start && tile != 16;
   fill_pcg_consts<T>(h, a);
-  a.degree = degree;
   SG_HIP(hipEventRecord(h->ev0, h->stream));
   SG_HIP(sgk::launch_pcg<T>(a, tile, h->pcg_max_blocks, h->stream));
   SG_HIP(hipEventRecord(h->ev1, h->stream));
@@ -419,9 +423,9 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   for (int v : it) {
     h->inner_it_acc += v;
     // phase A reads z, p and x and writes p, q and x; phase B reads r and q and writes r
-    // and z; the start reads b and writes z and x; a column that stops after at least
-    // one iteration reads x and p and writes x once more
-    h->inner_bytes_acc += (10.0 * v + (v > 0 ? 6.0 : 3.0)) * (double)h->n * sizeof(T);
+    // and z; the start reads b and writes z and x (warm: reads b and x, writes z and r);
+    // a column that stops after at least one iteration reads x and p and writes x once more
+    h->inner_bytes_acc += (10.0 * v + (v > 0 ? 6.0 : 3.0) + (a.warm ? 1.0 : 0.0)) * (double)h->n * sizeof(T);
     mx = std::max(mx, v);
   }
   if (level_for_stats >= 0 && level_for_stats < sgk::kMaxLevels)
@@ -514,7 +518,8 @@ int hsc_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs, int ptop) {
     const int lo = h->off[l], hi = h->off[l + 1];
     coupling<T>(h, l, 1, rw, Zb);  // w = r_l^l - C_l u_{l-1}
     *nbmv += coupling_blocks(h, l, 1);
-    rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l);  // u_l^l = D_l^-1 w
+    // u_l^l = D_l^-1 w, from y_l of the down sweep when warm starts are on
+    rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l, nullptr, true);
     if (rc) return rc;
     *nbs += hi - lo;
   }
@@ -543,7 +548,8 @@ int bgs_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs) {
     const int lo = h->off[l], hi = h->off[l + 1];
     coupling<T>(h, l + 1, 0, rw, Zb);  // ... - B_{l+1} z_{l+1}
     *nbmv += coupling_blocks(h, l + 1, 0);
-    rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l);  // z_l
+    // z_l, from z'_l of the forward sweep when warm starts are on
+    rc = run_pcg<T>(h, rw + lo * n, Zb + lo * n, hi - lo, l, nullptr, true);
     if (rc) return rc;
     *nbs += hi - lo;
   }

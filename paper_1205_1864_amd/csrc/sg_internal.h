@@ -19,7 +19,7 @@ constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 // Tiles of the inner PCG on an nx x nx grid. tile == 16: square 16 x 16 tiles.
 // Otherwise banded tiles of tsx x kBandRows nodes, tsx = ceil(nx / ntx), sized
 // so that the tile plus its Chebyshev halo (degree - 1 nodes, at least one)
-// spans at most one wavefront of 64 columns. Tiles are numbered row-major:
+// plus one more node spans at most one wavefront of 64 columns. Tiles are numbered row-major:
 // tile t covers columns (t % ntx) * tsx ... and rows (t / ntx) * tile height ...
 constexpr int kBandRows = 32;
 inline void pcg_tiling(int nx, int degree, int tile, int& ntx, int& ntiles) {
@@ -28,7 +28,8 @@ inline void pcg_tiling(int nx, int degree, int tile, int& ntx, int& ntiles) {
     ntiles = ntx * ntx;
     return;
   }
-  const int h = degree - 1 > 1 ? degree - 1 : 1;
+  // one more node on each side for the residual of a warm start
+  const int h = (degree - 1 > 1 ? degree - 1 : 1) + 1;
   const int wmax = 64 - 2 * h;
   ntx = (nx + wmax - 1) / wmax;
   ntiles = ntx * ((nx + kBandRows - 1) / kBandRows);
@@ -152,10 +153,13 @@ struct PcgArgs {
   int degree;
   int maxit;
   double rtol;
+  int warm;    // start each column from the contents of its x (banded tiles), else from 0
   T c0;        // centre weight of K_0: theta0 * 8/3
   T c1;        // neighbour weight of K_0: -theta0 / 3
   T inv_diag;  // 1 / (theta0 * 8/3)
   T inv_theta; // 1 / centre of the Chebyshev interval
+  T w8;        // 1/8: neighbour weight of the Jacobi-scaled stencil D^-1 K_0 (a runtime value, so
+               // that the kernels take it from a scalar register)
   T chebA[kMaxCheb];
   T chebB[kMaxCheb];
 };
@@ -163,7 +167,7 @@ struct PcgArgs {
 // Per-problem constants of a ragged launch (same meaning as the fields of PcgArgs).
 template <typename T>
 struct PcgConsts {
-  T c0, c1, inv_diag, inv_theta;
+  T c0, c1, inv_diag, inv_theta, w8;
   T chebA[kMaxCheb];
   T chebB[kMaxCheb];
 };

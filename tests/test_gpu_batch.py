@@ -41,11 +41,13 @@ def _rhs(probs):
     return F
 
 
-@pytest.mark.parametrize("prec,pc", [(64, "hsc"), (32, "hsc"), (64, "mean"), (64, "bgs"), (32, "bgs")])
-def test_batch_matches_single_solves(prec, pc):
+@pytest.mark.parametrize("prec,pc,warm", [(64, "hsc", False), (32, "hsc", False), (64, "mean", False),
+                                          (64, "bgs", False), (32, "bgs", False), (64, "hsc", True),
+                                          (32, "hsc", True), (64, "bgs", True)])
+def test_batch_matches_single_solves(prec, pc, warm):
     b = _b()
     probs = _problems()
-    opts = b.Options(inner_precision=prec, precond=pc, inner_rtol=1e-4)
+    opts = b.Options(inner_precision=prec, precond=pc, inner_rtol=1e-4, warm_start=warm)
     batch = b.SGBatch(probs, opts)
     F = _rhs(probs)
     U, stats, info = batch.sg_batch_solve(F, rtol=1e-8, maxit=100, use_graph=True)

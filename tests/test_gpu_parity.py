@@ -158,12 +158,67 @@ def test_preconditioner_tight_parity(which, kw):
     assert np.linalg.norm(Z - Zo) <= 1e-9 * np.linalg.norm(Zo)
 
 
-@pytest.mark.parametrize("prec,pc", [(64, "hsc"), (32, "hsc"), (64, "mean"), (32, "mean"), (64, "bgs"), (32, "bgs")])
-def test_solve_small(prec, pc):
+@pytest.mark.parametrize("which", ["hsc", "bgs"])
+@pytest.mark.parametrize("kw", [dict(n_e=24, M=3, p=3), dict(n_e=64, M=4, p=2), dict(n_e=19, M=2, p=4)])
+def test_preconditioner_tight_parity_warm(which, kw):
+    """Warm-started up-sweep (backward-sweep) solves reach the same action."""
+    b = _b()
+    prob, s = _sys(**kw)
+    solver = b.SGSolver(prob, b.Options(inner_precision=64, inner_rtol=1e-13, inner_maxit=2000, warm_start=True))
+    R = random_block(prob.P, prob.n, seed=9)
+    apply = solver.sg_apply_hsc if which == "hsc" else solver.sg_apply_bgs
+    Z = apply(_dev(R)).cpu().numpy()
+    ex = hsc.ExactMeanSolver(s)
+    Zo = (hsc.hsc_apply(s, R.T, ex) if which == "hsc" else bgs.bgs_apply(s, R.T, ex)).T
+    assert np.linalg.norm(Z - Zo) <= 1e-9 * np.linalg.norm(Zo)
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-11), (32, 1e-4)])
+@pytest.mark.parametrize("n_e", [4, 52, 130])
+@pytest.mark.parametrize("degree,tile", [(1, 0), (2, 0), (4, 0), (8, 0), (4, 16)])
+def test_hsc_warm_fixed_iterations(prec, tol, n_e, degree, tile):
+    """Three inner iterations per solve, up sweep from y_l: element-wise against the
+    oracle's Algorithm 1 with the same inner PCG from the same initial guesses (16 x 16
+    tiles start from zero)."""
+    b = _b()
+    prob, s = _sys(n_e=n_e, M=2, p=2, sigma=0.3)
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=degree, inner_maxit=3, inner_rtol=0.0,
+                                        tile=tile, warm_start=True))
+    R = random_block(prob.P, prob.n, seed=12)
+    Z = solver.sg_apply_hsc(_dev(R)).cpu().numpy()
+    inner = hsc.PCGMeanSolver(s, 0.0, 3, degree)
+    Zo = hsc.hsc_apply(s, R.T, inner, warm=tile != 16).T
+    assert np.linalg.norm(Z - Zo) <= tol * np.linalg.norm(Zo)
+    if tile != 16 and prec == 64 and n_e >= 52:
+        # a cold start gives a different action (three iterations are far from converged here)
+        Zc = hsc.hsc_apply(s, R.T, hsc.PCGMeanSolver(s, 0.0, 3, degree)).T
+        assert np.linalg.norm(Z - Zc) > 1e3 * tol * np.linalg.norm(Zo)
+
+
+def test_warm_start_saves_inner_iterations():
+    b = _b()
+    prob, s = _sys(n_e=64, M=4, p=3, sigma=0.3)
+    F = prob.load_block()
+    out = {}
+    for warm in (False, True):
+        solver = b.SGSolver(prob, b.Options(inner_precision=64, cheb_degree=8, inner_rtol=1e-4, warm_start=warm))
+        U, st = solver.sg_solve(_dev(F), rtol=1e-8, maxit=100)
+        assert st["rc"] == 0 and st["true_relres"] <= 1.05e-8
+        out[warm] = (U.cpu().numpy(), st)
+    (Uc, sc), (Uw, sw) = out[False], out[True]
+    assert abs(sc["outer_it"] - sw["outer_it"]) <= 1
+    assert sw["inner_it_total"] < sc["inner_it_total"]
+    assert np.linalg.norm(Uw - Uc) <= 1e-6 * np.linalg.norm(Uc)
+
+
+@pytest.mark.parametrize("prec,pc,warm", [(64, "hsc", False), (32, "hsc", False), (64, "mean", False),
+                                          (32, "mean", False), (64, "bgs", False), (32, "bgs", False),
+                                          (64, "hsc", True), (32, "hsc", True), (64, "bgs", True), (32, "bgs", True)])
+def test_solve_small(prec, pc, warm):
     b = _b()
     prob, s = _sys()
     F = prob.load_block()
-    solver = b.SGSolver(prob, b.Options(inner_precision=prec, precond=pc, inner_rtol=1e-4))
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, precond=pc, inner_rtol=1e-4, warm_start=warm))
     U, st = solver.sg_solve(_dev(F), rtol=1e-8, maxit=100)
     U = U.cpu().numpy()
     assert st["rc"] == 0

@@ -143,3 +143,57 @@ def test_mean_preconditioner_is_block_inverse():
     Z = hsc.mean_apply(s, R, hsc.ExactMeanSolver(s))
     assert np.linalg.norm(s.K[0] @ Z - R) <= 1e-12 * np.linalg.norm(R)
     assert hsc.diagonal_blocks_are_mean(s)
+
+
+def test_inner_pcg_initial_guess():
+    """PCG from an initial guess x0: the textbook shift x = x0 + d, K_0 d = b - K_0 x0."""
+    n_e = 18
+    K0 = fe.assemble_stiffness(np.full((n_e, n_e), 0.9), n_e)
+    prec = krylov.make_chebyshev(K0, n_e, 0.9, 3)
+    rng = np.random.default_rng(11)
+    n = K0.shape[0]
+    B = rng.standard_normal((n, 4))
+    B[:, 1] = 0.0
+    X0 = rng.standard_normal((n, 4))
+    ref = np.linalg.solve(K0.toarray(), B)
+    # exact initial guess: no iteration, x0 returned; a zero column gives 0 whatever x0
+    st = krylov.InnerStats()
+    X = krylov.pcg_columns(K0, B, prec, 1e-10, 500, st, ref)
+    assert np.all(st.iterations == 0)
+    assert np.array_equal(X[:, [0, 2, 3]], ref[:, [0, 2, 3]]) and np.all(X[:, 1] == 0.0)
+    X = krylov.pcg_columns(K0, B, prec, 1e-10, 500, None, X0)
+    assert np.all(X[:, 1] == 0.0)
+    # fixed iteration count: the iterates from x0 are x0 plus those of the shifted system from 0
+    for m in (1, 4):
+        Xw = krylov.pcg_columns(K0, B, prec, 0.0, m, None, X0)
+        D = krylov.pcg_columns(K0, B - K0 @ X0, prec, 0.0, m)
+        for j in (0, 2, 3):
+            assert np.linalg.norm(Xw[:, j] - (X0[:, j] + D[:, j])) <= 1e-12 * np.linalg.norm(Xw[:, j])
+    # to tolerance from a random guess, and fewer iterations from a close one
+    st_w, st_c = krylov.InnerStats(), krylov.InnerStats()
+    Xw = krylov.pcg_columns(K0, B, prec, 1e-10, 500, st_w, X0)
+    krylov.pcg_columns(K0, B, prec, 1e-10, 500, st_c, ref + 1e-4 * X0)
+    for j in (0, 2, 3):
+        assert np.linalg.norm(B[:, j] - K0 @ Xw[:, j]) <= 1.01e-10 * np.linalg.norm(B[:, j])
+    st0 = krylov.InnerStats()
+    krylov.pcg_columns(K0, B, prec, 1e-10, 500, st0)
+    assert np.all(st_c.iterations[[0, 2, 3]] < st0.iterations[[0, 2, 3]])
+
+
+def test_hsc_warm_up_sweep():
+    """Starting the up-sweep solves from y_l changes nothing with exact solves and,
+    with inner PCG to a tight tolerance, gives the same action in fewer inner iterations."""
+    prob = named_problem("small", n_e=14, M=3, p=3, sigma=0.3)
+    s = sg.build_system(prob)
+    R = np.random.default_rng(4).standard_normal((s.n, s.P))
+    ex = hsc.ExactMeanSolver(s)
+    Zx = hsc.hsc_apply(s, R, ex)
+    assert np.array_equal(hsc.hsc_apply(s, R, ex, warm=True), Zx)
+    cold = hsc.PCGMeanSolver(s, 1e-12, 2000, 4)
+    warm = hsc.PCGMeanSolver(s, 1e-12, 2000, 4)
+    Zc = hsc.hsc_apply(s, R, cold)
+    Zw = hsc.hsc_apply(s, R, warm, warm=True)
+    assert np.linalg.norm(Zw - Zx) <= 1e-9 * np.linalg.norm(Zx)
+    assert np.linalg.norm(Zc - Zx) <= 1e-9 * np.linalg.norm(Zx)
+    up = slice(prob.p + 1, None)  # the up-sweep solves are the last p calls
+    assert sum(int(v.sum()) for v in warm.iterations[up]) < sum(int(v.sum()) for v in cold.iterations[up])
