@@ -155,6 +155,18 @@ __device__ void group_sum2(double& a, double& b, double (*sred)[GT / 64][2], Gro
   b = sb;
 }
 
+// K_0 v at a node from its column sums: cm, c, cp are v at the node below,
+// the node and the node above (one lane per grid column); the horizontal
+// neighbours come from the adjacent lanes. c0, c1: centre and neighbour
+// weights of K_0. Every product with K_0 of the banded tiles uses this one
+// expression, so a value computed twice is the same bit for bit.
+template <typename T>
+__device__ __forceinline__ T k0_apply(T cm, T c, T cp, T c0, T c1) {
+  const T col = (cm + c) + cp;
+  const T s8 = (from_prev(col) + from_next(col)) + (cm + cp);
+  return c0 * c + c1 * s8;
+}
+
 // The grid, state vectors and constants of one column.
 template <typename T>
 struct ColView {
@@ -187,6 +199,7 @@ struct IterVecs {
 template <typename T, int TS, int NS>
 struct SquareTile {
   static constexpr int kThreads = kSquareGroup;
+  static constexpr bool kStoresQ = true;  // phase B reads q = K_0 p from memory
   static constexpr int NI = (TS * TS + kThreads - 1) / kThreads;  // interior nodes per thread
   // elements of T in one group's LDS buffers (two buffers; phase A needs a 1-node halo)
   static int lds_group(int degree) {
@@ -425,18 +438,20 @@ struct SquareTile {
 template <typename T, int TSY, int HMAX, int NW>
 struct BandTile {
   static constexpr int kThreads = 64 * NW;
+  static constexpr bool kStoresQ = false;  // phase B recomputes q = K_0 p
   static constexpr int RYMAX = TSY + 2 * HMAX;
   static constexpr int BR = (RYMAX + NW - 1) / NW;     // region rows per wave (Chebyshev)
   static constexpr int BRA = (TSY + 2 + NW - 1) / NW;  // region rows per wave (phase A, halo 1)
   static constexpr int RB = NW * BR;                   // rows of one LDS buffer (bands padded)
   static constexpr int CH = 2;                         // rows per chunk of a sweep (registers)
   static_assert(NW * BRA <= RB, "phase A rows exceed the buffer");
+  static_assert(TSY + 2 * (HMAX + 1) <= RB, "phase B needs the Chebyshev halo plus one row");
   static int lds_group(int) { return 2 * RB * 64; }
   static bool fits(int degree, int nx, int ntx, int ntiles) {
     const int H = degree - 1;
     if (H > HMAX || ntx < 1) return false;
     const int tsx = (nx + ntx - 1) / ntx;
-    const int h = H > 1 ? H : 1;
+    const int h = (H > 1 ? H : 1) + 1;  // phase B: Chebyshev halo plus one node
     return tsx + 2 * h <= 64 && ntiles == ntx * ((nx + TSY - 1) / TSY);
   }
   __device__ static void origin(const ColView<T>& v, int t, int& x0, int& y0) {
@@ -578,9 +593,7 @@ struct BandTile {
         const int ly = yb + r;
         const T cm = W1[(ly > 0 ? ly - 1 : 0) * 64 + lane];
         const T cp = W1[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane];
-        const T col = (cm + xv[r]) + cp;
-        const T s8 = (from_prev(col) + from_next(col)) + (cm + cp);
-        rv[r] = bv[r] - (v.c0 * xv[r] + v.c1 * s8);
+        rv[r] = bv[r] - k0_apply(cm, xv[r], cp, v.c0, v.c1);
       }
       // cheb's first sweep, which overwrites W1, begins with a group barrier
     }
@@ -664,14 +677,11 @@ struct BandTile {
       const int ly = yb + r;
       const T cm = W0[(ly > 0 ? ly - 1 : 0) * 64 + lane];
       const T cp = W0[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane];
-      const T col = (cm + pc[r]) + cp;
-      const T s8 = (from_prev(col) + from_next(col)) + (cm + cp);
-      const T qv = v.c0 * pc[r] + v.c1 * s8;
+      const T qv = k0_apply(cm, pc[r], cp, v.c0, v.c1);
       const int gy = y0 - 1 + ly;
       if (xint && ly >= 1 && ly <= TSY && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
-        I.pn[o] = pc[r];
-        v.q[o] = qv;
+        I.pn[o] = pc[r];  // q is recomputed in phase B
         pq += (double)pc[r] * (double)qv;
       }
     }
@@ -721,14 +731,16 @@ struct BandTile {
     }
   }
 
-  // Inputs of phase B on this wave's rows of the region (tile plus the Chebyshev halo).
+  // Inputs of phase B on this wave's rows of the region: r and p on the tile
+  // grown by `degree` nodes (the Chebyshev halo plus one node, so that
+  // q = K_0 p is known on the Chebyshev region without storing q).
   struct InB {
-    T r[BR], q[BR];
+    T r[BR], p[BR];
   };
   __device__ static void load_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, InB& in) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
-    const int H = degree - 1, nx = v.nx;
+    const int H = degree, nx = v.nx;
     int x0, y0;
     origin(v, t, x0, y0);
     const int gx = x0 - H + lane;
@@ -737,11 +749,11 @@ struct BandTile {
     for (int r = 0; r < BR; ++r) {
       const int ly = wv * BR + r;
       const int gy = y0 - H + ly;
-      in.r[r] = in.q[r] = T(0);
+      in.r[r] = in.p[r] = T(0);
       if (xin && ly < TSY + 2 * H && gy >= 0 && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
         in.r[r] = I.ro[o];
-        in.q[r] = v.q[o];
+        in.p[r] = I.pn[o];
       }
     }
   }
@@ -750,11 +762,28 @@ struct BandTile {
                                    T* W0, T* W1, GroupBarrier& gb, double& rz, double& rr) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
-    const int H = degree - 1, nx = v.nx;
+    const int H = degree, nx = v.nx;
     int x0, y0;
     origin(v, t, x0, y0);
+    const int yb = wv * BR;
+    // q = K_0 p on the region, valid off its outermost ring (rows above and
+    // below through LDS; every read of W1 by the previous tile ended before
+    // the group reduction that closed it)
+#pragma unroll
+    for (int r = 0; r < BR; ++r) W1[(yb + r) * 64 + lane] = in.p[r];
+    group_sync(gb);
+    // r - alpha q goes to this thread's own slots of W0, where step 0 reads it
+    // back before overwriting it
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int ly = yb + r;
+      const T cm = W1[(ly > 0 ? ly - 1 : 0) * 64 + lane];
+      const T cp = W1[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane];
+      W0[ly * 64 + lane] = in.r[r] - I.alpha * k0_apply(cm, in.p[r], cp, v.c0, v.c1);
+    }
     T Zi[BR], Ri[BR];
-    auto val = [&](int r, unsigned) { return in.r[r] - I.alpha * in.q[r]; };
+    auto val = [&](int r, unsigned) { return W0[(yb + r) * 64 + lane]; };
+    // cheb's first sweep, which overwrites W1, begins with a group barrier
     cheb(v, degree, H, x0, y0, val, W0, W1, Zi, Ri, gb);
     rz = rr = 0.0;
     const int gx = x0 - H + lane;

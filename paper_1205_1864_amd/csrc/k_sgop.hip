@@ -428,9 +428,9 @@ __device__ __forceinline__ void march_body(const SgOpArgs<T>& A, const StripTabl
   const T* __restrict__ in = A.in;
   const T* __restrict__ acoef = A.a;
 
-  // Neighbour columns and weights of the group's rows (uniform, read once).
-  // A missing neighbour gets column 0 and weight 0, so every load of a step is
-  // issued without waiting for a table read and contributes nothing.
+  // Neighbour columns and weights of the group's rows (uniform, read once);
+  // a missing neighbour has column -1 and weight 0 and is not loaded (a
+  // uniform branch on a scalar register).
   int cl[RG][NK], cu[RG][NK];
   T wl[RG][NK], wu[RG][NK];
 #pragma unroll
@@ -455,8 +455,8 @@ __device__ __forceinline__ void march_body(const SgOpArgs<T>& A, const StripTabl
           }
         }
       }
-      cl[j][s] = lo >= 0 ? lo : 0;
-      cu[j][s] = up >= 0 ? up : 0;
+      cl[j][s] = lo;
+      cu[j][s] = up;
       wl[j][s] = gl;
       wu[j][s] = gu;
     }
@@ -498,8 +498,8 @@ __device__ __forceinline__ void march_body(const SgOpArgs<T>& A, const StripTabl
         ul[j][s] = T(0);
         uu[j][s] = T(0);
         if (row >= 0) {
-          if (LK || A.use_lower) ul[j][s] = in[(long)cl[j][s] * n + nid];
-          if (!LK && A.use_upper) uu[j][s] = in[(long)cu[j][s] * n + nid];
+          if (cl[j][s] >= 0) ul[j][s] = in[(long)cl[j][s] * n + nid];
+          if (!LK && cu[j][s] >= 0) uu[j][s] = in[(long)cu[j][s] * n + nid];
         }
       }
     }

@@ -422,10 +422,12 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   int mx = 0;
   for (int v : it) {
     h->inner_it_acc += v;
-    // phase A reads z, p and x and writes p, q and x; phase B reads r and q and writes r
-    // and z; the start reads b and writes z and x (warm: reads b and x, writes z and r);
-    // a column that stops after at least one iteration reads x and p and writes x once more
-    h->inner_bytes_acc += (10.0 * v + (v > 0 ? 6.0 : 3.0) + (a.warm ? 1.0 : 0.0)) * (double)h->n * sizeof(T);
+    // phase A reads z, p and x and writes p and x (and q with 16 x 16 tiles); phase B
+    // reads r and p (q) and writes r and z; the start reads b and writes z and x (warm:
+    // reads b and x, writes z and r); a column that stops after at least one iteration
+    // reads x and p and writes x once more
+    const double per_it = tile == 16 ? 10.0 : 9.0;
+    h->inner_bytes_acc += (per_it * v + (v > 0 ? 6.0 : 3.0) + (a.warm ? 1.0 : 0.0)) * (double)h->n * sizeof(T);
     mx = std::max(mx, v);
   }
   if (level_for_stats >= 0 && level_for_stats < sgk::kMaxLevels)
