@@ -38,8 +38,8 @@ CHEB_DEGREE = 8  # updates of the Chebyshev preconditioner of the inner PCG
 # runs of this benchmark, scaled by the same counters of a 512 MiB elementwise
 # kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Set to None when the
 # kernel changes.
-PCG_TRAFFIC_BYTES = 25.30e9     # pcg_kernel<double, BandTile<double, 32, 7, 8>, 2>, average over a solve's launches
-MATVEC_TRAFFIC_BYTES = {(2, 2): 572.1e6}  # sgop_march_kernel<double, 10>, one SG matvec, by schedule
+PCG_TRAFFIC_BYTES = 23.59e9     # pcg_kernel<double, BandTile<double, 32, 7, 8>, 2>, average over a solve's launches
+MATVEC_TRAFFIC_BYTES = {(2, 2): 570.4e6, (2, 1): 543.0e6}  # sgop_march_kernel<double, 10>, one SG matvec, by schedule
 
 
 def log(msg):
@@ -223,7 +223,12 @@ def main():
         for label, o in [("hsc_fp32", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="hsc", inner_maxit=2000)),
                          ("mean_fp64", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000)),
                          ("mean_fp32", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="mean", inner_maxit=2000)),
-                         ("bgs_fp64", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="bgs", inner_maxit=2000))]:
+                         ("bgs_fp64", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="bgs", inner_maxit=2000)),
+                         # up-sweep (backward-sweep) inner solves started from the down-sweep values
+                         ("hsc_fp64_warm", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="hsc",
+                                                   inner_maxit=2000, warm_start=True)),
+                         ("bgs_fp64_warm", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="bgs",
+                                                   inner_maxit=2000, warm_start=True))]:
             sv = SGSolver(prob, o)
             sv.sg_autotune(3)
             Uv = sv.empty()
