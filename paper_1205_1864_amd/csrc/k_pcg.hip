@@ -1149,8 +1149,9 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
 #endif
     constexpr int NW = SGPC_BAND_NW;
     constexpr int G = SGPC_BAND_G;
-    if (H <= 3) return launch_cfg<T, BandTile<T, kBandRows, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
-    if (H <= 7) return launch_cfg<T, BandTile<T, kBandRows, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);
+    constexpr int TSY = kBandRowsOf<T>;
+    if (H <= 3) return launch_cfg<T, BandTile<T, TSY, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
+    if (H <= 7) return launch_cfg<T, BandTile<T, TSY, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);
     return hipErrorInvalidValue;
   }
   return launch_cfg<T, SquareTile<T, 16, slots(16, 15)>, 4, RAGGED>(args, cols, max_blocks, s);

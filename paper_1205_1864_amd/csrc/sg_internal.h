@@ -17,12 +17,16 @@ constexpr int kPcgPartials = 7;  // per-tile partial-sum arrays of the inner sol
 constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 
 // Tiles of the inner PCG on an nx x nx grid. tile == 16: square 16 x 16 tiles.
-// Otherwise banded tiles of tsx x kBandRows nodes, tsx = ceil(nx / ntx), sized
+// Otherwise banded tiles of tsx x `rows` nodes, tsx = ceil(nx / ntx), sized
 // so that the tile plus its Chebyshev halo (degree - 1 nodes, at least one)
 // plus one more node spans at most one wavefront of 64 columns. Tiles are numbered row-major:
-// tile t covers columns (t % ntx) * tsx ... and rows (t / ntx) * tile height ...
-constexpr int kBandRows = 32;
-inline void pcg_tiling(int nx, int degree, int tile, int& ntx, int& ntiles) {
+// tile t covers columns (t % ntx) * tsx ... and rows (t / ntx) * rows ...
+// The band height is 32 rows in FP64 and 64 in FP32, where the registers of a
+// band allow it (a taller band recomputes less of the halo).
+template <typename T>
+constexpr int kBandRowsOf = sizeof(T) == 4 ? 64 : 32;
+inline int band_rows(int inner_precision) { return inner_precision == 32 ? kBandRowsOf<float> : kBandRowsOf<double>; }
+inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& ntiles) {
   if (tile == 16) {
     ntx = (nx + 15) / 16;
     ntiles = ntx * ntx;
@@ -32,7 +36,7 @@ inline void pcg_tiling(int nx, int degree, int tile, int& ntx, int& ntiles) {
   const int h = (degree - 1 > 1 ? degree - 1 : 1) + 1;
   const int wmax = 64 - 2 * h;
   ntx = (nx + wmax - 1) / wmax;
-  ntiles = ntx * ((nx + kBandRows - 1) / kBandRows);
+  ntiles = ntx * ((nx + rows - 1) / rows);
 }
 
 // Chaos neighbour lists of the Hermite Galerkin matrices G_k (k >= 1): for
