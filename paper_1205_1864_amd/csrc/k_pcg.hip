@@ -1141,14 +1141,10 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
   if (args.ncols <= 0) return hipSuccess;
   const int H = args.degree - 1;
   if (tile != 16) {
-    // banded tiles: two groups of eight waves per block (16 waves per CU; the
-    // next tile's inputs prefetched in registers)
-#ifndef SGPC_BAND_NW
-#define SGPC_BAND_NW 8
-#define SGPC_BAND_G 2
-#endif
-    constexpr int NW = SGPC_BAND_NW;
-    constexpr int G = SGPC_BAND_G;
+    // banded tiles, 16 waves per block (one group of 16 waves in FP64, two of
+    // 8 in FP32); the next tile's inputs prefetched in registers
+    constexpr int NW = kBandWavesOf<T>;
+    constexpr int G = kBandGroupsOf<T>;
     constexpr int TSY = kBandRowsOf<T>;
     if (H <= 3) return launch_cfg<T, BandTile<T, TSY, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
     if (H <= 7) return launch_cfg<T, BandTile<T, TSY, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);

@@ -21,10 +21,16 @@ constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 // so that the tile plus its Chebyshev halo (degree - 1 nodes, at least one)
 // plus one more node spans at most one wavefront of 64 columns. Tiles are numbered row-major:
 // tile t covers columns (t % ntx) * tsx ... and rows (t / ntx) * rows ...
-// The band height is 32 rows in FP64 and 64 in FP32, where the registers of a
-// band allow it (a taller band recomputes less of the halo).
+// The band height is 64 rows (a taller band recomputes less of the halo); a
+// tile is worked on by 16 waves in FP64 (one tile group per block) and by 8
+// waves in FP32 (two tile groups per block), so that a wave's share of the
+// band fits its registers.
 template <typename T>
-constexpr int kBandRowsOf = sizeof(T) == 4 ? 64 : 32;
+constexpr int kBandRowsOf = 64;
+template <typename T>
+constexpr int kBandWavesOf = sizeof(T) == 4 ? 8 : 16;
+template <typename T>
+constexpr int kBandGroupsOf = sizeof(T) == 4 ? 2 : 1;
 inline int band_rows(int inner_precision) { return inner_precision == 32 ? kBandRowsOf<float> : kBandRowsOf<double>; }
 inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& ntiles) {
   if (tile == 16) {
