@@ -33,12 +33,12 @@ import numpy as np  # noqa: E402
 
 METRIC = "SG solve s to relres 1e-8 + matvec HBM GB/s (256², M=10, p=3); adjoint grad s"
 HBM_PEAK_GBS = 8000.0
-CHEB_DEGREE = 8  # updates of the Chebyshev preconditioner of the inner PCG
+CHEB_DEGREE = 16  # updates of the Chebyshev preconditioner of the inner PCG (fastest measured; 8 as an extra)
 # HBM bytes per launch measured with separate FETCH_SIZE and WRITE_SIZE counter
 # runs of this benchmark, scaled by the same counters of a 512 MiB elementwise
 # kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Set to None when the
 # kernel changes.
-PCG_TRAFFIC_BYTES = 22.12e9     # pcg_kernel<double, BandTile<double, 64, 7, 16>, 1>, average over a solve's launches
+PCG_TRAFFIC_BYTES = None  # pcg_kernel<double, BandTile<double, 64, 15, 16>, 1>: to be measured, average over a solve's launches
 MATVEC_TRAFFIC_BYTES = {(2, 2): 570.4e6, (2, 1): 543.0e6}  # sgop_march_kernel<double, 10>, one SG matvec, by schedule
 
 
@@ -228,7 +228,10 @@ def main():
                          ("hsc_fp64_warm", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="hsc",
                                                    inner_maxit=2000, warm_start=True)),
                          ("bgs_fp64_warm", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="bgs",
-                                                   inner_maxit=2000, warm_start=True))]:
+                                                   inner_maxit=2000, warm_start=True)),
+                         # the same solves with a degree-8 Chebyshev preconditioner
+                         ("hsc_fp64_d8", Options(inner_precision=64, cheb_degree=8, precond="hsc", inner_maxit=2000)),
+                         ("hsc_fp32_d8", Options(inner_precision=32, cheb_degree=8, precond="hsc", inner_maxit=2000))]:
             sv = SGSolver(prob, o)
             sv.sg_autotune(3)
             Uv = sv.empty()

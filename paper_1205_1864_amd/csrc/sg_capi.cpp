@@ -372,10 +372,10 @@ template void fill_pcg_consts<float>(const sg_ctx*, sgk::PcgArgs<float>&);
 int effective_degree(const sg_ctx* h) { return h->lmax - h->lmin > 0.0 ? h->opts.cheb_degree : 1; }
 
 int choose_tile(const sg_ctx* h, int degree) {
-  // banded tiles (code 32) up to degree 8; the halo of larger degrees does not
-  // fit one wavefront, so they take 16 x 16 tiles
+  // banded tiles (code 32) up to the precision's band degree limit; beyond it
+  // the halo does not fit one wavefront (or the band its registers), so 16 x 16 tiles
   if (h->opts.tile == 16) return 16;
-  return degree <= 8 ? 32 : 16;
+  return degree <= sgk::band_max_degree(h->opts.inner_precision) ? 32 : 16;
 }
 
 // Batched inner PCG on `ncols` contiguous columns (inner precision T). warm:
@@ -983,7 +983,8 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     sgk::launch_fill(h->pv, 1.0, N, s);
     if (h->opts.inner_precision == 32) sgk::launch_copy_d2f((float*)h->rw, h->pv, N, s);
     else sgk::launch_copy_d2d((double*)h->rw, h->pv, N, s);
-    std::vector<int> tiles = degree <= 8 ? std::vector<int>{32, 16} : std::vector<int>{16};
+    std::vector<int> tiles = degree <= sgk::band_max_degree(h->opts.inner_precision) ? std::vector<int>{32, 16}
+                                                                                       : std::vector<int>{16};
     std::vector<int> blocks = {0, std::max(1, h->num_cu / 2)};
     double best = 1e300;
     int bt = choose_tile(h, degree), bb = h->pcg_max_blocks;

@@ -31,6 +31,12 @@ template <typename T>
 constexpr int kBandWavesOf = sizeof(T) == 4 ? 8 : 16;
 template <typename T>
 constexpr int kBandGroupsOf = sizeof(T) == 4 ? 2 : 1;
+// Highest Chebyshev degree served by banded tiles: the halo (degree - 1) plus
+// one node on each side leaves 32 interior columns of 64 lanes at degree 16.
+// Above degree 8 both precisions use one 16-wave group per block (a wave's
+// share of the taller region fits its registers). Higher degrees take 16 x 16 tiles.
+constexpr int kBandMaxDegree = 16;
+inline int band_max_degree(int) { return kBandMaxDegree; }
 inline int band_rows(int inner_precision) { return inner_precision == 32 ? kBandRowsOf<float> : kBandRowsOf<double>; }
 inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& ntiles) {
   if (tile == 16) {

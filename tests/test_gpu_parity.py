@@ -79,13 +79,15 @@ def test_inner_solve_fixed_iterations(prec, tol, degree, tile):
 
 
 @pytest.mark.parametrize("prec,tol", [(64, 1e-11), (32, 2e-5)])
-@pytest.mark.parametrize("n_e", [4, 51, 52, 130])
-@pytest.mark.parametrize("degree", [1, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("n_e", [4, 33, 34, 49, 50, 130])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4, 5, 8, 12, 16])
 def test_inner_solve_band_geometry(prec, tol, n_e, degree):
     """Banded inner tiles at the edges of their geometry: a grid smaller than
-    the halo (n_e = 4), a tile plus halo exactly one wavefront wide (n_e = 51
-    at degree 8), one column more (n_e = 52) and several ragged tiles
-    (n_e = 130), for both halo capacities (degree <= 4 and <= 8)."""
+    the halo (n_e = 4); a tile plus its halo and the extra node exactly one
+    wavefront wide (nx = 64 - 2d: n_e = 49 at degree 8, 33 at degree 16) and
+    one column more (n_e = 50, 34); several ragged tiles in both directions
+    (n_e = 130); every halo capacity (degree <= 4, 8, 12, 16; FP32 above 8
+    takes the 16 x 16 tiles)."""
     b = _b()
     prob, s = _sys(n_e=n_e, M=2, p=1)
     print(f"inner band prec={prec} n_e={n_e} degree={degree}", flush=True)
