@@ -1148,8 +1148,9 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
     constexpr int TSY = kBandRowsOf<T>;
     if (H <= 3) return launch_cfg<T, BandTile<T, TSY, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
     if (H <= 7) return launch_cfg<T, BandTile<T, TSY, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);
-    if (H <= 11) return launch_cfg<T, BandTile<T, TSY, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
-    if (H <= 15) return launch_cfg<T, BandTile<T, TSY, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+    constexpr int TSYH = kBandRowsHiOf<T>;
+    if (H <= 11) return launch_cfg<T, BandTile<T, TSYH, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+    if (H <= 15) return launch_cfg<T, BandTile<T, TSYH, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
     return hipErrorInvalidValue;
   }
   return launch_cfg<T, SquareTile<T, 16, slots(16, 15)>, 4, RAGGED>(args, cols, max_blocks, s);

@@ -123,7 +123,7 @@ int make_batch_plan(int count, const sg_problem* probs, const sg_opts* op, Batch
   for (int b = 0; b < count; ++b) {
     const std::vector<int> off = level_offsets(probs[b].M, probs[b].p);
     int ntx = 0, nt = 0;
-    sgk::pcg_tiling(probs[b].n_e - 1, op->cheb_degree, tile, sgk::band_rows(op->inner_precision), ntx, nt);
+    sgk::pcg_tiling(probs[b].n_e - 1, op->cheb_degree, tile, sgk::band_rows(op->inner_precision, op->cheb_degree), ntx, nt);
     for (int l = 0; l <= probs[b].p; ++l) {
       bp.set_ncols[l] += off[l + 1] - off[l];
       bp.set_nwork[l] += (long)(off[l + 1] - off[l]) * nt;
@@ -175,7 +175,7 @@ int build_set(sg_batch_ctx* B, int s, char* base, std::vector<char>& host, sgk::
     }
     const long n = h->n;
     int t = 0, nt = 0;
-    sgk::pcg_tiling(h->nx, B->degree, B->tile, sgk::band_rows(B->inner), t, nt);
+    sgk::pcg_tiling(h->nx, B->degree, B->tile, sgk::band_rows(B->inner, B->degree), t, nt);
     T* rw = (T*)h->rw;
     T* zw = B->inner == 32 ? (T*)h->zw : (T*)h->z;
     for (int j = j0; j < j1; ++j) {

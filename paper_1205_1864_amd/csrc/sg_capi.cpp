@@ -400,7 +400,7 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.Q = (T*)h->pQ;
   a.Z = (T*)h->pZ;
   a.sc = h->pcgsc;
-  sgk::pcg_tiling(h->nx, degree, tile, sgk::kBandRowsOf<T>, a.ntx, a.ntiles);
+  sgk::pcg_tiling(h->nx, degree, tile, sgk::band_rows(sizeof(T) == 4 ? 32 : 64, degree), a.ntx, a.ntiles);
   a.degree = degree;
   a.maxit = h->opts.inner_maxit;
   a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;

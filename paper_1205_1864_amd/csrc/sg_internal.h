@@ -26,7 +26,9 @@ constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 // waves in FP32 (two tile groups per block), so that a wave's share of the
 // band fits its registers.
 template <typename T>
-constexpr int kBandRowsOf = 64;
+constexpr int kBandRowsOf = 64;    // degrees <= 8
+template <typename T>
+constexpr int kBandRowsHiOf = sizeof(T) == 4 ? 128 : 64;  // degrees 9 .. 16 (FP64: LDS and registers)
 template <typename T>
 constexpr int kBandWavesOf = sizeof(T) == 4 ? 8 : 16;
 template <typename T>
@@ -37,7 +39,10 @@ constexpr int kBandGroupsOf = sizeof(T) == 4 ? 2 : 1;
 // share of the taller region fits its registers). Higher degrees take 16 x 16 tiles.
 constexpr int kBandMaxDegree = 16;
 inline int band_max_degree(int) { return kBandMaxDegree; }
-inline int band_rows(int inner_precision) { return inner_precision == 32 ? kBandRowsOf<float> : kBandRowsOf<double>; }
+inline int band_rows(int inner_precision, int degree) {
+  if (inner_precision == 32) return degree > 8 ? kBandRowsHiOf<float> : kBandRowsOf<float>;
+  return degree > 8 ? kBandRowsHiOf<double> : kBandRowsOf<double>;
+}
 inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& ntiles) {
   if (tile == 16) {
     ntx = (nx + 15) / 16;
