@@ -430,10 +430,12 @@ struct SquareTile {
 // ---------------------------------------------------------------------------
 // Banded tiles: tsx x TSY nodes. The region (tile plus halo) has one column
 // per lane (at most 64) and its rows are split into NW bands of BR rows, one
-// per wave of the group. LDS rows are 64 values apart, so a wave reads or writes one region
-// row with one conflict-free access. A stencil update takes the row above and
-// the row below from a sliding window (one LDS read per node) and the column
-// sums of the neighbouring lanes by DPP.
+// per wave of the group. Each wave keeps its band in registers: a stencil
+// update takes the horizontal neighbours from the adjacent lanes (DPP), the
+// rows above and below from the wave's own registers, and only the rows just
+// outside the band from the neighbouring waves, through a small LDS exchange
+// area (two rows per wave, two buffers used alternately). r on the interior
+// of the tile waits in LDS while the Chebyshev sweeps run.
 // ---------------------------------------------------------------------------
 template <typename T, int TSY, int HMAX, int NW>
 struct BandTile {
@@ -442,11 +444,32 @@ struct BandTile {
   static constexpr int RYMAX = TSY + 2 * HMAX;
   static constexpr int BR = (RYMAX + NW - 1) / NW;     // region rows per wave (Chebyshev)
   static constexpr int BRA = (TSY + 2 + NW - 1) / NW;  // region rows per wave (phase A, halo 1)
-  static constexpr int RB = NW * BR;                   // rows of one LDS buffer (bands padded)
-  static constexpr int CH = 2;                         // rows per chunk of a sweep (registers)
-  static_assert(NW * BRA <= RB, "phase A rows exceed the buffer");
+  static constexpr int RB = NW * BR;                   // region rows covered by the bands
+  static constexpr int kEx = 2 * NW * 2 * 64;          // exchange area: 2 buffers x NW waves x 2 rows
+  // the next tile's inputs are loaded during the current one, except where two
+  // copies of them do not fit the registers (FP64 bands taller than 64 rows)
+  static constexpr bool kPrefetch = !(sizeof(T) == 8 && TSY > 64);
+  static_assert(NW * BRA <= RB, "phase A rows exceed the bands");
   static_assert(TSY + 2 * (HMAX + 1) <= RB, "phase B needs the Chebyshev halo plus one row");
-  static int lds_group(int) { return 2 * RB * 64; }
+  // elements of T per group: the exchange area, then r of the region rows
+  static int lds_group(int) { return kEx + RB * 64; }
+
+  // Band-edge exchange of an N-row band partition: the row above the band
+  // (last row of the wave before) and the row below it (first row of the wave
+  // after); zero at the ends of the region. Consecutive exchanges must use
+  // alternate buffers: a wave may write buffer b again only after every wave
+  // has passed the barrier of an exchange in the other buffer.
+  template <int N>
+  __device__ static void exchange(const T (&v)[N], T* E, int buf, T& up, T& dn, GroupBarrier& gb) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    T* e = E + buf * (NW * 2 * 64);
+    e[(wv * 2 + 0) * 64 + lane] = v[0];
+    e[(wv * 2 + 1) * 64 + lane] = v[N - 1];
+    group_sync(gb);
+    up = wv > 0 ? e[((wv - 1) * 2 + 1) * 64 + lane] : T(0);
+    dn = wv + 1 < NW ? e[((wv + 1) * 2 + 0) * 64 + lane] : T(0);
+  }
   static bool fits(int degree, int nx, int ntx, int ntiles) {
     const int H = degree - 1;
     if (H > HMAX || ntx < 1) return false;
@@ -459,9 +482,10 @@ struct BandTile {
     y0 = (t / v.ntx) * TSY;
   }
 
-  // Chebyshev preconditioner on one tile: Zi[r] receives z and Ri[r] r at
-  // row wave * BR + r of the region. Ri is zero outside the interior of the
-  // tile; Zi is meaningful only there (callers mask it).
+  // Chebyshev preconditioner on one tile: Zi[r] receives z at row
+  // wave * BR + r of the region (meaningful only on the interior of the tile;
+  // callers mask it) and Rl[(wave * BR + r) * 64 + lane] r on the interior
+  // (zero elsewhere; read back by the same thread).
   //
   // Every sweep updates all rows and lanes of the band without branches, so
   // the rows of a band overlap in the pipeline. Values outside the part of
@@ -469,13 +493,14 @@ struct BandTile {
   // meaningless but never reach a valid value: a valid node of sweep j + 1
   // reads only nodes valid in sweep j. Nodes outside the grid hold zero
   // (homogeneous Dirichlet values); S is meaningful only inside the grid.
-  // `val(r, o)` gives r at band row r (grid offset o) of the region; it is only
-  // called for nodes inside the grid.
+  // `val(r)` gives r at band row r of the region for every lane (it may use
+  // DPP, so it runs unmasked); its value at nodes outside the grid is dropped.
   // H is the halo of the region: degree - 1, or degree when r is valid only
-  // off the outermost ring of the region (warm start).
+  // off the outermost ring of the region (warm start). The sweeps exchange
+  // through buffers 1, 0, 1, ... of E.
   template <typename VF>
-  __device__ static void cheb(const ColView<T>& A, int degree, int H, int x0, int y0, VF val, T* W0, T* W1,
-                              T (&Zi)[BR], T (&Ri)[BR], GroupBarrier& gb) {
+  __device__ static void cheb(const ColView<T>& A, int degree, int H, int x0, int y0, VF val, T* E, T* Rl,
+                              T (&Zi)[BR], GroupBarrier& gb) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int tsx = A.tsx, nx = A.nx;
@@ -484,65 +509,44 @@ struct BandTile {
     const bool xin = lane < RX && gx >= 0 && gx < nx;          // lane holds a grid column
     const bool xint = lane >= H && lane < H + tsx && gx < nx;  // interior column of the tile
     const int yb = wv * BR;                                    // first region row of this wave
-    T S[BR];
+    T S[BR], W[BR];
     // step 0: S = D^-1 r, W = S / theta
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const int ly = yb + r;
       const int gy = y0 - H + ly;
       const bool in = xin && ly < RY && gy >= 0 && gy < nx;
-      T rv = T(0);
-      if (in) rv = val(r, (unsigned)(gy * nx + gx));
+      const T v = val(r);
+      const T rv = in ? v : T(0);
       S[r] = rv * A.inv_diag;
-      const T w0 = S[r] * A.inv_theta;
-      W0[ly * 64 + lane] = w0;
+      W[r] = S[r] * A.inv_theta;
+      Zi[r] = W[r];
       const bool interior = xint && ly >= H && ly < H + TSY;
-      Zi[r] = w0;
-      Ri[r] = interior ? rv : T(0);
+      Rl[ly * 64 + lane] = interior ? rv : T(0);
     }
     const T w8 = A.w8;
-    T* cur = W0;
-    T* nxt = W1;
     for (int j = 1; j < degree; ++j) {
-      // all rows of cur are written and every read of nxt (the older buffer) is done
-      group_sync(gb);
+      T up, dn;
+      exchange(W, E, j & 1, up, dn, gb);
       const T ca = ld_uniform(A.chebA, j), cb = ld_uniform(A.chebB, j);
-      T cm = cur[(yb > 0 ? yb - 1 : 0) * 64 + lane];
-      T c0 = cur[yb * 64 + lane];
-      // rows in chunks of CH: the reads of a chunk are issued together (the
-      // compiler keeps them behind the previous chunk's writes, since it
-      // cannot tell that cur and nxt do not overlap)
+      T cm = up;
 #pragma unroll
-      for (int r0 = 0; r0 < BR; r0 += CH) {
-        T cpv[CH];
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          const int ly = yb + r0 + k;
-          cpv[k] = r0 + k < BR ? cur[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane] : T(0);
-        }
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          const int r = r0 + k;
-          if (r >= BR) break;
-          const int ly = yb + r;
-          const T cp = cpv[k];
-          const T vs = cm + cp;
-          const T col = vs + c0;
-          const T s8 = (from_prev(col) + from_next(col)) + vs;
-          // S - D^-1 K_0 W, with D^-1 K_0 W = W - s8 / 8
-          const T sn = S[r] - (c0 - w8 * s8);
-          S[r] = sn;
-          const int gy = y0 - H + ly;
-          const T wn = xin && gy >= 0 && gy < nx ? ca * c0 + cb * sn : T(0);
-          nxt[ly * 64 + lane] = wn;
-          Zi[r] += wn;
-          cm = c0;
-          c0 = cp;
-        }
+      for (int r = 0; r < BR; ++r) {
+        const int ly = yb + r;
+        const T c0 = W[r];
+        const T cp = r + 1 < BR ? W[r + 1] : dn;
+        const T vs = cm + cp;
+        const T col = vs + c0;
+        const T s8 = (from_prev(col) + from_next(col)) + vs;
+        // S - D^-1 K_0 W, with D^-1 K_0 W = W - s8 / 8
+        const T sn = S[r] - (c0 - w8 * s8);
+        S[r] = sn;
+        const int gy = y0 - H + ly;
+        const T wn = xin && gy >= 0 && gy < nx ? ca * c0 + cb * sn : T(0);
+        W[r] = wn;
+        Zi[r] += wn;
+        cm = c0;
       }
-      T* t = cur;
-      cur = nxt;
-      nxt = t;
     }
   }
 
@@ -555,8 +559,10 @@ struct BandTile {
 
   // Start of the iteration: z = M r with r = b (x = 0), or r = b - K_0 x from
   // the contents of x (warm). Partials r.z, b.b and r.r; a warm start stores r.
-  __device__ static void start(const ColView<T>& v, int degree, int t, bool warm, T* W0, T* W1, GroupBarrier& gb,
+  __device__ static void start(const ColView<T>& v, int degree, int t, bool warm, T* W0, T*, GroupBarrier& gb,
                                double& rz, double& bb, double& rr) {
+    T* E = W0;
+    T* Rl = W0 + kEx;
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
@@ -567,52 +573,43 @@ struct BandTile {
     const int gx = x0 - H + lane;
     const bool xin = lane < RX && gx >= 0 && gx < nx;
     const int yb = wv * BR;
-    T bv[BR], rv[BR];
+    const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
+    T bv[BR], xv[BR];
+    bb = 0.0;
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const int ly = yb + r;
       const int gy = y0 - H + ly;
-      bv[r] = T(0);
-      if (xin && ly < RY && gy >= 0 && gy < nx) bv[r] = v.b[(unsigned)(gy * nx + gx)];
-      rv[r] = bv[r];
+      const bool in = xin && ly < RY && gy >= 0 && gy < nx;
+      bv[r] = xv[r] = T(0);
+      if (in) bv[r] = v.b[(unsigned)(gy * nx + gx)];
+      if (warm && in) xv[r] = v.x[(unsigned)(gy * nx + gx)];
+      if (xint && ly >= H && ly < H + TSY && gy < nx) bb += (double)bv[r] * (double)bv[r];
     }
-    if (warm) {
-      // r = b - K_0 x, valid off the outermost ring of the region
-      T xv[BR];
-#pragma unroll
-      for (int r = 0; r < BR; ++r) {
-        const int ly = yb + r;
-        const int gy = y0 - H + ly;
-        xv[r] = T(0);
-        if (xin && ly < RY && gy >= 0 && gy < nx) xv[r] = v.x[(unsigned)(gy * nx + gx)];
-        W1[ly * 64 + lane] = xv[r];
-      }
-      group_sync(gb);
-#pragma unroll
-      for (int r = 0; r < BR; ++r) {
-        const int ly = yb + r;
-        const T cm = W1[(ly > 0 ? ly - 1 : 0) * 64 + lane];
-        const T cp = W1[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane];
-        rv[r] = bv[r] - k0_apply(cm, xv[r], cp, v.c0, v.c1);
-      }
-      // cheb's first sweep, which overwrites W1, begins with a group barrier
-    }
-    T Zi[BR], Ri[BR];
-    auto val = [&](int r, unsigned) { return rv[r]; };
-    cheb(v, degree, H, x0, y0, val, W0, W1, Zi, Ri, gb);
-    rz = bb = rr = 0.0;
-    const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
+    // warm: r = b - K_0 x, valid off the outermost ring of the region
+    // (exchange buffer 0; the sweeps continue with 1, 0, ...)
+    T up = T(0), dn = T(0);
+    if (warm) exchange(xv, E, 0, up, dn, gb);
+    auto val = [&](int r) {
+      if (!warm) return bv[r];
+      const T cm = r > 0 ? xv[r - 1] : up;
+      const T cp = r + 1 < BR ? xv[r + 1] : dn;
+      return bv[r] - k0_apply(cm, xv[r], cp, v.c0, v.c1);
+    };
+    T Zi[BR];
+    cheb(v, degree, H, x0, y0, val, E, Rl, Zi, gb);
+    rz = rr = 0.0;
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const int ly = yb + r;
       const int gy = y0 - H + ly;
       if (xint && ly >= H && ly < H + TSY && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
-        bb += (double)bv[r] * (double)bv[r];
-        rr += (double)Ri[r] * (double)Ri[r];
-        rz += (double)Ri[r] * (double)Zi[r];
+        const T ri = Rl[ly * 64 + lane];
+        rr += (double)ri * (double)ri;
+        rz += (double)ri * (double)Zi[r];
         if (warm) {
-          v.r0[o] = Ri[r];
+          v.r0[o] = ri;
         } else {
           v.x[o] = T(0);
         }
@@ -668,15 +665,15 @@ struct BandTile {
       pc[r] = I.first ? in.z[r] : in.z[r] + I.beta * in.po[r];
       if (!I.first && xint && ly >= 1 && ly <= TSY && gy < nx)
         v.x[(unsigned)(gy * nx + gx)] = in.x[r] + I.alpha_prev * in.po[r];
-      if (ly < TSY + 2) W0[ly * 64 + lane] = pc[r];
     }
-    group_sync(gb);
+    T up, dn;
+    exchange(pc, W0, 0, up, dn, gb);
     double pq = 0.0;
 #pragma unroll
     for (int r = 0; r < BRA; ++r) {
       const int ly = yb + r;
-      const T cm = W0[(ly > 0 ? ly - 1 : 0) * 64 + lane];
-      const T cp = W0[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane];
+      const T cm = r > 0 ? pc[r - 1] : up;
+      const T cp = r + 1 < BRA ? pc[r + 1] : dn;
       const T qv = k0_apply(cm, pc[r], cp, v.c0, v.c1);
       const int gy = y0 - 1 + ly;
       if (xint && ly >= 1 && ly <= TSY && gy < nx) {
@@ -698,11 +695,12 @@ struct BandTile {
     for (int t = t_begin; t < t_end; t += step) {
       InA nxt;
       const bool more = t + step < t_end;
-      if (more) load_a(v, t + step, I, nxt);
+      if (kPrefetch && more) load_a(v, t + step, I, nxt);
       double pq = compute_a(v, t, I, cur, W0, gb), unused = 0.0;
       group_sum2<kThreads>(pq, unused, sred, gb);
       if ((threadIdx.x % kThreads) == 0) part[t] = pq;
-      if (more) cur = nxt;
+      if (kPrefetch && more) cur = nxt;
+      if (!kPrefetch && more) load_a(v, t + step, I, cur);
     }
   }
 
@@ -766,25 +764,19 @@ struct BandTile {
     int x0, y0;
     origin(v, t, x0, y0);
     const int yb = wv * BR;
-    // q = K_0 p on the region, valid off its outermost ring (rows above and
-    // below through LDS; every read of W1 by the previous tile ended before
-    // the group reduction that closed it)
-#pragma unroll
-    for (int r = 0; r < BR; ++r) W1[(yb + r) * 64 + lane] = in.p[r];
-    group_sync(gb);
-    // r - alpha q goes to this thread's own slots of W0, where step 0 reads it
-    // back before overwriting it
-#pragma unroll
-    for (int r = 0; r < BR; ++r) {
-      const int ly = yb + r;
-      const T cm = W1[(ly > 0 ? ly - 1 : 0) * 64 + lane];
-      const T cp = W1[(ly + 1 < RB ? ly + 1 : RB - 1) * 64 + lane];
-      W0[ly * 64 + lane] = in.r[r] - I.alpha * k0_apply(cm, in.p[r], cp, v.c0, v.c1);
-    }
-    T Zi[BR], Ri[BR];
-    auto val = [&](int r, unsigned) { return W0[(yb + r) * 64 + lane]; };
-    // cheb's first sweep, which overwrites W1, begins with a group barrier
-    cheb(v, degree, H, x0, y0, val, W0, W1, Zi, Ri, gb);
+    T* E = W0;
+    T* Rl = W0 + kEx;
+    // r - alpha q with q = K_0 p on the region, valid off its outermost ring
+    // (exchange buffer 0; the sweeps continue with 1, 0, ...)
+    T up, dn;
+    exchange(in.p, E, 0, up, dn, gb);
+    auto val = [&](int r) {
+      const T cm = r > 0 ? in.p[r - 1] : up;
+      const T cp = r + 1 < BR ? in.p[r + 1] : dn;
+      return in.r[r] - I.alpha * k0_apply(cm, in.p[r], cp, v.c0, v.c1);
+    };
+    T Zi[BR];
+    cheb(v, degree, H, x0, y0, val, E, Rl, Zi, gb);
     rz = rr = 0.0;
     const int gx = x0 - H + lane;
     const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
@@ -794,10 +786,11 @@ struct BandTile {
       const int gy = y0 - H + ly;
       if (xint && ly >= H && ly < H + TSY && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
-        I.rn[o] = Ri[r];
+        const T ri = Rl[ly * 64 + lane];
+        I.rn[o] = ri;
         v.z[o] = Zi[r];
-        rr += (double)Ri[r] * (double)Ri[r];
-        rz += (double)Ri[r] * (double)Zi[r];
+        rr += (double)ri * (double)ri;
+        rz += (double)ri * (double)Zi[r];
       }
     }
   }
@@ -813,7 +806,7 @@ struct BandTile {
     for (int t = t_begin; t < t_end; t += step) {
       InB nxt;
       const bool more = t + step < t_end;
-      if (more) load_b(v, degree, t + step, I, nxt);
+      if (kPrefetch && more) load_b(v, degree, t + step, I, nxt);
       double rz, rr;
       compute_b(v, degree, t, I, cur, W0, W1, gb, rz, rr);
       group_sum2<kThreads>(rz, rr, sred, gb);
@@ -821,7 +814,8 @@ struct BandTile {
         part_rz[t] = rz;
         part_rr[t] = rr;
       }
-      if (more) cur = nxt;
+      if (kPrefetch && more) cur = nxt;
+      if (!kPrefetch && more) load_b(v, degree, t + step, I, cur);
     }
   }
 };

@@ -28,7 +28,7 @@ constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 template <typename T>
 constexpr int kBandRowsOf = 64;    // degrees <= 8
 template <typename T>
-constexpr int kBandRowsHiOf = sizeof(T) == 4 ? 128 : 64;  // degrees 9 .. 16 (FP64: LDS and registers)
+constexpr int kBandRowsHiOf = 128;  // degrees 9 .. 16
 template <typename T>
 constexpr int kBandWavesOf = sizeof(T) == 4 ? 8 : 16;
 template <typename T>
