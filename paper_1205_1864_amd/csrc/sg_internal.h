@@ -21,12 +21,12 @@ constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 // so that the tile plus its Chebyshev halo (degree - 1 nodes, at least one)
 // plus one more node spans at most one wavefront of 64 columns. Tiles are numbered row-major:
 // tile t covers columns (t % ntx) * tsx ... and rows (t / ntx) * rows ...
-// The band height is 64 rows (a taller band recomputes less of the halo); a
-// tile is worked on by 16 waves in FP64 (one tile group per block) and by 8
-// waves in FP32 (two tile groups per block), so that a wave's share of the
-// band fits its registers.
+// Band heights: a taller band recomputes less of the halo. FP64 bands are 128
+// rows high (one 16-wave group per block, no next-tile prefetch, so that a
+// wave's rows fit its registers); FP32 bands are 64 rows up to degree 8 (two
+// 8-wave groups per block, prefetch) and 128 above (one 16-wave group).
 template <typename T>
-constexpr int kBandRowsOf = 64;    // degrees <= 8
+constexpr int kBandRowsOf = sizeof(T) == 4 ? 64 : 128;  // degrees <= 8
 template <typename T>
 constexpr int kBandRowsHiOf = 128;  // degrees 9 .. 16
 template <typename T>
