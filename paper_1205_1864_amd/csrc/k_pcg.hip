@@ -447,8 +447,9 @@ struct BandTile {
   static constexpr int RB = NW * BR;                   // region rows covered by the bands
   static constexpr int kEx = 2 * NW * 2 * 64;          // exchange area: 2 buffers x NW waves x 2 rows
   // the next tile's inputs are loaded during the current one, except where two
-  // copies of them do not fit the registers (FP64 bands taller than 64 rows)
-  static constexpr bool kPrefetch = !(sizeof(T) == 8 && TSY > 64);
+  // copies of them do not fit the registers (FP64 bands taller than 64 rows,
+  // FP32 bands taller than 128)
+  static constexpr bool kPrefetch = TSY <= 64 || (sizeof(T) == 4 && TSY <= 128);
   static_assert(NW * BRA <= RB, "phase A rows exceed the bands");
   static_assert(TSY + 2 * (HMAX + 1) <= RB, "phase B needs the Chebyshev halo plus one row");
   // elements of T per group: the exchange area, then r of the region rows

@@ -24,11 +24,11 @@ constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 // Band heights: a taller band recomputes less of the halo. FP64 bands are 128
 // rows high (one 16-wave group per block, no next-tile prefetch, so that a
 // wave's rows fit its registers); FP32 bands are 64 rows up to degree 8 (two
-// 8-wave groups per block, prefetch) and 128 above (one 16-wave group).
+// 8-wave groups per block, prefetch) and 256 above (one 16-wave group, no prefetch).
 template <typename T>
 constexpr int kBandRowsOf = sizeof(T) == 4 ? 64 : 128;  // degrees <= 8
 template <typename T>
-constexpr int kBandRowsHiOf = 128;  // degrees 9 .. 16
+constexpr int kBandRowsHiOf = sizeof(T) == 4 ? 256 : 128;  // degrees 9 .. 16
 template <typename T>
 constexpr int kBandWavesOf = sizeof(T) == 4 ? 8 : 16;
 template <typename T>
