@@ -98,9 +98,11 @@ typedef struct sg_problem {
  *   inner_maxit       cap on inner PCG iterations per solve (>= 1).
  *   precond           SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC or SG_PC_BGS for sg_solve.
  *   tile              spatial tiles of the inner solver: 32 = banded tiles (up to
- *                     64 columns including the Chebyshev halo, 64 rows; for
- *                     degrees <= 16 in FP64 and <= 8 in FP32), 16 = 16 x 16
- *                     tiles, 0 = automatic.
+ *                     64 columns including the Chebyshev halo; 128 rows in FP64,
+ *                     64 in FP32 up to degree 8 and 256 above; degrees <= 16),
+ *                     16 = 16 x 16 tiles, 0 = automatic (banded tiles, with
+ *                     64-row bands for launches of fewer tiles than twice the
+ *                     compute units; 16 x 16 tiles above degree 16).
  *   warm_start        0: every inner solve starts from zero. 1: the inner
  *                     solves of the up sweep of Algorithm 1 start from the
  *                     down-sweep solution of the same level, and those of the

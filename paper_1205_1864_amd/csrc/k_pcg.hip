@@ -1136,16 +1136,36 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
   if (args.ncols <= 0) return hipSuccess;
   const int H = args.degree - 1;
   if (tile != 16) {
-    // banded tiles, 16 waves per block (one group of 16 waves in FP64, two of
-    // 8 in FP32); the next tile's inputs prefetched in registers
+    // banded tiles, 16 waves per block (one group of 16 waves, or two of 8 for
+    // FP32 up to degree 8), of the band height the host tiled with: the
+    // default of the precision and degree, or 64 rows for small launches
     constexpr int NW = kBandWavesOf<T>;
     constexpr int G = kBandGroupsOf<T>;
     constexpr int TSY = kBandRowsOf<T>;
-    if (H <= 3) return launch_cfg<T, BandTile<T, TSY, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
-    if (H <= 7) return launch_cfg<T, BandTile<T, TSY, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);
     constexpr int TSYH = kBandRowsHiOf<T>;
-    if (H <= 11) return launch_cfg<T, BandTile<T, TSYH, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
-    if (H <= 15) return launch_cfg<T, BandTile<T, TSYH, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+    constexpr int TS = kBandRowsSmall;
+    if (H <= 7) {
+      if (args.rows == TSY) {
+        if (H <= 3) return launch_cfg<T, BandTile<T, TSY, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
+        return launch_cfg<T, BandTile<T, TSY, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);
+      }
+      if constexpr (TS != TSY) {
+        if (args.rows == TS) {
+          if (H <= 3) return launch_cfg<T, BandTile<T, TS, 3, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+          return launch_cfg<T, BandTile<T, TS, 7, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+        }
+      }
+      return hipErrorInvalidValue;
+    }
+    if (H > 15) return hipErrorInvalidValue;
+    if (args.rows == TSYH) {
+      if (H <= 11) return launch_cfg<T, BandTile<T, TSYH, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+      return launch_cfg<T, BandTile<T, TSYH, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+    }
+    if (args.rows == TS) {
+      if (H <= 11) return launch_cfg<T, BandTile<T, TS, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+      return launch_cfg<T, BandTile<T, TS, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+    }
     return hipErrorInvalidValue;
   }
   return launch_cfg<T, SquareTile<T, 16, slots(16, 15)>, 4, RAGGED>(args, cols, max_blocks, s);

@@ -247,6 +247,7 @@ int run_set(sg_batch_ctx* B, int s, int pmin = 0, bool warm = false) {
   sgk::PcgArgs<T> a{};
   a.ncols = ncols;
   a.degree = B->degree;
+  a.rows = sgk::band_rows(B->inner, B->degree);
   a.maxit = B->opts.inner_maxit;
   a.rtol = B->opts.inner_rtol > 0.0 ? B->opts.inner_rtol : 0.0;
   a.warm = warm && B->opts.warm_start && B->tile != 16;

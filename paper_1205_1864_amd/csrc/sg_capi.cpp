@@ -400,7 +400,13 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.Q = (T*)h->pQ;
   a.Z = (T*)h->pZ;
   a.sc = h->pcgsc;
-  sgk::pcg_tiling(h->nx, degree, tile, sgk::band_rows(sizeof(T) == 4 ? 32 : 64, degree), a.ntx, a.ntiles);
+  a.rows = sgk::band_rows(sizeof(T) == 4 ? 32 : 64, degree);
+  sgk::pcg_tiling(h->nx, degree, tile, a.rows, a.ntx, a.ntiles);
+  if (tile != 16 && h->opts.tile == 0 && (long)ncols * a.ntiles < 2L * h->num_cu) {
+    // automatic choice, few tiles for the compute units: shorter bands
+    a.rows = sgk::kBandRowsSmall;
+    sgk::pcg_tiling(h->nx, degree, tile, a.rows, a.ntx, a.ntiles);
+  }
   a.degree = degree;
   a.maxit = h->opts.inner_maxit;
   a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;
@@ -983,7 +989,10 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     sgk::launch_fill(h->pv, 1.0, N, s);
     if (h->opts.inner_precision == 32) sgk::launch_copy_d2f((float*)h->rw, h->pv, N, s);
     else sgk::launch_copy_d2d((double*)h->rw, h->pv, N, s);
-    std::vector<int> tiles = degree <= sgk::band_max_degree(h->opts.inner_precision) ? std::vector<int>{32, 16}
+    // banded candidate: the automatic choice (0, which also shortens the bands of
+    // small launches) unless banded tiles were asked for explicitly
+    const int band = h->opts.tile == 32 ? 32 : 0;
+    std::vector<int> tiles = degree <= sgk::band_max_degree(h->opts.inner_precision) ? std::vector<int>{band, 16}
                                                                                        : std::vector<int>{16};
     std::vector<int> blocks = {0, std::max(1, h->num_cu / 2)};
     double best = 1e300;

@@ -39,6 +39,9 @@ constexpr int kBandGroupsOf = sizeof(T) == 4 ? 2 : 1;
 // share of the taller region fits its registers). Higher degrees take 16 x 16 tiles.
 constexpr int kBandMaxDegree = 16;
 inline int band_max_degree(int) { return kBandMaxDegree; }
+// Band height of launches with few tiles: shorter bands give more tiles, so a
+// launch of a few columns still spreads over the compute units.
+constexpr int kBandRowsSmall = 64;
 inline int band_rows(int inner_precision, int degree) {
   if (inner_precision == 32) return degree > 8 ? kBandRowsHiOf<float> : kBandRowsOf<float>;
   return degree > 8 ? kBandRowsHiOf<double> : kBandRowsOf<double>;
@@ -171,6 +174,7 @@ struct PcgArgs {
   PcgScratch sc;
   int ntx;
   int ntiles;
+  int rows;    // band height of banded tiles (as in the tiling of ntx, ntiles)
   int degree;
   int maxit;
   double rtol;
