@@ -137,8 +137,9 @@ typedef struct sg_stats {
   double ms_precond;          /* time in preconditioner actions */
   double ms_matvec;           /* time in SG matvecs */
   double ms_inner;            /* device time of the inner PCG launches (HIP events on the stream) */
-  double inner_bytes;         /* algorithmic bytes of those launches: per column (10 its + 6) n w
-                                 (3 n w when it stops at once; n w more from a warm start) */
+  double inner_bytes;         /* algorithmic bytes of those launches: per column (9 its + 6) n w
+                                 with banded tiles, (10 its + 6) n w with 16 x 16 tiles (3 n w
+                                 when it stops at once; n w more from a warm start) */
   int64_t inner_launches;     /* number of inner PCG launches */
 } sg_stats;
 
