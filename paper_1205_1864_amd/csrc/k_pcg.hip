@@ -199,7 +199,7 @@ struct IterVecs {
 template <typename T, int TS, int NS>
 struct SquareTile {
   static constexpr int kThreads = kSquareGroup;
-  static constexpr bool kStoresQ = true;  // phase B reads q = K_0 p from memory
+  // phase A stores q = K_0 p and phase B reads it
   static constexpr int NI = (TS * TS + kThreads - 1) / kThreads;  // interior nodes per thread
   // elements of T in one group's LDS buffers (two buffers; phase A needs a 1-node halo)
   static int lds_group(int degree) {
@@ -440,7 +440,7 @@ struct SquareTile {
 template <typename T, int TSY, int HMAX, int NW>
 struct BandTile {
   static constexpr int kThreads = 64 * NW;
-  static constexpr bool kStoresQ = false;  // phase B recomputes q = K_0 p
+  // phase B recomputes q = K_0 p from p instead of reading a stored q
   static constexpr int RYMAX = TSY + 2 * HMAX;
   static constexpr int BR = (RYMAX + NW - 1) / NW;     // region rows per wave (Chebyshev)
   static constexpr int BRA = (TSY + 2 + NW - 1) / NW;  // region rows per wave (phase A, halo 1)

@@ -81,7 +81,7 @@ std::vector<int> level_offsets(int M, int p) {
 
 int batch_tile(const sg_opts& op) {
   if (op.tile == 16) return 16;
-  return op.cheb_degree <= sgk::band_max_degree(op.inner_precision) ? 32 : 16;
+  return op.cheb_degree <= sgk::kBandMaxDegree ? 32 : 16;
 }
 
 // Byte layout of the batch: the problems' own workspaces first, then the

@@ -375,7 +375,7 @@ int choose_tile(const sg_ctx* h, int degree) {
   // banded tiles (code 32) up to the precision's band degree limit; beyond it
   // the halo does not fit one wavefront (or the band its registers), so 16 x 16 tiles
   if (h->opts.tile == 16) return 16;
-  return degree <= sgk::band_max_degree(h->opts.inner_precision) ? 32 : 16;
+  return degree <= sgk::kBandMaxDegree ? 32 : 16;
 }
 
 // Batched inner PCG on `ncols` contiguous columns (inner precision T). warm:
@@ -992,7 +992,7 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     // banded candidate: the automatic choice (0, which also shortens the bands of
     // small launches) unless banded tiles were asked for explicitly
     const int band = h->opts.tile == 32 ? 32 : 0;
-    std::vector<int> tiles = degree <= sgk::band_max_degree(h->opts.inner_precision) ? std::vector<int>{band, 16}
+    std::vector<int> tiles = degree <= sgk::kBandMaxDegree ? std::vector<int>{band, 16}
                                                                                        : std::vector<int>{16};
     std::vector<int> blocks = {0, std::max(1, h->num_cu / 2)};
     double best = 1e300;

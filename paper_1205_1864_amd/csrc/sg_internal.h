@@ -38,7 +38,6 @@ constexpr int kBandGroupsOf = sizeof(T) == 4 ? 2 : 1;
 // Above degree 8 both precisions use one 16-wave group per block (a wave's
 // share of the taller region fits its registers). Higher degrees take 16 x 16 tiles.
 constexpr int kBandMaxDegree = 16;
-inline int band_max_degree(int) { return kBandMaxDegree; }
 // Band height of launches with few tiles: shorter bands give more tiles, so a
 // launch of a few columns still spreads over the compute units.
 constexpr int kBandRowsSmall = 64;
