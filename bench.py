@@ -159,7 +159,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the timed solve and the matvec")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
