@@ -321,3 +321,23 @@ def test_autotune_keeps_parity(kw, prec):
     F = prob.load_block()
     Ux, st = solver.sg_solve(_dev(F), rtol=1e-8, maxit=100)
     assert st["rc"] == 0 and solve.true_relres(s, F.T, Ux.cpu().numpy().T) <= 1.05e-8
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_solve_scale_benchmark_configuration(prec):
+    """256^2, M = 10, p = 3, Hermite chaos, in the benchmark's launch configuration
+    (Chebyshev degree 16, autotuned schedules): the solve reaches 1e-8 and its true
+    residual on the oracle's operator agrees."""
+    b = _b()
+    prob = named_problem("scale")
+    print(f"benchmark configuration solve 256^2 inner FP{prec}", flush=True)
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=16, precond="hsc", inner_rtol=1e-4,
+                                        inner_maxit=2000))
+    solver.sg_autotune(3)
+    F = prob.load_block()
+    U, st = solver.sg_solve(_dev(F), rtol=1e-8, maxit=100)
+    assert st["rc"] == 0 and st["true_relres"] <= 1.05e-8
+    s = sg.build_system(prob)
+    tr = solve.true_relres(s, F.T, U.cpu().numpy().T)
+    assert tr <= 1.05e-8
+    assert abs(st["true_relres"] - tr) <= 1e-3 * tr
