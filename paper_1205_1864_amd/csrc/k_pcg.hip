@@ -447,9 +447,8 @@ struct BandTile {
   static constexpr int RB = NW * BR;                   // region rows covered by the bands
   static constexpr int kEx = 2 * NW * 2 * 64;          // exchange area: 2 buffers x NW waves x 2 rows
   // the next tile's inputs are loaded during the current one, except where two
-  // copies of them do not fit the registers (FP64 bands taller than 64 rows,
-  // FP32 bands taller than 128)
-  static constexpr bool kPrefetch = TSY <= 64 || (sizeof(T) == 4 && TSY <= 128);
+  // copies of them do not fit the registers (bands taller than 64 rows)
+  static constexpr bool kPrefetch = TSY <= 64;
   static_assert(NW * BRA <= RB, "phase A rows exceed the bands");
   static_assert(TSY + 2 * (HMAX + 1) <= RB, "phase B needs the Chebyshev halo plus one row");
   // elements of T per group: the exchange area, then r of the region rows
@@ -1136,33 +1135,20 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
   if (args.ncols <= 0) return hipSuccess;
   const int H = args.degree - 1;
   if (tile != 16) {
-    // banded tiles, 16 waves per block (one group of 16 waves, or two of 8 for
-    // FP32 up to degree 8), of the band height the host tiled with: the
-    // default of the precision and degree, or 64 rows for small launches
-    constexpr int NW = kBandWavesOf<T>;
-    constexpr int G = kBandGroupsOf<T>;
+    // banded tiles, one group of 16 waves per block, of the band height the
+    // host tiled with: the precision's default or, for small launches, 64 rows
     constexpr int TSY = kBandRowsOf<T>;
-    constexpr int TSYH = kBandRowsHiOf<T>;
     constexpr int TS = kBandRowsSmall;
-    if (H <= 7) {
-      if (args.rows == TSY) {
-        if (H <= 3) return launch_cfg<T, BandTile<T, TSY, 3, NW>, G, RAGGED>(args, cols, max_blocks, s);
-        return launch_cfg<T, BandTile<T, TSY, 7, NW>, G, RAGGED>(args, cols, max_blocks, s);
-      }
-      if constexpr (TS != TSY) {
-        if (args.rows == TS) {
-          if (H <= 3) return launch_cfg<T, BandTile<T, TS, 3, 16>, 1, RAGGED>(args, cols, max_blocks, s);
-          return launch_cfg<T, BandTile<T, TS, 7, 16>, 1, RAGGED>(args, cols, max_blocks, s);
-        }
-      }
-      return hipErrorInvalidValue;
-    }
     if (H > 15) return hipErrorInvalidValue;
-    if (args.rows == TSYH) {
-      if (H <= 11) return launch_cfg<T, BandTile<T, TSYH, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
-      return launch_cfg<T, BandTile<T, TSYH, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+    if (args.rows == TSY) {
+      if (H <= 3) return launch_cfg<T, BandTile<T, TSY, 3, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+      if (H <= 7) return launch_cfg<T, BandTile<T, TSY, 7, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+      if (H <= 11) return launch_cfg<T, BandTile<T, TSY, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+      return launch_cfg<T, BandTile<T, TSY, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
     }
     if (args.rows == TS) {
+      if (H <= 3) return launch_cfg<T, BandTile<T, TS, 3, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+      if (H <= 7) return launch_cfg<T, BandTile<T, TS, 7, 16>, 1, RAGGED>(args, cols, max_blocks, s);
       if (H <= 11) return launch_cfg<T, BandTile<T, TS, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
       return launch_cfg<T, BandTile<T, TS, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
     }

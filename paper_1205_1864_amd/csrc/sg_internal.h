@@ -21,29 +21,22 @@ constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 // so that the tile plus its Chebyshev halo (degree - 1 nodes, at least one)
 // plus one more node spans at most one wavefront of 64 columns. Tiles are numbered row-major:
 // tile t covers columns (t % ntx) * tsx ... and rows (t / ntx) * rows ...
-// Band heights: a taller band recomputes less of the halo. FP64 bands are 128
-// rows high (one 16-wave group per block, no next-tile prefetch, so that a
-// wave's rows fit its registers); FP32 bands are 64 rows up to degree 8 (two
-// 8-wave groups per block, prefetch) and 256 above (one 16-wave group, no prefetch).
+// Band heights: a taller band recomputes less of the halo. Bands are 128 rows
+// high in FP64 and 256 in FP32 (one band row at 256^2), worked by one group of
+// 16 waves per block without the next-tile prefetch, so that a wave's rows fit
+// its registers; launches with few tiles use 64-row bands (kBandRowsSmall,
+// with the prefetch).
 template <typename T>
-constexpr int kBandRowsOf = sizeof(T) == 4 ? 64 : 128;  // degrees <= 8
-template <typename T>
-constexpr int kBandRowsHiOf = sizeof(T) == 4 ? 256 : 128;  // degrees 9 .. 16
-template <typename T>
-constexpr int kBandWavesOf = sizeof(T) == 4 ? 8 : 16;
-template <typename T>
-constexpr int kBandGroupsOf = sizeof(T) == 4 ? 2 : 1;
+constexpr int kBandRowsOf = sizeof(T) == 4 ? 256 : 128;
 // Highest Chebyshev degree served by banded tiles: the halo (degree - 1) plus
 // one node on each side leaves 32 interior columns of 64 lanes at degree 16.
-// Above degree 8 both precisions use one 16-wave group per block (a wave's
-// share of the taller region fits its registers). Higher degrees take 16 x 16 tiles.
+// Higher degrees take 16 x 16 tiles.
 constexpr int kBandMaxDegree = 16;
 // Band height of launches with few tiles: shorter bands give more tiles, so a
 // launch of a few columns still spreads over the compute units.
 constexpr int kBandRowsSmall = 64;
-inline int band_rows(int inner_precision, int degree) {
-  if (inner_precision == 32) return degree > 8 ? kBandRowsHiOf<float> : kBandRowsOf<float>;
-  return degree > 8 ? kBandRowsHiOf<double> : kBandRowsOf<double>;
+inline int band_rows(int inner_precision, int) {
+  return inner_precision == 32 ? kBandRowsOf<float> : kBandRowsOf<double>;
 }
 inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& ntiles) {
   if (tile == 16) {
