@@ -99,7 +99,7 @@ typedef struct sg_problem {
  *   precond           SG_PC_NONE, SG_PC_MEAN, SG_PC_HSC or SG_PC_BGS for sg_solve.
  *   tile              spatial tiles of the inner solver: 32 = banded tiles (up to
  *                     64 columns including the Chebyshev halo; 128 rows in FP64,
- *                     64 in FP32 up to degree 8 and 256 above; degrees <= 16),
+ *                     256 in FP32; degrees <= 16),
  *                     16 = 16 x 16 tiles, 0 = automatic (banded tiles, with
  *                     64-row bands for launches of fewer tiles than twice the
  *                     compute units; 16 x 16 tiles above degree 16).
