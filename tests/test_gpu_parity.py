@@ -86,8 +86,7 @@ def test_inner_solve_band_geometry(prec, tol, n_e, degree):
     the halo (n_e = 4); a tile plus its halo and the extra node exactly one
     wavefront wide (nx = 64 - 2d: n_e = 49 at degree 8, 33 at degree 16) and
     one column more (n_e = 50, 34); several ragged tiles in both directions
-    (n_e = 130); every halo capacity (degree <= 4, 8, 12, 16; FP32 above 8
-    takes the 16 x 16 tiles)."""
+    (n_e = 130); every halo capacity (degree <= 4, 8, 12, 16)."""
     b = _b()
     prob, s = _sys(n_e=n_e, M=2, p=1)
     print(f"inner band prec={prec} n_e={n_e} degree={degree}", flush=True)
@@ -99,6 +98,30 @@ def test_inner_solve_band_geometry(prec, tol, n_e, degree):
     prec_o = krylov.make_chebyshev(s.K[0], prob.n_e, prob.theta0, degree)
     st = krylov.InnerStats()
     Xo = krylov.pcg_columns(s.K[0], B.T, prec_o, 0.0, 7, st).T
+    assert list(its) == list(st.iterations)
+    for c in range(3):
+        assert np.linalg.norm(X[c] - Xo[c]) <= tol * np.linalg.norm(Xo[c])
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-11), (32, 2e-5)])
+@pytest.mark.parametrize("degree", [2, 8, 16])
+@pytest.mark.parametrize("tile", [0, 32])
+def test_inner_solve_tall_grid(prec, tol, degree, tile):
+    """Several bands in y at every band height: 299 unknown rows take three
+    128-row bands (FP64) or two 256-row bands (FP32), the last one ragged, with
+    tile = 32; with tile = 0 the three-column launch is small enough for the
+    64-row bands (five per tile column) that load the next tile ahead."""
+    b = _b()
+    prob, s = _sys(n_e=300, M=2, p=1)
+    print(f"inner tall prec={prec} degree={degree} tile={tile}", flush=True)
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=degree, inner_maxit=6,
+                                        inner_rtol=0.0, tile=tile))
+    B = random_block(3, prob.n, seed=300 + degree)
+    X, its = solver.sg_inner_solve(_dev(B))
+    X = X.cpu().numpy()
+    prec_o = krylov.make_chebyshev(s.K[0], prob.n_e, prob.theta0, degree)
+    st = krylov.InnerStats()
+    Xo = krylov.pcg_columns(s.K[0], B.T, prec_o, 0.0, 6, st).T
     assert list(its) == list(st.iterations)
     for c in range(3):
         assert np.linalg.norm(X[c] - Xo[c]) <= tol * np.linalg.norm(Xo[c])
