@@ -184,9 +184,9 @@ int sg_apply_bgs(sg_handle h, const double* R, double* Z);
 
 /* Inner solves on the diagonal blocks (Section 5): for columns c = 0..ncols-1,
  * PCG on K_0 x_c = b_c with the Jacobi-scaled Chebyshev preconditioner, in
- * the handle's inner precision (FP64 data in and out). B and X are
- * n x ncols device blocks (ld = n). iters[ncols] (host, may be NULL)
- * receives the iteration count of each column. */
+ * the handle's inner precision (FP64 data in and out). B and X are distinct
+ * n x ncols device blocks (ld = n), 0 <= ncols <= P. iters[ncols] (host, may
+ * be NULL) receives the iteration count of each column. */
 int sg_inner_solve(sg_handle h, const double* B, double* X, int32_t ncols, int32_t* iters);
 
 /* Coupling products of Algorithm 1 on level l (1 <= l <= p), FP64:
@@ -228,8 +228,8 @@ int sg_qoi(sg_handle h, const double* U, const double* w_mean, const double* w_v
  * of A U = F: solves the adjoint system A Lambda = dQ/dU with the same
  * preconditioned FCG (A is symmetric) to rtol, then contracts
  * dQ/dtheta_i = -<Lambda, (dA/dtheta_i) U>. Q (host) and grad[1+M] (host)
- * receive the results; Lambda (device n x P, may be NULL) receives the
- * adjoint solution. */
+ * receive the results; Lambda (device n x P, may be NULL, distinct from U)
+ * receives the adjoint solution. rtol >= 0 and maxit >= 0 as for sg_solve. */
 int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const double* w_var,
                     double rtol, int32_t maxit, double* Q, double* grad, double* Lambda,
                     sg_stats* stats);

@@ -1363,6 +1363,7 @@ int sg_apply_mean(sg_handle h, const double* R, double* Z) {
 
 int sg_inner_solve(sg_handle h, const double* B, double* X, int32_t ncols, int32_t* iters) {
   if (!h || !B || !X) return fail(SG_EINVAL, "null argument");
+  if ((const double*)X == B) return fail(SG_EINVAL, "B and X must be distinct");
   if (ncols < 0 || ncols > h->P) return fail(SG_EINVAL, "ncols must be in 0..P");
   if (ncols == 0) return SG_OK;
   std::vector<int> it;
@@ -1426,11 +1427,12 @@ int sg_qoi(sg_handle h, const double* U, const double* w_mean, const double* w_v
 int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const double* w_var, double rtol,
                     int32_t maxit, double* Q, double* grad, double* Lambda, sg_stats* stats) {
   if (!h || !U || !w_mean || !w_var || !Q || !grad) return fail(SG_EINVAL, "null argument");
+  if ((const double*)Lambda == U) return fail(SG_EINVAL, "Lambda must differ from U");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(SG_EINVAL, "rtol must be >= 0 and maxit >= 0");
   int rc = sg_qoi(h, U, w_mean, w_var, Q);
   if (rc) return rc;
   sgk::launch_qoi_grad(U, w_mean, w_var, h->n, h->P, h->rhs, h->stream);
   double* lam = Lambda ? Lambda : h->lam;
-  if (lam == U) return fail(SG_EINVAL, "Lambda must differ from U");
   const int status = fcg(h, h->rhs, lam, rtol, maxit, 0, h->opts.precond, stats);
   if (status < 0) return status;
   sgk::ContractArgs c{};

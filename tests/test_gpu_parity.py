@@ -311,6 +311,30 @@ def test_solve_edge_cases():
         solver.sg_solve(_dev(Fn))
 
 
+def test_argument_errors():
+    """Aliased or out-of-range arguments are rejected before any work is enqueued."""
+    from sg_inputs import qoi_weights
+    b = _b()
+    prob, s = _sys(n_e=12, M=2, p=2)
+    solver = b.SGSolver(prob)
+    Bd = _dev(random_block(2, prob.n, seed=5))
+    with pytest.raises(b.SGError, match="distinct"):
+        solver.sg_inner_solve(Bd, X=Bd)
+    F = _dev(prob.load_block())
+    with pytest.raises(b.SGError, match="distinct"):
+        solver.sg_solve(F, U=F)
+    U, st = solver.sg_solve(F, rtol=1e-10)
+    wm, wv = (_b().to_device_vec(w) for w in qoi_weights(prob.n_e))
+    with pytest.raises(b.SGError, match="Lambda"):
+        solver.sg_adjoint_grad(U, wm, wv, Lambda=U)
+    with pytest.raises(b.SGError, match="rtol"):
+        solver.sg_adjoint_grad(U, wm, wv, rtol=-1.0)
+    with pytest.raises(b.SGError, match="ncols"):
+        solver.sg_inner_solve(_dev(random_block(prob.P + 1, prob.n, seed=6)))
+    Q, g, st = solver.sg_adjoint_grad(U, wm, wv, rtol=1e-10)
+    assert st["rc"] == 0 and np.all(np.isfinite(g))
+
+
 def test_adjoint_parity_small():
     from oracle import adjoint
     from sg_inputs import qoi_weights
