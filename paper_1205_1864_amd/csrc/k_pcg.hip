@@ -697,10 +697,11 @@ struct BandTile {
       const bool more = t + step < t_end;
       if (kPrefetch && more) load_a(v, t + step, I, nxt);
       double pq = compute_a(v, t, I, cur, W0, gb), unused = 0.0;
+      // without the prefetch the next tile's loads still overlap the reduction
+      if (!kPrefetch && more) load_a(v, t + step, I, cur);
       group_sum2<kThreads>(pq, unused, sred, gb);
       if ((threadIdx.x % kThreads) == 0) part[t] = pq;
       if (kPrefetch && more) cur = nxt;
-      if (!kPrefetch && more) load_a(v, t + step, I, cur);
     }
   }
 
@@ -809,13 +810,13 @@ struct BandTile {
       if (kPrefetch && more) load_b(v, degree, t + step, I, nxt);
       double rz, rr;
       compute_b(v, degree, t, I, cur, W0, W1, gb, rz, rr);
+      if (!kPrefetch && more) load_b(v, degree, t + step, I, cur);
       group_sum2<kThreads>(rz, rr, sred, gb);
       if ((threadIdx.x % kThreads) == 0) {
         part_rz[t] = rz;
         part_rr[t] = rr;
       }
       if (kPrefetch && more) cur = nxt;
-      if (!kPrefetch && more) load_b(v, degree, t + step, I, cur);
     }
   }
 };
