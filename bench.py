@@ -38,7 +38,7 @@ CHEB_DEGREE = 16  # updates of the Chebyshev preconditioner of the inner PCG (fa
 # runs of this benchmark, scaled by the same counters of a 512 MiB elementwise
 # kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Set to None when the
 # kernel changes.
-PCG_TRAFFIC_BYTES = 15.32e9     # pcg_kernel<double, BandTile<double, 128 | 64, 15, 16>, 1>, average over a solve's launches
+PCG_TRAFFIC_BYTES = 15.41e9     # pcg_kernel<double, BandTile<double, 128 | 64, 15, 16>, 1>, average over a solve's launches
 MATVEC_TRAFFIC_BYTES = {(2, 2): 570.4e6, (2, 1): 543.0e6}  # sgop_march_kernel<double, 10>, one SG matvec, by schedule
 
 
