@@ -247,6 +247,11 @@ def main():
             extra[f"n_blocksolve_{label}"] = sv_st["n_blocksolve"]
             extra[f"true_relres_{label}"] = sv_st["true_relres"]
             extra[f"rel_diff_vs_fp64_hsc_{label}"] = float(torch.linalg.norm(Uv - U64) / torch.linalg.norm(U64))
+            # algorithmic inner-PCG bandwidth of this variant (library byte count over its HIP-event time)
+            if sv_st["ms_inner"] > 0:
+                gbs = sv_st["inner_bytes"] / (sv_st["ms_inner"] * 1e-3) / 1e9
+                extra[f"pcg_GBs_{label}"] = gbs
+                extra[f"pcg_frac_{label}"] = gbs / HBM_PEAK_GBS
             if label == "hsc_fp32":
                 # FP32-inner error of one preconditioner action against the FP64 one
                 Rr = to_device_block(random_block(prob.P, prob.n, seed=5))

@@ -101,8 +101,8 @@ typedef struct sg_problem {
  *                     64 columns including the Chebyshev halo; 128 rows in FP64,
  *                     256 in FP32; degrees <= 16),
  *                     16 = 16 x 16 tiles, 0 = automatic (banded tiles, with
- *                     64-row bands for launches of fewer tiles than twice the
- *                     compute units; 16 x 16 tiles above degree 16).
+ *                     64-row bands for launches of fewer tiles than compute
+ *                     units; 16 x 16 tiles above degree 16).
  *   warm_start        0: every inner solve starts from zero. 1: the inner
  *                     solves of the up sweep of Algorithm 1 start from the
  *                     down-sweep solution of the same level, and those of the

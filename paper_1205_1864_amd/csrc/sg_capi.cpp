@@ -402,8 +402,8 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.sc = h->pcgsc;
   a.rows = sgk::band_rows(sizeof(T) == 4 ? 32 : 64, degree);
   sgk::pcg_tiling(h->nx, degree, tile, a.rows, a.ntx, a.ntiles);
-  if (tile != 16 && h->opts.tile == 0 && (long)ncols * a.ntiles < 2L * h->num_cu) {
-    // automatic choice, few tiles for the compute units: shorter bands
+  if (tile != 16 && h->opts.tile == 0 && (long)ncols * a.ntiles < h->num_cu) {
+    // automatic choice, fewer tiles than compute units: shorter bands
     a.rows = sgk::kBandRowsSmall;
     sgk::pcg_tiling(h->nx, degree, tile, a.rows, a.ntx, a.ntiles);
   }
