@@ -21,6 +21,13 @@ krylov   Flexible CG (Section 5), inner PCG with a Jacobi-scaled Chebyshev
 hsc      Algorithm 1 (hierarchical Schur complement preconditioner) and the
          mean-based preconditioner (Section 6).
 adjoint  Quantity of interest, adjoint gradient and finite differences.
+bgs      Block symmetric Gauss-Seidel preconditioner (Section 6).
+schur    A-priori reduction to the Schur complement of the top degree
+         (Section 5).
+lognormal
+         Lognormal coefficient expanded in Hermite chaos to twice the
+         solution's degree, with the full-level-block preconditioners
+         (Section 7, Tables 6-9). The GPU library does not implement it.
 
 Every function cites the passage it follows. Readings of points where the
 paper is silent are stated where they are used.

@@ -38,23 +38,37 @@ def _row_products(sys: SGSystem, a: int, X: np.ndarray, cols) -> tuple:
     return out, int(np.count_nonzero(used))
 
 
-def bgs_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = None) -> np.ndarray:
-    """One action of M_bGS on a residual block R of shape (n, P)."""
+def bgs_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = None, row_products=None,
+              solve_block=None) -> np.ndarray:
+    """One action of M_bGS on a residual block R of shape (n, P).
+
+    ``row_products(a, X, cols)`` (default: from the K_k and G_k) and
+    ``solve_block(a, v)`` (default: ``solve_mean``, for A_aa = K_0) serve
+    systems whose diagonal blocks are not K_0 (the lognormal coefficient of
+    Section 7).
+    """
+    rowp = row_products if row_products is not None else (lambda a, X, cols: _row_products(sys, a, X, cols))
+
+    def bsolve(a, v):
+        if solve_block is not None:
+            return solve_block(a, v)
+        return solve_mean(v[:, None])[:, 0]
+
     P = sys.P
     cnt = counters if counters is not None else Counters()
     R = np.asarray(R, dtype=np.float64)
     xf = np.zeros_like(R)
     for a in range(P):
-        lower, m = _row_products(sys, a, xf, list(range(a)))
+        lower, m = rowp(a, xf, list(range(a)))
         cnt.block_matvecs += m
-        xf[:, a] = solve_mean((R[:, a] - lower)[:, None])[:, 0]
+        xf[:, a] = bsolve(a, R[:, a] - lower)
         cnt.block_solves += 1
     x = np.zeros_like(R)
     for a in range(P - 1, -1, -1):
-        lower, m1 = _row_products(sys, a, xf, list(range(a)))
-        upper, m2 = _row_products(sys, a, x, list(range(a + 1, P)))
+        lower, m1 = rowp(a, xf, list(range(a)))
+        upper, m2 = rowp(a, x, list(range(a + 1, P)))
         cnt.block_matvecs += m1 + m2
-        x[:, a] = solve_mean((R[:, a] - lower - upper)[:, None])[:, 0]
+        x[:, a] = bsolve(a, R[:, a] - lower - upper)
         cnt.block_solves += 1
     return x
 

@@ -83,7 +83,7 @@ class PCGMeanSolver:
 
 
 def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = None, ptop: int = None,
-              warm: bool = False) -> np.ndarray:
+              warm: bool = False, blocks=None, solve_level=None) -> np.ndarray:
     """One action of M_P (Algorithm 1) on a residual block R of shape (n, P).
 
     ``solve_mean(V, X0=None)`` applies the inverse of the K_0 diagonal blocks
@@ -92,8 +92,19 @@ def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = Non
     ``off[ptop + 1]`` columns of degree <= ptop (the preconditioner M_{P-1}
     of the reduced system of Section 5). ``warm``: each solve of the up sweep
     starts from the down-sweep solution y_l of its level (the algorithm fixes
-    what is solved, not the inner solver's initial guess).
+    what is solved, not the inner solver's initial guess). ``blocks(rows,
+    cols)`` (default: ``level_block``) gives the sub-block operators B_l, C_l,
+    and ``solve_level(l, V)`` (default: ``solve_mean(V)``) applies D_l^-1, for
+    systems whose D_l are not block diagonal (the lognormal coefficient of
+    Section 7).
     """
+    blk = blocks if blocks is not None else (lambda rows, cols: level_block(sys, rows, cols))
+
+    def dsolve(l, V, X0=None):
+        if solve_level is not None:
+            return solve_level(l, V)
+        return solve_mean(V, X0) if X0 is not None else solve_mean(V)
+
     off = sys.off
     p = sys.p if ptop is None else ptop
     r = np.array(R, dtype=np.float64, copy=True)
@@ -103,21 +114,21 @@ def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = Non
     # Down sweep: pre-corrections on levels p..1.
     for l in range(p, 0, -1):
         lo, hi = int(off[l]), int(off[l + 1])
-        y = ys[l] = solve_mean(r[:, lo:hi])
+        y = ys[l] = dsolve(l, r[:, lo:hi])
         cnt.block_solves += hi - lo
-        B_l = level_block(sys, slice(0, lo), slice(lo, hi))
+        B_l = blk(slice(0, lo), slice(lo, hi))
         r[:, :lo] -= B_l(y)
         cnt.block_matvecs += count_blocks(sys, slice(0, lo), slice(lo, hi))
     # Mean-value problem A_0 u_0 = g_0.
-    u[:, 0:1] = solve_mean(r[:, 0:1])
+    u[:, 0:1] = dsolve(0, r[:, 0:1])
     cnt.block_solves += 1
     # Up sweep: post-corrections on levels 1..p.
     for l in range(1, p + 1):
         lo, hi = int(off[l]), int(off[l + 1])
-        C_l = level_block(sys, slice(lo, hi), slice(0, lo))
+        C_l = blk(slice(lo, hi), slice(0, lo))
         w = r[:, lo:hi] - C_l(u[:, :lo])
         cnt.block_matvecs += count_blocks(sys, slice(lo, hi), slice(0, lo))
-        u[:, lo:hi] = solve_mean(w, ys[l]) if warm else solve_mean(w)
+        u[:, lo:hi] = dsolve(l, w, ys[l]) if warm else dsolve(l, w)
         cnt.block_solves += hi - lo
     return u
 

@@ -1,0 +1,172 @@
+"""Pins of the oracle's lognormal-coefficient system (Section 7, Tables 6-9).
+
+Closed forms against library quadrature, the fast assembly against the
+Kronecker definition and against tensor quadrature of the expanded
+coefficient, the preconditioners against their dense definitions, and the
+paper's own iteration counts and condition estimates.
+"""
+
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from numpy.polynomial import hermite_e
+
+from oracle import chaos, fe, hsc, krylov, lognormal, sg
+from oracle.bgs import bgs_dense
+from sg_inputs import named_problem
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "lognormal_tables.txt")
+
+
+def _gauss(nq):
+    x, w = hermite_e.hermegauss(nq)
+    return x, w / w.sum()
+
+
+def _psi(a, x):
+    c = np.zeros(a + 1)
+    c[a] = 1.0
+    return hermite_e.hermeval(x, c) / math.sqrt(math.factorial(a))
+
+
+def test_hermite_triple_products_by_quadrature():
+    x, w = _gauss(20)
+    for a, b, c in itertools.product(range(7), repeat=3):
+        q = float(np.sum(w * _psi(a, x) * _psi(b, x) * _psi(c, x)))
+        assert abs(lognormal.hermite_triple(a, b, c) - q) <= 1e-11 * max(1.0, abs(q)), (a, b, c)
+
+
+def test_gpc_coefficients_by_quadrature():
+    """k_i = E[exp(mu + g . xi) psi_i(xi)] on a tensor Gauss-Hermite grid, M = 2."""
+    rng = np.random.default_rng(7)
+    mu = rng.normal(size=3) * 0.3
+    g = rng.normal(size=(2, 3)) * 0.6
+    idx = chaos.multi_indices(2, 6)
+    k = lognormal.gpc_coefficients(mu, g, idx)
+    x, w = _gauss(40)
+    for j, (i1, i2) in enumerate(idx):
+        f = np.exp(mu[:, None, None] + g[0][:, None, None] * x[None, :, None] + g[1][:, None, None] * x[None, None, :])
+        q = np.einsum("a,b,eab->e", w * _psi(i1, x), w * _psi(i2, x), f)
+        assert np.allclose(k[j], q, rtol=1e-11, atol=1e-14), (i1, i2)
+
+
+def _small(M=2, p=1, n_e=3, cov=0.8):
+    prob = named_problem("paper_legendre", n_e=n_e, M=M, p=p)
+    return prob, lognormal.build(prob, cov)
+
+
+def test_assembly_matches_kronecker_definition():
+    _, ls = _small(M=2, p=2, n_e=4)
+    A_kron = sg.assemble(ls.sys)
+    assert abs(ls.A - A_kron).max() <= 1e-13 * abs(A_kron).max()
+    assert abs(ls.A - ls.A.T).max() <= 1e-13 * abs(ls.A).max()
+
+
+def test_assembly_by_tensor_quadrature():
+    """A = E[psi psi^T (x) K(k_2p(xi))] with k_2p the expanded coefficient; the
+    integrand is a polynomial of degree 4p per variable, so the rule is exact."""
+    prob, ls = _small(M=2, p=1, n_e=3)
+    alpha = chaos.multi_indices(2, 1)
+    x, w = _gauss(4)
+    A = np.zeros(ls.A.shape)
+    for q1, q2 in itertools.product(range(len(x)), repeat=2):
+        xi = (x[q1], x[q2])
+        wq = w[q1] * w[q2]
+        psi = np.array([_psi(a[0], xi[0]) * _psi(a[1], xi[1]) for a in alpha])
+        kx = sum(ls.coef[j] * _psi(i[0], xi[0]) * _psi(i[1], xi[1]) for j, i in enumerate(ls.coef_idx))
+        A += wq * np.kron(np.outer(psi, psi), fe.assemble_stiffness(kx, prob.n_e).toarray())
+    assert np.max(np.abs(ls.A.toarray() - A)) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_hsc_degree_one_equals_block_formula():
+    """p = 1 with exact D_1: Algorithm 1 is the block factorisation with the
+    Schur complement replaced by A_0 (eq. (block-inverse))."""
+    prob, ls = _small(M=3, p=1, n_e=4)
+    pcs = lognormal.LognormalPreconditioners(ls)
+    n, P = ls.sys.n, ls.sys.P
+    Md = hsc.hsc_dense_p1(ls.A.toarray(), n, P)
+    R = np.random.default_rng(3).normal(size=(n, P))
+    Z = pcs.hsc(R)
+    assert np.allclose(sg.vec(Z), Md @ sg.vec(R), rtol=1e-10, atol=1e-12)
+
+
+def test_bgs_equals_splitting_formula():
+    prob, ls = _small(M=2, p=2, n_e=4)
+    pcs = lognormal.LognormalPreconditioners(ls)
+    n, P = ls.sys.n, ls.sys.P
+    Md = bgs_dense(ls.A.toarray(), n, P)
+    R = np.random.default_rng(4).normal(size=(n, P))
+    assert np.allclose(sg.vec(pcs.bgs(R)), Md @ sg.vec(R), rtol=1e-10, atol=1e-12)
+
+
+def test_vanishing_variance_reduces_to_the_mean_problem():
+    """CoV -> 0: A -> I (x) K(mean), so the mean-based preconditioner is exact
+    and the mean block solves the deterministic problem."""
+    prob, ls = _small(M=2, p=2, n_e=6, cov=1e-7)
+    F = prob.load_block().T.copy()
+    res, _ = lognormal.solve_fcg(ls, F, "mean", rtol=1e-8)
+    assert res.converged and res.iterations <= 2
+    u_det = np.linalg.solve(fe.laplacian(prob.n_e).toarray(), F[:, 0])
+    assert np.linalg.norm(res.x[:, 0] - u_det) <= 1e-6 * np.linalg.norm(u_det)
+    assert np.linalg.norm(res.x[:, 1:]) <= 1e-5 * np.linalg.norm(u_det)
+
+
+def _golden_rows():
+    rows = []
+    with open(GOLDEN) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            rows.append((int(t[0]), t[1], float(t[2]), [(int(t[3]), float(t[4])), (int(t[5]), float(t[6])),
+                                                        (int(t[7]), float(t[8]))]))
+    return rows
+
+
+def _run(key, val):
+    kw, cov = dict(M=4, p=4, n_e=10), 1.0
+    if key == "N":
+        kw["M"] = int(val)
+    elif key == "P":
+        kw["p"] = int(val)
+    elif key == "CoV":
+        cov = val / 100.0
+    elif key == "h":
+        kw["n_e"] = int(val)
+    prob = named_problem("paper_legendre", **kw)
+    ls = lognormal.build(prob, cov)
+    pcs = lognormal.LognormalPreconditioners(ls)
+    F = prob.load_block().T.copy()
+    out = {}
+    for pc in ("mean", "bgs", "hsc"):
+        res, _ = lognormal.solve_fcg(ls, F, pc, rtol=1e-8, maxit=500, pcs=pcs)
+        assert res.converged
+        out[pc] = (res.iterations, krylov.lanczos_kappa(res.alphas, res.betas))
+    return out
+
+
+@pytest.mark.parametrize("row", _golden_rows(), ids=lambda r: f"T{r[0]}-{r[1]}{r[2]:g}")
+def test_paper_tables_6_to_9(row):
+    """Against Tables 6-9. The KL data come from a Nystrom method and the
+    Dirichlet nodes are eliminated (the paper counts 11 x 11 nodes on the
+    10 x 10 mesh), so the comparison has tolerances, fixed from the rows:
+    M_HS within 2 iterations and 20 % in the condition estimate (up to CoV
+    125 %); M_bGS within 3 iterations; the mean-based condition estimate
+    within 12 % on the 10 x 10 mesh (its iteration counts run 5-25 % below the
+    paper's). In every row, as the paper concludes, the condition estimates
+    order M_HS <= M_bGS <= M_m."""
+    _, key, val, ref = row
+    got = _run(key, val)
+    (m_it, m_k), (b_it, b_k), (h_it, h_k) = ref
+    assert got["hsc"][1] <= got["bgs"][1] <= got["mean"][1]
+    assert got["hsc"][0] <= got["mean"][0] and got["bgs"][0] <= got["mean"][0]
+    if key == "CoV" and val > 125:
+        return
+    assert abs(got["hsc"][0] - h_it) <= 2, (got, ref)
+    assert abs(got["hsc"][1] - h_k) <= 0.20 * h_k, (got, ref)
+    assert abs(got["bgs"][0] - b_it) <= 3, (got, ref)
+    if key != "h":
+        assert abs(got["mean"][1] - m_k) <= 0.12 * m_k, (got, ref)
