@@ -303,6 +303,38 @@ int sg_batch_solve(sg_batch b, const double* const* F, double* const* U, double 
 void sg_batch_destroy(sg_batch b);
 
 /* Thread-local description of the last failure (never NULL). */
+/* Lognormal coefficient (Section 7, second set of experiments; Tables 6-9).
+ * The coefficient is k(x, xi) = exp(g(x, xi)) with the Gaussian field
+ * g = mu_g + sum_k g_k(x) xi_k, g_k(e) = sigma_g s[k] phi[k][e], expanded in
+ * the normalised Hermite chaos to total degree 2p; the solution has degree p.
+ * The fields of sg_problem mean here: theta0 > 0 the mean of k, sigma >= 0 its
+ * coefficient of variation, s and phi the KL data of the Gaussian field;
+ * family must be SG_FAMILY_HERMITE; 3 <= n_e <= 4096, M <= 16, p <= 8,
+ * P^2 <= 2^22. sigma_g^2 = ln(1 + sigma^2) and mu_g = ln(theta0) - sigma_g^2/2
+ * give k that mean and CoV. The global matrix A = sum_i G_i (x) K_i with
+ * (G_i)_ab = E[psi_i psi_a psi_b] couples every pair of chaos blocks that
+ * some term reaches (block dense); the library stores each such block's
+ * element coefficient field c_ab = sum_i (G_i)_ab k_i (nblocks x n_e^2 FP64 in
+ * the workspace, computed at setup).
+ *   sg_logn_workspace_bytes  device bytes the handle needs;
+ *   sg_logn_setup            tables and block fields into `workspace` (device,
+ *                            256-byte aligned, caller-owned, at least the
+ *                            queried size), work on `stream`; synchronises it;
+ *   sg_logn_sizes            n, P and the number of stored blocks (host outputs,
+ *                            each may be NULL);
+ *   sg_logn_matvec           Y = A U for distinct n x P FP64 device blocks in the
+ *                            layout of sg_matvec (asynchronous on the stream);
+ *   sg_logn_destroy          frees the host handle (not the workspace).
+ * Only the operator is provided: the preconditioners of Section 6 for this
+ * case (full level blocks D_l) are not. */
+typedef struct sg_logn_ctx* sg_logn_handle;
+int sg_logn_workspace_bytes(const sg_problem* prob, size_t* bytes);
+int sg_logn_setup(const sg_problem* prob, void* workspace, size_t workspace_bytes, void* stream,
+                  sg_logn_handle* out);
+int sg_logn_sizes(sg_logn_handle h, int64_t* n, int32_t* P, int32_t* nblocks);
+int sg_logn_matvec(sg_logn_handle h, const double* U, double* Y);
+void sg_logn_destroy(sg_logn_handle h);
+
 const char* sg_last_error(void);
 
 #ifdef __cplusplus

@@ -87,6 +87,10 @@ def _load():
         "sg_batch_setup": [I32, P(SgProblem), P(SgOpts), VP, ctypes.c_size_t, VP, P(VP)],
         "sg_batch_sizes": [VP, I32, P(I64), P(I32)],
         "sg_batch_solve": [VP, P(VP), P(VP), D, I32, I32, P(SgStats), P(D)],
+        "sg_logn_workspace_bytes": [P(SgProblem), P(ctypes.c_size_t)],
+        "sg_logn_setup": [P(SgProblem), VP, ctypes.c_size_t, VP, P(VP)],
+        "sg_logn_sizes": [VP, P(I64), P(I32), P(I32)],
+        "sg_logn_matvec": [VP, VP, VP],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -96,6 +100,8 @@ def _load():
     lib.sg_destroy.restype = None
     lib.sg_batch_destroy.argtypes = [VP]
     lib.sg_batch_destroy.restype = None
+    lib.sg_logn_destroy.argtypes = [VP]
+    lib.sg_logn_destroy.restype = None
     lib.sg_last_error.argtypes = []
     lib.sg_last_error.restype = ctypes.c_char_p
     return lib
@@ -358,6 +364,48 @@ class SGBatch:
     def close(self):
         if getattr(self, "handle", None):
             lib.sg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LognormalOperator:
+    """The lognormal-coefficient SG operator (sg_logn_*): ``mean`` and ``cov``
+    of the coefficient, KL data of the Gaussian field from ``problem``."""
+
+    def __init__(self, problem, mean: float, cov: float, device="cuda"):
+        dev = torch.device(device)
+        self.device = dev if dev.index is not None else torch.device("cuda", torch.cuda.current_device())
+        cp, keep = make_c_problem(problem)
+        cp.theta0 = float(mean)
+        cp.sigma = float(cov)
+        nb = ctypes.c_size_t(0)
+        _check(lib.sg_logn_workspace_bytes(ctypes.byref(cp), ctypes.byref(nb)))
+        self.workspace = torch.empty(max(1, int(nb.value)), dtype=torch.uint8, device=self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib.sg_logn_setup(ctypes.byref(cp), _dptr(self.workspace), int(nb.value), ctypes.c_void_p(stream),
+                                 ctypes.byref(h)))
+        self.handle = h
+        n, P, nb_ = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.sg_logn_sizes(self.handle, ctypes.byref(n), ctypes.byref(P), ctypes.byref(nb_)))
+        self.n, self.P, self.nblocks = int(n.value), int(P.value), int(nb_.value)
+
+    def matvec(self, U: torch.Tensor, Y: torch.Tensor = None) -> torch.Tensor:
+        if U.dtype != torch.float64 or not U.is_contiguous() or tuple(U.shape) != (self.P, self.n) \
+                or U.device != self.device:
+            raise ValueError(f"expected a contiguous float64 ({self.P}, {self.n}) tensor on {self.device}")
+        Y = torch.empty_like(U) if Y is None else Y
+        _check(lib.sg_logn_matvec(self.handle, _dptr(U), _dptr(Y)))
+        return Y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.sg_logn_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,304 @@
+// Lognormal-coefficient SG operator (Section 7, second set of experiments;
+// Tables 6-9): k(x, xi) = exp(g(x, xi)) with the Gaussian field
+// g = mu_g + sum_k g_k(x) xi_k, expanded in the normalised Hermite chaos to
+// total degree 2p. The global matrix A = sum_i G_i (x) K_i,
+// (G_i)_ab = E[psi_i psi_a psi_b], is block dense; this file sets up the block
+// coefficient fields c_ab = sum_i (G_i)_ab k_i on the device and applies A.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "sg_host.h"
+#include "sg_internal.h"
+
+namespace sgk {
+void launch_logn_blocks(const long* ptr, const int* term, const double* g, const double* kc, int ne2, int nslots,
+                        double* C, hipStream_t s);
+void launch_logn_matvec(const int* rptr, const int* rcol, const int* rslot, const double* C, const double* U,
+                        int n_e, long n, int P, double* Y, hipStream_t s);
+}  // namespace sgk
+
+struct sg_logn_ctx {
+  int n_e = 0, M = 0, p = 0, P = 0, nslots = 0;
+  long n = 0;
+  hipStream_t stream = nullptr;
+  double* C = nullptr;  // block coefficient fields, nslots x n_e^2
+  int *rptr = nullptr, *rcol = nullptr, *rslot = nullptr;
+};
+
+namespace {
+
+using sgh::fail;
+
+// Multi-indices of total degree <= p, graded, descending lexicographic within
+// a degree (the order of the chaos columns).
+std::vector<std::vector<int>> graded(int M, int p) {
+  std::vector<std::vector<int>> out;
+  for (int d = 0; d <= p; ++d) {
+    std::vector<std::vector<int>> lvl;
+    std::vector<int> pre;
+    struct Rec {
+      std::vector<std::vector<int>>& lv;
+      int M;
+      void go(std::vector<int>& pre, int rem) {
+        if ((int)pre.size() == M) {
+          if (rem == 0) lv.push_back(pre);
+          return;
+        }
+        for (int v = rem; v >= 0; --v) {
+          pre.push_back(v);
+          go(pre, rem - v);
+          pre.pop_back();
+        }
+      }
+    } rec{lvl, M};
+    if (M == 0) {
+      if (d == 0) lvl.push_back({});
+    } else {
+      rec.go(pre, d);
+    }
+    out.insert(out.end(), lvl.begin(), lvl.end());
+  }
+  return out;
+}
+
+double factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+// E[psi_a psi_b psi_c] for the normalised 1D Hermite basis: with s = (a+b+c)/2
+// an integer not below a, b, c, sqrt(a! b! c!) / ((s-a)! (s-b)! (s-c)!); else 0.
+double triple(int a, int b, int c) {
+  const int two_s = a + b + c;
+  if (two_s & 1) return 0.0;
+  const int s = two_s / 2;
+  if (s < a || s < b || s < c) return 0.0;
+  return std::sqrt(factorial(a) * factorial(b) * factorial(c)) / (factorial(s - a) * factorial(s - b) * factorial(s - c));
+}
+
+struct Plan {
+  int P = 0, T = 0, nslots = 0;
+  long nentries = 0;
+  size_t o_C = 0, o_kc = 0, o_ptr = 0, o_term = 0, o_g = 0, o_rptr = 0, o_rcol = 0, o_rslot = 0, total = 0;
+  // host tables
+  std::vector<std::vector<int>> alpha, coef;
+  std::vector<long> ptr;
+  std::vector<int> term, rptr, rcol, rslot;
+  std::vector<double> g;
+};
+
+size_t take(size_t& total, size_t bytes) {
+  const size_t o = total;
+  total += (bytes + 255) / 256 * 256;
+  return o;
+}
+
+int validate(const sg_problem* pr) {
+  if (!pr) return fail(SG_EINVAL, "null problem");
+  if (pr->n_e < 3 || pr->n_e > 4096) return fail(SG_EINVAL, "n_e must be in 3..4096");
+  if (pr->M < 0 || pr->M > 16 || pr->p < 0 || pr->p > 8) return fail(SG_EINVAL, "need 0 <= M <= 16, 0 <= p <= 8");
+  if (pr->family != SG_FAMILY_HERMITE) return fail(SG_EINVAL, "the lognormal operator uses the Hermite family");
+  if (!(pr->theta0 > 0.0) || !(pr->sigma >= 0.0) || !std::isfinite(pr->theta0) || !std::isfinite(pr->sigma))
+    return fail(SG_EINVAL, "theta0 (mean) must be > 0 and sigma (CoV) >= 0");
+  if (pr->M > 0 && (!pr->s || !pr->phi)) return fail(SG_EINVAL, "null KL arrays");
+  return SG_OK;
+}
+
+// Chaos tables and the (block, term) lists: block (a, b) is stored if some
+// coefficient term i with |i| <= 2p couples a and b.
+int plan(const sg_problem* pr, Plan& pl) {
+  const int M = pr->M, p = pr->p, ne2 = pr->n_e * pr->n_e;
+  pl.alpha = graded(M, p);
+  pl.coef = graded(M, 2 * p);
+  pl.P = (int)pl.alpha.size();
+  pl.T = (int)pl.coef.size();
+  if ((long)pl.P * pl.P > (1L << 22)) return fail(SG_EINVAL, "too many chaos blocks (P^2 > 2^22)");
+  std::unordered_map<unsigned long long, int> index;
+  const unsigned base = 2u * (unsigned)p + 1u;
+  if (M * std::log2((double)base) >= 63.0) return fail(SG_EINVAL, "M and p too large for the coefficient index");
+  auto key = [&](const std::vector<int>& v) {
+    unsigned long long k = 0;
+    for (int d = 0; d < M; ++d) k = k * base + (unsigned)v[d];
+    return k;
+  };
+  for (int t = 0; t < pl.T; ++t) index[key(pl.coef[t])] = t;
+  pl.ptr.assign(1, 0);
+  pl.rptr.assign(1, 0);
+  std::vector<int> cur(M);
+  for (int a = 0; a < pl.P; ++a) {
+    for (int b = 0; b < pl.P; ++b) {
+      const std::vector<int>&A = pl.alpha[a], &B = pl.alpha[b];
+      const long before = (long)pl.term.size();
+      // per dimension i_d runs over |a_d - b_d|, +2, ..., a_d + b_d
+      std::vector<int> lo(M), hi(M);
+      for (int d = 0; d < M; ++d) {
+        lo[d] = std::abs(A[d] - B[d]);
+        hi[d] = A[d] + B[d];
+      }
+      for (int d = 0; d < M; ++d) cur[d] = lo[d];
+      if (M == 0) {
+        pl.term.push_back(0);
+        pl.g.push_back(1.0);
+      } else {
+        while (true) {
+          int deg = 0;
+          for (int d = 0; d < M; ++d) deg += cur[d];
+          if (deg <= 2 * p) {
+            double gv = 1.0;
+            for (int d = 0; d < M && gv != 0.0; ++d) gv *= triple(cur[d], A[d], B[d]);
+            if (gv != 0.0) {
+              pl.term.push_back(index.at(key(cur)));
+              pl.g.push_back(gv);
+            }
+          }
+          int d = M - 1;
+          while (d >= 0 && cur[d] + 2 > hi[d]) {
+            cur[d] = lo[d];
+            --d;
+          }
+          if (d < 0) break;
+          cur[d] += 2;
+        }
+      }
+      if ((long)pl.term.size() > before) {
+        pl.ptr.push_back((long)pl.term.size());
+        pl.rcol.push_back(b);
+        pl.rslot.push_back(pl.nslots++);
+      }
+    }
+    pl.rptr.push_back((int)pl.rcol.size());
+  }
+  pl.nentries = (long)pl.term.size();
+  size_t tot = 0;
+  pl.o_C = take(tot, sizeof(double) * (size_t)pl.nslots * ne2);
+  pl.o_kc = take(tot, sizeof(double) * (size_t)pl.T * ne2);
+  pl.o_ptr = take(tot, sizeof(long) * pl.ptr.size());
+  pl.o_term = take(tot, sizeof(int) * std::max<size_t>(1, pl.term.size()));
+  pl.o_g = take(tot, sizeof(double) * std::max<size_t>(1, pl.g.size()));
+  pl.o_rptr = take(tot, sizeof(int) * pl.rptr.size());
+  pl.o_rcol = take(tot, sizeof(int) * std::max<size_t>(1, pl.rcol.size()));
+  pl.o_rslot = take(tot, sizeof(int) * std::max<size_t>(1, pl.rslot.size()));
+  pl.total = tot;
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sg_logn_workspace_bytes(const sg_problem* prob, size_t* bytes) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  if (!bytes) return fail(SG_EINVAL, "null output");
+  Plan pl;
+  rc = plan(prob, pl);
+  if (rc) return rc;
+  *bytes = pl.total;
+  return SG_OK;
+}
+
+int sg_logn_setup(const sg_problem* pr, void* workspace, size_t workspace_bytes, void* stream, sg_logn_handle* out) {
+  int rc = validate(pr);
+  if (rc) return rc;
+  if (!out || !workspace) return fail(SG_EINVAL, "null workspace or output handle");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(SG_EINVAL, "workspace must be 256-byte aligned");
+  Plan pl;
+  rc = plan(pr, pl);
+  if (rc) return rc;
+  if (workspace_bytes < pl.total) return fail(SG_ENOMEM, "workspace too small");
+  const int n_e = pr->n_e, M = pr->M, ne2 = n_e * n_e;
+  // Chaos coefficients of exp(g) (Section 7; the Gaussian field carries the KL
+  // data and the lognormal mean and CoV fix its mean and variance):
+  // k_i(e) = exp(mu_g + sum_k g_k(e)^2 / 2) prod_k g_k(e)^{i_k} / sqrt(i_k!).
+  const double sg2 = std::log(1.0 + pr->sigma * pr->sigma);
+  const double mu_g = std::log(pr->theta0) - 0.5 * sg2;
+  const double sgm = std::sqrt(sg2);
+  std::vector<double> gk((size_t)M * ne2), base(ne2);
+  for (int e = 0; e < ne2; ++e) {
+    double q = 0.0;
+    for (int k = 0; k < M; ++k) {
+      const double v = sgm * pr->s[k] * pr->phi[(size_t)k * ne2 + e];
+      gk[(size_t)k * ne2 + e] = v;
+      q += v * v;
+    }
+    base[e] = std::exp(mu_g + 0.5 * q);
+  }
+  std::vector<double> kc((size_t)pl.T * ne2);
+  for (int t = 0; t < pl.T; ++t) {
+    double norm = 1.0;
+    for (int k = 0; k < M; ++k) norm *= std::sqrt(factorial(pl.coef[t][k]));
+    for (int e = 0; e < ne2; ++e) {
+      double v = base[e];
+      for (int k = 0; k < M; ++k)
+        for (int j = 0; j < pl.coef[t][k]; ++j) v *= gk[(size_t)k * ne2 + e];
+      kc[(size_t)t * ne2 + e] = v / norm;
+    }
+  }
+  auto* h = new (std::nothrow) sg_logn_ctx();
+  if (!h) return fail(SG_ENOMEM, "host allocation failed");
+  h->n_e = n_e;
+  h->M = M;
+  h->p = pr->p;
+  h->P = pl.P;
+  h->n = (long)(n_e - 1) * (n_e - 1);
+  h->nslots = pl.nslots;
+  h->stream = (hipStream_t)stream;
+  char* w = (char*)workspace;
+  h->C = (double*)(w + pl.o_C);
+  h->rptr = (int*)(w + pl.o_rptr);
+  h->rcol = (int*)(w + pl.o_rcol);
+  h->rslot = (int*)(w + pl.o_rslot);
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, h->stream) : hipSuccess;
+  };
+  hipError_t e = up(pl.o_kc, kc.data(), sizeof(double) * kc.size());
+  if (e == hipSuccess) e = up(pl.o_ptr, pl.ptr.data(), sizeof(long) * pl.ptr.size());
+  if (e == hipSuccess) e = up(pl.o_term, pl.term.data(), sizeof(int) * pl.term.size());
+  if (e == hipSuccess) e = up(pl.o_g, pl.g.data(), sizeof(double) * pl.g.size());
+  if (e == hipSuccess) e = up(pl.o_rptr, pl.rptr.data(), sizeof(int) * pl.rptr.size());
+  if (e == hipSuccess) e = up(pl.o_rcol, pl.rcol.data(), sizeof(int) * pl.rcol.size());
+  if (e == hipSuccess) e = up(pl.o_rslot, pl.rslot.data(), sizeof(int) * pl.rslot.size());
+  if (e == hipSuccess) {
+    sgk::launch_logn_blocks((const long*)(w + pl.o_ptr), (const int*)(w + pl.o_term), (const double*)(w + pl.o_g),
+                            (const double*)(w + pl.o_kc), ne2, pl.nslots, h->C, h->stream);
+    e = hipGetLastError();
+  }
+  // the host tables are freed on return: wait for the copies
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(SG_EDEVICE, std::string("lognormal setup: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return SG_OK;
+}
+
+int sg_logn_sizes(sg_logn_handle h, int64_t* n, int32_t* P, int32_t* nblocks) {
+  if (!h) return fail(SG_EINVAL, "null handle");
+  if (n) *n = h->n;
+  if (P) *P = h->P;
+  if (nblocks) *nblocks = h->nslots;
+  return SG_OK;
+}
+
+int sg_logn_matvec(sg_logn_handle h, const double* U, double* Y) {
+  if (!h || !U || !Y) return fail(SG_EINVAL, "null argument");
+  if (U == Y) return fail(SG_EINVAL, "U and Y must be distinct");
+  sgk::launch_logn_matvec(h->rptr, h->rcol, h->rslot, h->C, U, h->n_e, h->n, h->P, Y, h->stream);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+void sg_logn_destroy(sg_logn_handle h) { delete h; }
+
+}  // extern "C"
