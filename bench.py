@@ -324,6 +324,39 @@ def main():
         extra.update(bench_batch(CHEB_DEGREE))
         torch.cuda.empty_cache()
 
+        # lognormal-coefficient operator (Section 7, Tables 6-9): the paper's finest
+        # mesh of Table 9 (h = 1/30, N = 4, degree 4) and a 256^2 grid at degree 2
+        from paper_1205_1864_amd.binding import LognormalOperator
+        for label, kw in (("logn_30sq_N4_p4", dict(n_e=30, M=4, p=4)), ("logn_256sq_N4_p2", dict(n_e=256, M=4, p=2))):
+            pr = named_problem("small", L=0.5, **kw)
+            op = LognormalOperator(pr, 1.0, 1.0)
+            Ul = to_device_block(random_block(op.P, op.n, seed=1))
+            Yl = torch.empty_like(Ul)
+            stream = torch.cuda.current_stream()
+            for _ in range(3):
+                op.matvec(Ul, Yl)
+            ts = []
+            for _ in range(20):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                op.matvec(Ul, Yl)
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            # algorithmic bytes: U and Y once, every stored block field once
+            nbytes = 2.0 * op.n * op.P * 8 + op.nblocks * pr.n_e * pr.n_e * 8.0
+            extra[f"{label}_matvec_ms"] = ms
+            extra[f"{label}_blocks"] = op.nblocks
+            extra[f"{label}_GBs"] = nbytes / (ms * 1e-3) / 1e9
+            extra[f"{label}_frac"] = extra[f"{label}_GBs"] / HBM_PEAK_GBS
+            log(f"{label}: {ms:.3f} ms, {op.nblocks} blocks, {extra[f'{label}_GBs']:.0f} GB/s")
+            op.close()
+            del op, Ul, Yl
+            torch.cuda.empty_cache()
+        torch.cuda.empty_cache()
+
     achieved = bytes_inner / (ms_inner * 1e-3) / 1e9 if ms_inner > 0 else 0.0
     # the counter traffic belongs to the schedules it was measured with
     pcg_traffic = PCG_TRAFFIC_BYTES if (schedule["pcg_tile"], schedule["pcg_max_blocks"]) == (32, 0) else None
