@@ -310,7 +310,8 @@ void sg_batch_destroy(sg_batch b);
  * The fields of sg_problem mean here: theta0 > 0 the mean of k, sigma >= 0 its
  * coefficient of variation, s and phi the KL data of the Gaussian field;
  * family must be SG_FAMILY_HERMITE; 3 <= n_e <= 4096, M <= 16, p <= 8,
- * P^2 <= 2^22. sigma_g^2 = ln(1 + sigma^2) and mu_g = ln(theta0) - sigma_g^2/2
+ * P^2 <= 2^22, C(M+2p, 2p) <= 2^20 coefficient terms and that count times
+ * n_e^2 <= 2.5e8 (the host builds the terms' element fields). sigma_g^2 = ln(1 + sigma^2) and mu_g = ln(theta0) - sigma_g^2/2
  * give k that mean and CoV. The global matrix A = sum_i G_i (x) K_i with
  * (G_i)_ab = E[psi_i psi_a psi_b] couples every pair of chaos blocks that
  * some term reaches (block dense); the library stores each such block's

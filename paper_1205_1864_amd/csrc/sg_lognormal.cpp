@@ -118,6 +118,16 @@ int validate(const sg_problem* pr) {
 // coefficient term i with |i| <= 2p couples a and b.
 int plan(const sg_problem* pr, Plan& pl) {
   const int M = pr->M, p = pr->p, ne2 = pr->n_e * pr->n_e;
+  // sizes before any table is built: P = C(M+p, p) chaos functions, T = C(M+2p, 2p) coefficient terms
+  auto binom = [](int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+  };
+  const double P_est = binom(M + p, p), T_est = binom(M + 2 * p, 2 * p);
+  if (P_est * P_est > double(1L << 22)) return fail(SG_EINVAL, "too many chaos blocks (P^2 > 2^22)");
+  if (T_est > double(1 << 20) || T_est * ne2 > 2.5e8)
+    return fail(SG_EINVAL, "too many coefficient terms (C(M+2p, 2p) > 2^20 or times n_e^2 > 2.5e8)");
   pl.alpha = graded(M, p);
   pl.coef = graded(M, 2 * p);
   pl.P = (int)pl.alpha.size();

@@ -47,3 +47,23 @@ def test_workspace_query_and_validation(b):
         setattr(q, field, val)
         with pytest.raises(b.SGError):
             b.workspace_bytes(q, b.Options())
+
+
+def test_lognormal_workspace_query(b):
+    """The lognormal operator's size query: the stored block fields dominate
+    (nblocks n_e^2 FP64); oversize chaos or coefficient sets are rejected
+    before any table is built."""
+    import ctypes
+    from sg_inputs import named_problem
+
+    def query(**kw):
+        pr = named_problem("small", L=0.5, **kw)
+        cp, keep = b.make_c_problem(pr)
+        cp.theta0, cp.sigma = 1.0, 1.0
+        nb = ctypes.c_size_t(0)
+        return b.lib.sg_logn_workspace_bytes(ctypes.byref(cp), ctypes.byref(nb)), nb.value
+
+    rc, nb = query(n_e=10, M=4, p=4)
+    assert rc == 0 and nb >= 70 * 70 * 100 * 8
+    assert query(n_e=64, M=16, p=8)[0] == b.SG_EINVAL
+    assert query(n_e=256, M=10, p=3)[0] == b.SG_EINVAL
