@@ -27,7 +27,9 @@ __global__ void __launch_bounds__(256) logn_blocks_kernel(const long* __restrict
 // Y[:, a] = sum over the stored blocks (a, b) of K(c_ab) U[:, b]: one thread
 // per (interior node, chaos row a). The Q1 element matrix of the unit
 // coefficient is (4 on the diagonal, -1 along an edge, -2 across) / 6; nodes
-// on the boundary carry zero.
+// on the boundary carry zero. The node's 3 x 3 neighbourhood offsets and
+// boundary masks are fixed per thread, so every load of a block is
+// unconditional (a neighbour off the grid reads the node itself, masked to 0).
 __global__ void __launch_bounds__(256) logn_matvec_kernel(const int* __restrict__ rptr, const int* __restrict__ rcol,
                                                           const int* __restrict__ rslot,
                                                           const double* __restrict__ C,
@@ -39,26 +41,36 @@ __global__ void __launch_bounds__(256) logn_matvec_kernel(const int* __restrict_
   const int nx = n_e - 1;
   const int ix = (int)(xi % nx) + 1, iy = (int)(xi / nx) + 1;  // grid node, 1..n_e-1
   const long ne2 = (long)n_e * n_e;
+  long off[3][3];
+  double msk[3][3];
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int gx = ix + dx - 1, gy = iy + dy - 1;
+      const bool in = gx >= 1 && gx <= nx && gy >= 1 && gy <= nx;
+      off[dy][dx] = in ? (long)(gy - 1) * nx + (gx - 1) : xi;
+      msk[dy][dx] = in ? 1.0 : 0.0;
+    }
+  // elements below-left, below-right, above-left, above-right of the node
+  const long e00 = (long)(iy - 1) * n_e + (ix - 1);
   double y = 0.0;
   for (int r = rptr[a]; r < rptr[a + 1]; ++r) {
     const double* __restrict__ u = U + (long)rcol[r] * n;
     const double* __restrict__ c = C + (long)rslot[r] * ne2;
-    // node value at grid point (gx, gy); zero on the boundary
-    auto val = [&](int gx, int gy) -> double {
-      return (gx >= 1 && gx <= nx && gy >= 1 && gy <= nx) ? u[(long)(gy - 1) * nx + (gx - 1)] : 0.0;
-    };
+    double v[3][3];
 #pragma unroll
-    for (int ey = iy - 1; ey <= iy; ++ey) {
+    for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int ex = ix - 1; ex <= ix; ++ex) {
-        // the node sits at corner (cx, cy) of element (ex, ey); the other corners
-        // are the edge neighbours (ox, iy), (ix, oy) and the opposite (ox, oy)
-        const int ox = ex == ix ? ix + 1 : ix - 1;
-        const int oy = ey == iy ? iy + 1 : iy - 1;
-        const double s = 4.0 * val(ix, iy) - val(ox, iy) - val(ix, oy) - 2.0 * val(ox, oy);
-        y += c[(long)ey * n_e + ex] * s;
-      }
-    }
+      for (int dx = 0; dx < 3; ++dx) v[dy][dx] = u[off[dy][dx]] * msk[dy][dx];
+    const double c00 = c[e00], c01 = c[e00 + 1], c10 = c[e00 + n_e], c11 = c[e00 + n_e + 1];
+    const double uc = 4.0 * v[1][1];
+    // element (ey, ex) with the node at one corner: edge neighbours (ox, iy),
+    // (ix, oy) and the opposite corner (ox, oy)
+    y += c00 * (uc - v[1][0] - v[0][1] - 2.0 * v[0][0]);
+    y += c01 * (uc - v[1][2] - v[0][1] - 2.0 * v[0][2]);
+    y += c10 * (uc - v[1][0] - v[2][1] - 2.0 * v[2][0]);
+    y += c11 * (uc - v[1][2] - v[2][1] - 2.0 * v[2][2]);
   }
   Y[(long)a * n + xi] = y * (1.0 / 6.0);
 }
