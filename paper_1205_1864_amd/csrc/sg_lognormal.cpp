@@ -88,7 +88,6 @@ double triple(int a, int b, int c) {
 
 struct Plan {
   int P = 0, T = 0, nslots = 0;
-  long nentries = 0;
   size_t o_C = 0, o_kc = 0, o_ptr = 0, o_term = 0, o_g = 0, o_rptr = 0, o_rcol = 0, o_rslot = 0, total = 0;
   // host tables
   std::vector<std::vector<int>> alpha, coef;
@@ -180,6 +179,7 @@ int plan(const sg_problem* pr, Plan& pl) {
           cur[d] += 2;
         }
       }
+      if (pl.term.size() > (size_t(1) << 28)) return fail(SG_EINVAL, "too many (block, term) couplings (> 2^28)");
       if ((long)pl.term.size() > before) {
         pl.ptr.push_back((long)pl.term.size());
         pl.rcol.push_back(b);
@@ -188,7 +188,6 @@ int plan(const sg_problem* pr, Plan& pl) {
     }
     pl.rptr.push_back((int)pl.rcol.size());
   }
-  pl.nentries = (long)pl.term.size();
   size_t tot = 0;
   pl.o_C = take(tot, sizeof(double) * (size_t)pl.nslots * ne2);
   pl.o_kc = take(tot, sizeof(double) * (size_t)pl.T * ne2);
