@@ -5,6 +5,8 @@
 // with K(c) the Q1 stiffness of the element field c (eq. (global-matrix-block)).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sg_internal.h"
 
 namespace sgk {
@@ -73,6 +75,134 @@ __global__ void __launch_bounds__(256) logn_matvec_kernel(const int* __restrict_
     y += c11 * (uc - v[1][2] - v[2][1] - 2.0 * v[2][2]);
   }
   Y[(long)a * n + xi] = y * (1.0 / 6.0);
+}
+
+// Sub-block of the operator for the hierarchical preconditioner: rows
+// row0..row0+nrows-1 and columns col0..col1-1 of A (eq. (global-matrix-hierarchy)).
+// X holds the columns col0.. (ld n); mode 0: Y = A_sub X; mode 1: Y = R - A_sub X
+// (R may be Y). Same element form and summation order as logn_matvec_kernel.
+__global__ void __launch_bounds__(256) logn_apply_kernel(const int* __restrict__ rptr, const int* __restrict__ rcol,
+                                                         const int* __restrict__ rslot,
+                                                         const double* __restrict__ C,
+                                                         const double* __restrict__ X, int n_e, long n, int row0,
+                                                         int col0, int col1, int mode, const double* R, double* Y) {
+  const long xi = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = row0 + (int)blockIdx.y;
+  if (xi >= n) return;
+  const int nx = n_e - 1;
+  const int ix = (int)(xi % nx) + 1, iy = (int)(xi / nx) + 1;
+  const long ne2 = (long)n_e * n_e;
+  long off[3][3];
+  double msk[3][3];
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int gx = ix + dx - 1, gy = iy + dy - 1;
+      const bool in = gx >= 1 && gx <= nx && gy >= 1 && gy <= nx;
+      off[dy][dx] = in ? (long)(gy - 1) * nx + (gx - 1) : xi;
+      msk[dy][dx] = in ? 1.0 : 0.0;
+    }
+  const long e00 = (long)(iy - 1) * n_e + (ix - 1);
+  double y = 0.0;
+  for (int r = rptr[a]; r < rptr[a + 1]; ++r) {
+    const int b = rcol[r];
+    if (b < col0 || b >= col1) continue;
+    const double* __restrict__ u = X + (long)(b - col0) * n;
+    const double* __restrict__ c = C + (long)rslot[r] * ne2;
+    double v[3][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) v[dy][dx] = u[off[dy][dx]] * msk[dy][dx];
+    const double c00 = c[e00], c01 = c[e00 + 1], c10 = c[e00 + n_e], c11 = c[e00 + n_e + 1];
+    const double uc = 4.0 * v[1][1];
+    y += c00 * (uc - v[1][0] - v[0][1] - 2.0 * v[0][0]);
+    y += c01 * (uc - v[1][2] - v[0][1] - 2.0 * v[0][2]);
+    y += c10 * (uc - v[1][0] - v[2][1] - 2.0 * v[2][0]);
+    y += c11 * (uc - v[1][2] - v[2][1] - 2.0 * v[2][2]);
+  }
+  y *= (1.0 / 6.0);
+  const long o = (long)(a - row0) * n + xi;
+  Y[o] = mode ? R[o] - y : y;
+}
+
+// Inverse diagonal of A (Jacobi scaling of the level-block solves): the
+// (a, a) block's stencil centre, (4/6) times the sum of c_aa over the four
+// elements around the node.
+__global__ void __launch_bounds__(256) logn_invdiag_kernel(const int* __restrict__ rptr, const int* __restrict__ rcol,
+                                                           const int* __restrict__ rslot,
+                                                           const double* __restrict__ C, int n_e, long n,
+                                                           double* __restrict__ Dinv) {
+  const long xi = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (xi >= n) return;
+  const int nx = n_e - 1;
+  const int ix = (int)(xi % nx) + 1, iy = (int)(xi / nx) + 1;
+  const long e00 = (long)(iy - 1) * n_e + (ix - 1);
+  double d = 0.0;
+  for (int r = rptr[a]; r < rptr[a + 1]; ++r) {
+    if (rcol[r] != a) continue;
+    const double* c = C + (long)rslot[r] * n_e * n_e;
+    d = (4.0 / 6.0) * (c[e00] + c[e00 + 1] + c[e00 + n_e] + c[e00 + n_e + 1]);
+  }
+  Dinv[(long)a * n + xi] = d > 0.0 ? 1.0 / d : 0.0;
+}
+
+// Partial dot products: block b sums a strided range in a fixed order, then a
+// fixed LDS tree; the host adds the partials in index order.
+__global__ void __launch_bounds__(256) logn_dot_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                                       long len, double* __restrict__ part) {
+  __shared__ double sm[256];
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x)
+    acc += x[i] * y[i];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+// y = a x + b y (b = 0 overwrites y), or y = d * x (elementwise, mode 1).
+__global__ void __launch_bounds__(256) logn_axpby_kernel(long len, double a, const double* __restrict__ x, double b,
+                                                         double* __restrict__ y, int mode,
+                                                         const double* __restrict__ d) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x) {
+    if (mode == 1) {
+      y[i] = d[i] * x[i];
+    } else {
+      y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
+    }
+  }
+}
+
+void launch_logn_apply(const int* rptr, const int* rcol, const int* rslot, const double* C, const double* X,
+                       int n_e, long n, int row0, int nrows, int col0, int col1, int mode, const double* R, double* Y,
+                       hipStream_t s) {
+  if (n <= 0 || nrows <= 0) return;
+  hipLaunchKernelGGL(logn_apply_kernel, dim3((unsigned)((n + 255) / 256), nrows), dim3(256), 0, s, rptr, rcol, rslot,
+                     C, X, n_e, n, row0, col0, col1, mode, R, Y);
+}
+
+void launch_logn_invdiag(const int* rptr, const int* rcol, const int* rslot, const double* C, int n_e, long n, int P,
+                         double* Dinv, hipStream_t s) {
+  if (n <= 0 || P <= 0) return;
+  hipLaunchKernelGGL(logn_invdiag_kernel, dim3((unsigned)((n + 255) / 256), P), dim3(256), 0, s, rptr, rcol, rslot, C,
+                     n_e, n, Dinv);
+}
+
+void launch_logn_dot(const double* x, const double* y, long len, double* part, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(logn_dot_kernel, dim3(nblocks), dim3(256), 0, s, x, y, len, part);
+}
+
+void launch_logn_axpby(long len, double a, const double* x, double b, double* y, int mode, const double* d,
+                       hipStream_t s) {
+  if (len <= 0) return;
+  const long nb = std::min<long>((len + 255) / 256, 4096);
+  hipLaunchKernelGGL(logn_axpby_kernel, dim3((unsigned)nb), dim3(256), 0, s, len, a, x, b, y, mode, d);
 }
 
 void launch_logn_blocks(const long* ptr, const int* term, const double* g, const double* kc, int ne2, int nslots,

@@ -24,7 +24,21 @@ void launch_logn_blocks(const long* ptr, const int* term, const double* g, const
                         double* C, hipStream_t s);
 void launch_logn_matvec(const int* rptr, const int* rcol, const int* rslot, const double* C, const double* U,
                         int n_e, long n, int P, double* Y, hipStream_t s);
+void launch_logn_apply(const int* rptr, const int* rcol, const int* rslot, const double* C, const double* X,
+                       int n_e, long n, int row0, int nrows, int col0, int col1, int mode, const double* R, double* Y,
+                       hipStream_t s);
+void launch_logn_invdiag(const int* rptr, const int* rcol, const int* rslot, const double* C, int n_e, long n, int P,
+                         double* Dinv, hipStream_t s);
+void launch_logn_dot(const double* x, const double* y, long len, double* part, int nblocks, hipStream_t s);
+void launch_logn_axpby(long len, double a, const double* x, double b, double* y, int mode, const double* d,
+                       hipStream_t s);
 }  // namespace sgk
+
+namespace sgh {
+double lanczos_kappa(const std::vector<double>& al, const std::vector<double>& be);
+}  // namespace sgh
+
+constexpr int kLognDotBlocks = 256;
 
 struct sg_logn_ctx {
   int n_e = 0, M = 0, p = 0, P = 0, nslots = 0;
@@ -32,6 +46,12 @@ struct sg_logn_ctx {
   hipStream_t stream = nullptr;
   double* C = nullptr;  // block coefficient fields, nslots x n_e^2
   int *rptr = nullptr, *rcol = nullptr, *rslot = nullptr;
+  std::vector<int> off;  // level offsets of the chaos columns, p + 2 entries
+  // solver vectors (n x P each): outer FCG r, z, p, q; preconditioner copy of
+  // r and a level temporary; level-solve r, z, p, q; inverse diagonal of A
+  double *R = nullptr, *Z = nullptr, *Pv = nullptr, *Q = nullptr, *Rh = nullptr, *W = nullptr;
+  double *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *Dinv = nullptr, *part = nullptr;
+  std::vector<double> host_part;
 };
 
 namespace {
@@ -89,6 +109,7 @@ double triple(int a, int b, int c) {
 struct Plan {
   int P = 0, T = 0, nslots = 0;
   size_t o_C = 0, o_kc = 0, o_ptr = 0, o_term = 0, o_g = 0, o_rptr = 0, o_rcol = 0, o_rslot = 0, total = 0;
+  size_t o_vec = 0, o_part = 0;
   // host tables
   std::vector<std::vector<int>> alpha, coef;
   std::vector<long> ptr;
@@ -197,7 +218,83 @@ int plan(const sg_problem* pr, Plan& pl) {
   pl.o_rptr = take(tot, sizeof(int) * pl.rptr.size());
   pl.o_rcol = take(tot, sizeof(int) * std::max<size_t>(1, pl.rcol.size()));
   pl.o_rslot = take(tot, sizeof(int) * std::max<size_t>(1, pl.rslot.size()));
+  const size_t nP = (size_t)(pr->n_e - 1) * (pr->n_e - 1) * pl.P;
+  pl.o_vec = take(tot, sizeof(double) * nP * 11);
+  pl.o_part = take(tot, sizeof(double) * kLognDotBlocks);
   pl.total = tot;
+  return SG_OK;
+}
+
+// Deterministic FP64 dot product: device partials, host sum in index order.
+int dotp(sg_logn_ctx* h, const double* x, const double* y, long len, double& out) {
+  sgk::launch_logn_dot(x, y, len, h->part, kLognDotBlocks, h->stream);
+  SG_HIP(hipMemcpyAsync(h->host_part.data(), h->part, sizeof(double) * kLognDotBlocks, hipMemcpyDeviceToHost,
+                        h->stream));
+  SG_HIP(hipStreamSynchronize(h->stream));
+  double s = 0.0;
+  for (double v : h->host_part) s += v;
+  out = s;
+  return SG_OK;
+}
+
+// D_l X = B for the full level block D_l (Section 7: the level blocks couple),
+// by Jacobi-preconditioned CG on the n x P_l system from X = 0, to
+// ||r|| <= rtol ||B|| or maxit iterations. B and X: n x P_l device blocks.
+int level_solve(sg_logn_ctx* h, int l, const double* B, double* X, double rtol, int maxit, long& its) {
+  const int lo = h->off[l], nr = h->off[l + 1] - h->off[l];
+  const long len = h->n * (long)nr;
+  hipStream_t s = h->stream;
+  const double* dinv = h->Dinv + (long)lo * h->n;
+  double bb = 0.0, rz = 0.0, pq = 0.0, rr = 0.0, rzn = 0.0;
+  int rc = dotp(h, B, B, len, bb);
+  if (rc) return rc;
+  sgk::launch_logn_axpby(len, 0.0, B, 0.0, X, 0, nullptr, s);  // X = 0
+  if (bb == 0.0) return SG_OK;
+  sgk::launch_logn_axpby(len, 1.0, B, 0.0, h->cr, 0, nullptr, s);    // r = B
+  sgk::launch_logn_axpby(len, 0.0, h->cr, 0.0, h->cz, 1, dinv, s);   // z = D^-1 r
+  sgk::launch_logn_axpby(len, 1.0, h->cz, 0.0, h->cp, 0, nullptr, s);  // p = z
+  if ((rc = dotp(h, h->cr, h->cz, len, rz))) return rc;
+  for (int it = 0; it < maxit; ++it) {
+    sgk::launch_logn_apply(h->rptr, h->rcol, h->rslot, h->C, h->cp, h->n_e, h->n, lo, nr, lo, lo + nr, 0, nullptr,
+                           h->cq, s);
+    if ((rc = dotp(h, h->cp, h->cq, len, pq))) return rc;
+    if (!(pq > 0.0) || !std::isfinite(pq)) break;
+    const double alpha = rz / pq;
+    sgk::launch_logn_axpby(len, alpha, h->cp, 1.0, X, 0, nullptr, s);
+    sgk::launch_logn_axpby(len, -alpha, h->cq, 1.0, h->cr, 0, nullptr, s);
+    ++its;
+    if ((rc = dotp(h, h->cr, h->cr, len, rr))) return rc;
+    if (rr <= rtol * rtol * bb) break;
+    sgk::launch_logn_axpby(len, 0.0, h->cr, 0.0, h->cz, 1, dinv, s);
+    if ((rc = dotp(h, h->cr, h->cz, len, rzn))) return rc;
+    const double beta = rzn / rz;
+    rz = rzn;
+    sgk::launch_logn_axpby(len, 1.0, h->cz, beta, h->cp, 0, nullptr, s);
+  }
+  return SG_OK;
+}
+
+// One action of Algorithm 1 with the full level blocks: down sweep
+// y_l = D_l^-1 r_l, r_{<l} -= B_l y_l (l = p..1); u_0 = D_0^-1 r_0; up sweep
+// u_l = D_l^-1 (r_l - C_l u_{<l}) (l = 1..p). Z receives u.
+int hsc_apply(sg_logn_ctx* h, const double* R, double* Z, double rtol, int maxit, long& its) {
+  const long nP = h->n * (long)h->P;
+  hipStream_t s = h->stream;
+  sgk::launch_logn_axpby(nP, 1.0, R, 0.0, h->Rh, 0, nullptr, s);
+  int rc;
+  for (int l = h->p; l >= 1; --l) {
+    const int lo = h->off[l], hi = h->off[l + 1];
+    if ((rc = level_solve(h, l, h->Rh + (long)lo * h->n, Z + (long)lo * h->n, rtol, maxit, its))) return rc;
+    sgk::launch_logn_apply(h->rptr, h->rcol, h->rslot, h->C, Z + (long)lo * h->n, h->n_e, h->n, 0, lo, lo, hi, 1,
+                           h->Rh, h->Rh, s);
+  }
+  if ((rc = level_solve(h, 0, h->Rh, Z, rtol, maxit, its))) return rc;
+  for (int l = 1; l <= h->p; ++l) {
+    const int lo = h->off[l], hi = h->off[l + 1];
+    sgk::launch_logn_apply(h->rptr, h->rcol, h->rslot, h->C, Z, h->n_e, h->n, lo, hi - lo, 0, lo, 1,
+                           h->Rh + (long)lo * h->n, h->W, s);
+    if ((rc = level_solve(h, l, h->W, Z + (long)lo * h->n, rtol, maxit, its))) return rc;
+  }
   return SG_OK;
 }
 
@@ -267,6 +364,24 @@ int sg_logn_setup(const sg_problem* pr, void* workspace, size_t workspace_bytes,
   h->rptr = (int*)(w + pl.o_rptr);
   h->rcol = (int*)(w + pl.o_rcol);
   h->rslot = (int*)(w + pl.o_rslot);
+  {
+    const size_t nP = (size_t)h->n * pl.P;
+    double* v = (double*)(w + pl.o_vec);
+    double** vecs[11] = {&h->R, &h->Z, &h->Pv, &h->Q, &h->Rh, &h->W, &h->cr, &h->cz, &h->cp, &h->cq, &h->Dinv};
+    for (int i = 0; i < 11; ++i) *vecs[i] = v + i * nP;
+    h->part = (double*)(w + pl.o_part);
+    h->host_part.assign(kLognDotBlocks, 0.0);
+    h->off.assign(1, 0);
+    for (int d = 0; d <= pr->p; ++d) {
+      int cnt = 0;
+      for (const auto& al : pl.alpha) {
+        int deg = 0;
+        for (int v2 : al) deg += v2;
+        if (deg == d) ++cnt;
+      }
+      h->off.push_back(h->off.back() + cnt);
+    }
+  }
   auto up = [&](size_t off, const void* src, size_t bytes) {
     return bytes ? hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, h->stream) : hipSuccess;
   };
@@ -280,6 +395,7 @@ int sg_logn_setup(const sg_problem* pr, void* workspace, size_t workspace_bytes,
   if (e == hipSuccess) {
     sgk::launch_logn_blocks((const long*)(w + pl.o_ptr), (const int*)(w + pl.o_term), (const double*)(w + pl.o_g),
                             (const double*)(w + pl.o_kc), ne2, pl.nslots, h->C, h->stream);
+    sgk::launch_logn_invdiag(h->rptr, h->rcol, h->rslot, h->C, n_e, h->n, pl.P, h->Dinv, h->stream);
     e = hipGetLastError();
   }
   // the host tables are freed on return: wait for the copies
@@ -305,6 +421,67 @@ int sg_logn_matvec(sg_logn_handle h, const double* U, double* Y) {
   if (U == Y) return fail(SG_EINVAL, "U and Y must be distinct");
   sgk::launch_logn_matvec(h->rptr, h->rcol, h->rslot, h->C, U, h->n_e, h->n, h->P, Y, h->stream);
   SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_logn_solve(sg_logn_handle h, const double* F, double* U, double rtol, int32_t maxit, double inner_rtol,
+                  int32_t inner_maxit, int32_t* outer_it, int64_t* inner_it, double* relres, double* kappa) {
+  if (!h || !F || !U) return fail(SG_EINVAL, "null argument");
+  if (F == U) return fail(SG_EINVAL, "F and U must be distinct");
+  if (!(rtol >= 0.0) || maxit < 0 || !(inner_rtol > 0.0 && inner_rtol < 1.0) || inner_maxit < 1)
+    return fail(SG_EINVAL, "need rtol >= 0, maxit >= 0, 0 < inner_rtol < 1, inner_maxit >= 1");
+  const long nP = h->n * (long)h->P;
+  hipStream_t s = h->stream;
+  // flexible CG (Section 5) on A with Algorithm 1 as the preconditioner
+  sgk::launch_logn_axpby(nP, 0.0, F, 0.0, U, 0, nullptr, s);  // U = 0
+  sgk::launch_logn_axpby(nP, 1.0, F, 0.0, h->R, 0, nullptr, s);
+  double ff = 0.0, rr = 0.0;
+  int rc = dotp(h, F, F, nP, ff);
+  if (rc) return rc;
+  std::vector<double> al, be;
+  long its_in = 0;
+  int it = 0, status = SG_NOT_CONVERGED;
+  double rel = ff > 0.0 ? 1.0 : 0.0, pq_prev = 0.0;
+  if (ff == 0.0 || rel <= rtol) status = SG_OK;
+  for (; status == SG_NOT_CONVERGED && it < maxit; ++it) {
+    if ((rc = hsc_apply(h, h->R, h->Z, inner_rtol, inner_maxit, its_in))) return rc;
+    if (it == 0) {
+      sgk::launch_logn_axpby(nP, 1.0, h->Z, 0.0, h->Pv, 0, nullptr, s);
+    } else {
+      double zq = 0.0;
+      if ((rc = dotp(h, h->Z, h->Q, nP, zq))) return rc;
+      const double beta = -zq / pq_prev;
+      be.push_back(beta);
+      sgk::launch_logn_axpby(nP, 1.0, h->Z, beta, h->Pv, 0, nullptr, s);
+    }
+    sgk::launch_logn_matvec(h->rptr, h->rcol, h->rslot, h->C, h->Pv, h->n_e, h->n, h->P, h->Q, s);
+    double pq = 0.0, pr = 0.0;
+    if ((rc = dotp(h, h->Pv, h->Q, nP, pq))) return rc;
+    if (!(pq > 0.0) || !std::isfinite(pq)) {
+      status = SG_BREAKDOWN;
+      break;
+    }
+    if ((rc = dotp(h, h->Pv, h->R, nP, pr))) return rc;
+    const double alpha = pr / pq;
+    al.push_back(alpha);
+    sgk::launch_logn_axpby(nP, alpha, h->Pv, 1.0, U, 0, nullptr, s);
+    sgk::launch_logn_axpby(nP, -alpha, h->Q, 1.0, h->R, 0, nullptr, s);
+    pq_prev = pq;
+    if ((rc = dotp(h, h->R, h->R, nP, rr))) return rc;
+    rel = std::sqrt(rr / ff);
+    if (rel <= rtol) {
+      status = SG_OK;
+      ++it;
+      break;
+    }
+  }
+  SG_HIP(hipStreamSynchronize(s));
+  if (outer_it) *outer_it = it;
+  if (inner_it) *inner_it = its_in;
+  if (relres) *relres = rel;
+  if (kappa) *kappa = al.empty() ? 1.0 : sgh::lanczos_kappa(al, be);
+  if (status == SG_NOT_CONVERGED) return fail(SG_NOT_CONVERGED, "outer iteration did not converge");
+  if (status == SG_BREAKDOWN) return fail(SG_BREAKDOWN, "breakdown: non-positive or non-finite curvature");
   return SG_OK;
 }
 
