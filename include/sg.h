@@ -329,27 +329,32 @@ void sg_batch_destroy(sg_batch b);
  *   sg_logn_solve            A U = F (distinct n x P device blocks; U is overwritten,
  *                            zero start) by flexible CG (Section 5) to
  *                            ||f - A u||_2 <= rtol ||f||_2 (recursive residual) or maxit
- *                            iterations, preconditioned by Algorithm 1 with the full
- *                            level blocks D_l (they couple here), each D_l solve a
- *                            Jacobi-preconditioned CG on the whole level to
+ *                            iterations, preconditioned (Section 6) by
+ *                            SG_PC_HSC: Algorithm 1 with the full level blocks D_l
+ *                              (they couple here);
+ *                            SG_PC_BGS: block symmetric Gauss-Seidel over the chaos
+ *                              blocks, diagonal blocks A_aa = K(c_aa);
+ *                            SG_PC_MEAN: I (x) K(k_0)^-1, k_0 the mean coefficient.
+ *                            Each block solve is a Jacobi-preconditioned CG to
  *                            inner_rtol (0 < inner_rtol < 1) or inner_maxit
- *                            iterations; the paper found direct and iterative D_l
+ *                            iterations (one per column for the mean-based
+ *                            preconditioner); the paper found direct and iterative D_l
  *                            solves to the outer tolerance equivalent. Host outputs
  *                            (each may be NULL): outer iterations, total inner
  *                            iterations, final relative residual and the Lanczos
  *                            condition estimate of the preconditioned operator.
  *                            Synchronises the stream. Returns SG_OK,
  *                            SG_NOT_CONVERGED or SG_BREAKDOWN as sg_solve.
- * The mean-based and block Gauss-Seidel comparators of this case are not on
- * the GPU. */
+ */
 typedef struct sg_logn_ctx* sg_logn_handle;
 int sg_logn_workspace_bytes(const sg_problem* prob, size_t* bytes);
 int sg_logn_setup(const sg_problem* prob, void* workspace, size_t workspace_bytes, void* stream,
                   sg_logn_handle* out);
 int sg_logn_sizes(sg_logn_handle h, int64_t* n, int32_t* P, int32_t* nblocks);
 int sg_logn_matvec(sg_logn_handle h, const double* U, double* Y);
-int sg_logn_solve(sg_logn_handle h, const double* F, double* U, double rtol, int32_t maxit, double inner_rtol,
-                  int32_t inner_maxit, int32_t* outer_it, int64_t* inner_it, double* relres, double* kappa);
+int sg_logn_solve(sg_logn_handle h, int32_t precond, const double* F, double* U, double rtol, int32_t maxit,
+                  double inner_rtol, int32_t inner_maxit, int32_t* outer_it, int64_t* inner_it, double* relres,
+                  double* kappa);
 void sg_logn_destroy(sg_logn_handle h);
 
 const char* sg_last_error(void);

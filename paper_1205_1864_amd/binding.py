@@ -91,7 +91,7 @@ def _load():
         "sg_logn_setup": [P(SgProblem), VP, ctypes.c_size_t, VP, P(VP)],
         "sg_logn_sizes": [VP, P(I64), P(I32), P(I32)],
         "sg_logn_matvec": [VP, VP, VP],
-        "sg_logn_solve": [VP, VP, VP, D, I32, D, I32, P(I32), P(I64), P(D), P(D)],
+        "sg_logn_solve": [VP, I32, VP, VP, D, I32, D, I32, P(I32), P(I64), P(D), P(D)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -405,12 +405,14 @@ class LognormalOperator:
         return Y
 
     def solve(self, F: torch.Tensor, U: torch.Tensor = None, rtol=1e-8, maxit=500, inner_rtol=1e-12,
-              inner_maxit=5000):
-        """A U = F by flexible CG with Algorithm 1 over the full level blocks."""
+              inner_maxit=5000, precond="hsc"):
+        """A U = F by flexible CG; precond "hsc" (Algorithm 1 over the full level
+        blocks), "bgs" or "mean"."""
+        pc = {"hsc": SG_PC_HSC, "bgs": SG_PC_BGS, "mean": SG_PC_MEAN}[precond]
         self.matvec(F, torch.empty_like(F))  # shape and device check
         U = torch.empty_like(F) if U is None else U
         it, iin, rel, kap = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-        rc = _check(lib.sg_logn_solve(self.handle, _dptr(F), _dptr(U), float(rtol), int(maxit), float(inner_rtol),
+        rc = _check(lib.sg_logn_solve(self.handle, pc, _dptr(F), _dptr(U), float(rtol), int(maxit), float(inner_rtol),
                                       int(inner_maxit), ctypes.byref(it), ctypes.byref(iin), ctypes.byref(rel),
                                       ctypes.byref(kap)), allow_positive=True)
         return U, {"rc": rc, "outer_it": int(it.value), "inner_it": int(iin.value), "relres": float(rel.value),

@@ -127,6 +127,36 @@ __global__ void __launch_bounds__(256) logn_apply_kernel(const int* __restrict__
   Y[o] = mode ? R[o] - y : y;
 }
 
+// Y[:, j] = K(c) X[:, j] for ncols columns with one element field c (the
+// mean coefficient: the blocks of the mean-based preconditioner).
+__global__ void __launch_bounds__(256) logn_mean_apply_kernel(const double* __restrict__ c,
+                                                              const double* __restrict__ X, int n_e, long n,
+                                                              double* __restrict__ Y) {
+  const long xi = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (xi >= n) return;
+  const int nx = n_e - 1;
+  const int ix = (int)(xi % nx) + 1, iy = (int)(xi / nx) + 1;
+  const double* __restrict__ u = X + (long)j * n;
+  double v[3][3];
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int gx = ix + dx - 1, gy = iy + dy - 1;
+      const bool in = gx >= 1 && gx <= nx && gy >= 1 && gy <= nx;
+      v[dy][dx] = u[in ? (long)(gy - 1) * nx + (gx - 1) : xi] * (in ? 1.0 : 0.0);
+    }
+  const long e00 = (long)(iy - 1) * n_e + (ix - 1);
+  const double c00 = c[e00], c01 = c[e00 + 1], c10 = c[e00 + n_e], c11 = c[e00 + n_e + 1];
+  const double uc = 4.0 * v[1][1];
+  double y = c00 * (uc - v[1][0] - v[0][1] - 2.0 * v[0][0]);
+  y += c01 * (uc - v[1][2] - v[0][1] - 2.0 * v[0][2]);
+  y += c10 * (uc - v[1][0] - v[2][1] - 2.0 * v[2][0]);
+  y += c11 * (uc - v[1][2] - v[2][1] - 2.0 * v[2][2]);
+  Y[(long)j * n + xi] = y * (1.0 / 6.0);
+}
+
 // Inverse diagonal of A (Jacobi scaling of the level-block solves): the
 // (a, a) block's stencil centre, (4/6) times the sum of c_aa over the four
 // elements around the node.
@@ -166,13 +196,14 @@ __global__ void __launch_bounds__(256) logn_dot_kernel(const double* __restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
 }
 
-// y = a x + b y (b = 0 overwrites y), or y = d * x (elementwise, mode 1).
+// y = a x + b y (b = 0 overwrites y), or y = d * x elementwise with d of
+// period dn (mode 1).
 __global__ void __launch_bounds__(256) logn_axpby_kernel(long len, double a, const double* __restrict__ x, double b,
                                                          double* __restrict__ y, int mode,
-                                                         const double* __restrict__ d) {
+                                                         const double* __restrict__ d, long dn) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x) {
     if (mode == 1) {
-      y[i] = d[i] * x[i];
+      y[i] = d[i % dn] * x[i];
     } else {
       y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
     }
@@ -199,10 +230,17 @@ void launch_logn_dot(const double* x, const double* y, long len, double* part, i
 }
 
 void launch_logn_axpby(long len, double a, const double* x, double b, double* y, int mode, const double* d,
-                       hipStream_t s) {
+                       long dn, hipStream_t s) {
   if (len <= 0) return;
   const long nb = std::min<long>((len + 255) / 256, 4096);
-  hipLaunchKernelGGL(logn_axpby_kernel, dim3((unsigned)nb), dim3(256), 0, s, len, a, x, b, y, mode, d);
+  hipLaunchKernelGGL(logn_axpby_kernel, dim3((unsigned)nb), dim3(256), 0, s, len, a, x, b, y, mode, d,
+                     dn > 0 ? dn : len);
+}
+
+void launch_logn_mean_apply(const double* c, const double* X, int n_e, long n, int ncols, double* Y, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(logn_mean_apply_kernel, dim3((unsigned)((n + 255) / 256), ncols), dim3(256), 0, s, c, X, n_e, n,
+                     Y);
 }
 
 void launch_logn_blocks(const long* ptr, const int* term, const double* g, const double* kc, int ne2, int nslots,

@@ -31,7 +31,8 @@ void launch_logn_invdiag(const int* rptr, const int* rcol, const int* rslot, con
                          double* Dinv, hipStream_t s);
 void launch_logn_dot(const double* x, const double* y, long len, double* part, int nblocks, hipStream_t s);
 void launch_logn_axpby(long len, double a, const double* x, double b, double* y, int mode, const double* d,
-                       hipStream_t s);
+                       long dn, hipStream_t s);
+void launch_logn_mean_apply(const double* c, const double* X, int n_e, long n, int ncols, double* Y, hipStream_t s);
 }  // namespace sgk
 
 namespace sgh {
@@ -51,6 +52,7 @@ struct sg_logn_ctx {
   // r and a level temporary; level-solve r, z, p, q; inverse diagonal of A
   double *R = nullptr, *Z = nullptr, *Pv = nullptr, *Q = nullptr, *Rh = nullptr, *W = nullptr;
   double *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *Dinv = nullptr, *part = nullptr;
+  double* XF = nullptr;  // forward-sweep values of block Gauss-Seidel
   std::vector<double> host_part;
 };
 
@@ -209,6 +211,7 @@ int plan(const sg_problem* pr, Plan& pl) {
     }
     pl.rptr.push_back((int)pl.rcol.size());
   }
+  if (pl.rcol.empty() || pl.rcol[0] != 0) return fail(SG_EINVAL, "internal: block (0, 0) is not the first slot");
   size_t tot = 0;
   pl.o_C = take(tot, sizeof(double) * (size_t)pl.nslots * ne2);
   pl.o_kc = take(tot, sizeof(double) * (size_t)pl.T * ne2);
@@ -219,7 +222,7 @@ int plan(const sg_problem* pr, Plan& pl) {
   pl.o_rcol = take(tot, sizeof(int) * std::max<size_t>(1, pl.rcol.size()));
   pl.o_rslot = take(tot, sizeof(int) * std::max<size_t>(1, pl.rslot.size()));
   const size_t nP = (size_t)(pr->n_e - 1) * (pr->n_e - 1) * pl.P;
-  pl.o_vec = take(tot, sizeof(double) * nP * 11);
+  pl.o_vec = take(tot, sizeof(double) * nP * 12);
   pl.o_part = take(tot, sizeof(double) * kLognDotBlocks);
   pl.total = tot;
   return SG_OK;
@@ -237,39 +240,71 @@ int dotp(sg_logn_ctx* h, const double* x, const double* y, long len, double& out
   return SG_OK;
 }
 
-// D_l X = B for the full level block D_l (Section 7: the level blocks couple),
-// by Jacobi-preconditioned CG on the n x P_l system from X = 0, to
-// ||r|| <= rtol ||B|| or maxit iterations. B and X: n x P_l device blocks.
-int level_solve(sg_logn_ctx* h, int l, const double* B, double* X, double rtol, int maxit, long& its) {
-  const int lo = h->off[l], nr = h->off[l + 1] - h->off[l];
+// Block solve by Jacobi-preconditioned CG from X = 0 to ||r|| <= rtol ||B||
+// or maxit iterations, on the n x nr system of
+//   kind 0: the diagonal sub-block of A over chaos columns lo..lo+nr-1 (a
+//           level block D_l of Section 7, where the level blocks couple, or one
+//           block A_aa);
+//   kind 1: I (x) K(k_0) over nr columns (the mean-based preconditioner).
+// B and X: n x nr device blocks.
+int range_solve(sg_logn_ctx* h, int kind, int lo, int nr, const double* B, double* X, double rtol, int maxit,
+                long& its) {
   const long len = h->n * (long)nr;
   hipStream_t s = h->stream;
-  const double* dinv = h->Dinv + (long)lo * h->n;
+  const double* dinv = kind == 0 ? h->Dinv + (long)lo * h->n : h->Dinv;  // column 0: K(k_0)
+  const long dn = kind == 0 ? len : h->n;
   double bb = 0.0, rz = 0.0, pq = 0.0, rr = 0.0, rzn = 0.0;
   int rc = dotp(h, B, B, len, bb);
   if (rc) return rc;
-  sgk::launch_logn_axpby(len, 0.0, B, 0.0, X, 0, nullptr, s);  // X = 0
+  sgk::launch_logn_axpby(len, 0.0, B, 0.0, X, 0, nullptr, 0, s);  // X = 0
   if (bb == 0.0) return SG_OK;
-  sgk::launch_logn_axpby(len, 1.0, B, 0.0, h->cr, 0, nullptr, s);    // r = B
-  sgk::launch_logn_axpby(len, 0.0, h->cr, 0.0, h->cz, 1, dinv, s);   // z = D^-1 r
-  sgk::launch_logn_axpby(len, 1.0, h->cz, 0.0, h->cp, 0, nullptr, s);  // p = z
+  sgk::launch_logn_axpby(len, 1.0, B, 0.0, h->cr, 0, nullptr, 0, s);    // r = B
+  sgk::launch_logn_axpby(len, 0.0, h->cr, 0.0, h->cz, 1, dinv, dn, s);   // z = D^-1 r
+  sgk::launch_logn_axpby(len, 1.0, h->cz, 0.0, h->cp, 0, nullptr, 0, s);  // p = z
   if ((rc = dotp(h, h->cr, h->cz, len, rz))) return rc;
   for (int it = 0; it < maxit; ++it) {
-    sgk::launch_logn_apply(h->rptr, h->rcol, h->rslot, h->C, h->cp, h->n_e, h->n, lo, nr, lo, lo + nr, 0, nullptr,
-                           h->cq, s);
+    if (kind == 0)
+      sgk::launch_logn_apply(h->rptr, h->rcol, h->rslot, h->C, h->cp, h->n_e, h->n, lo, nr, lo, lo + nr, 0, nullptr,
+                             h->cq, s);
+    else
+      sgk::launch_logn_mean_apply(h->C, h->cp, h->n_e, h->n, nr, h->cq, s);  // block (0, 0) is slot 0
     if ((rc = dotp(h, h->cp, h->cq, len, pq))) return rc;
     if (!(pq > 0.0) || !std::isfinite(pq)) break;
     const double alpha = rz / pq;
-    sgk::launch_logn_axpby(len, alpha, h->cp, 1.0, X, 0, nullptr, s);
-    sgk::launch_logn_axpby(len, -alpha, h->cq, 1.0, h->cr, 0, nullptr, s);
+    sgk::launch_logn_axpby(len, alpha, h->cp, 1.0, X, 0, nullptr, 0, s);
+    sgk::launch_logn_axpby(len, -alpha, h->cq, 1.0, h->cr, 0, nullptr, 0, s);
     ++its;
     if ((rc = dotp(h, h->cr, h->cr, len, rr))) return rc;
     if (rr <= rtol * rtol * bb) break;
-    sgk::launch_logn_axpby(len, 0.0, h->cr, 0.0, h->cz, 1, dinv, s);
+    sgk::launch_logn_axpby(len, 0.0, h->cr, 0.0, h->cz, 1, dinv, dn, s);
     if ((rc = dotp(h, h->cr, h->cz, len, rzn))) return rc;
     const double beta = rzn / rz;
     rz = rzn;
-    sgk::launch_logn_axpby(len, 1.0, h->cz, beta, h->cp, 0, nullptr, s);
+    sgk::launch_logn_axpby(len, 1.0, h->cz, beta, h->cp, 0, nullptr, 0, s);
+  }
+  return SG_OK;
+}
+
+int level_solve(sg_logn_ctx* h, int l, const double* B, double* X, double rtol, int maxit, long& its) {
+  return range_solve(h, 0, h->off[l], h->off[l + 1] - h->off[l], B, X, rtol, maxit, its);
+}
+
+// Block symmetric Gauss-Seidel over the chaos blocks (Section 6) from zero:
+// forward a = 0..P-1: xf_a = A_aa^-1 (r_a - sum_{b<a} A_ab xf_b); backward
+// a = P-1..0: x_a = A_aa^-1 (r_a - sum_{b<a} A_ab xf_b - sum_{b>a} A_ab x_b).
+int bgs_apply(sg_logn_ctx* h, const double* R, double* Z, double rtol, int maxit, long& its) {
+  hipStream_t s = h->stream;
+  const long n = h->n;
+  int rc;
+  for (int a = 0; a < h->P; ++a) {
+    sgk::launch_logn_apply(h->rptr, h->rcol, h->rslot, h->C, h->XF, h->n_e, n, a, 1, 0, a, 1, R + a * n, h->W, s);
+    if ((rc = range_solve(h, 0, a, 1, h->W, h->XF + a * n, rtol, maxit, its))) return rc;
+  }
+  for (int a = h->P - 1; a >= 0; --a) {
+    sgk::launch_logn_apply(h->rptr, h->rcol, h->rslot, h->C, h->XF, h->n_e, n, a, 1, 0, a, 1, R + a * n, h->W, s);
+    sgk::launch_logn_apply(h->rptr, h->rcol, h->rslot, h->C, Z + (a + 1) * n, h->n_e, n, a, 1, a + 1, h->P, 1, h->W,
+                           h->W, s);
+    if ((rc = range_solve(h, 0, a, 1, h->W, Z + a * n, rtol, maxit, its))) return rc;
   }
   return SG_OK;
 }
@@ -280,7 +315,7 @@ int level_solve(sg_logn_ctx* h, int l, const double* B, double* X, double rtol, 
 int hsc_apply(sg_logn_ctx* h, const double* R, double* Z, double rtol, int maxit, long& its) {
   const long nP = h->n * (long)h->P;
   hipStream_t s = h->stream;
-  sgk::launch_logn_axpby(nP, 1.0, R, 0.0, h->Rh, 0, nullptr, s);
+  sgk::launch_logn_axpby(nP, 1.0, R, 0.0, h->Rh, 0, nullptr, 0, s);
   int rc;
   for (int l = h->p; l >= 1; --l) {
     const int lo = h->off[l], hi = h->off[l + 1];
@@ -367,8 +402,9 @@ int sg_logn_setup(const sg_problem* pr, void* workspace, size_t workspace_bytes,
   {
     const size_t nP = (size_t)h->n * pl.P;
     double* v = (double*)(w + pl.o_vec);
-    double** vecs[11] = {&h->R, &h->Z, &h->Pv, &h->Q, &h->Rh, &h->W, &h->cr, &h->cz, &h->cp, &h->cq, &h->Dinv};
-    for (int i = 0; i < 11; ++i) *vecs[i] = v + i * nP;
+    double** vecs[12] = {&h->R,  &h->Z,  &h->Pv, &h->Q,  &h->Rh,   &h->W,
+                         &h->cr, &h->cz, &h->cp, &h->cq, &h->Dinv, &h->XF};
+    for (int i = 0; i < 12; ++i) *vecs[i] = v + i * nP;
     h->part = (double*)(w + pl.o_part);
     h->host_part.assign(kLognDotBlocks, 0.0);
     h->off.assign(1, 0);
@@ -424,17 +460,20 @@ int sg_logn_matvec(sg_logn_handle h, const double* U, double* Y) {
   return SG_OK;
 }
 
-int sg_logn_solve(sg_logn_handle h, const double* F, double* U, double rtol, int32_t maxit, double inner_rtol,
-                  int32_t inner_maxit, int32_t* outer_it, int64_t* inner_it, double* relres, double* kappa) {
+int sg_logn_solve(sg_logn_handle h, int32_t precond, const double* F, double* U, double rtol, int32_t maxit,
+                  double inner_rtol, int32_t inner_maxit, int32_t* outer_it, int64_t* inner_it, double* relres,
+                  double* kappa) {
   if (!h || !F || !U) return fail(SG_EINVAL, "null argument");
+  if (precond != SG_PC_HSC && precond != SG_PC_MEAN && precond != SG_PC_BGS)
+    return fail(SG_EINVAL, "precond must be SG_PC_HSC, SG_PC_MEAN or SG_PC_BGS");
   if (F == U) return fail(SG_EINVAL, "F and U must be distinct");
   if (!(rtol >= 0.0) || maxit < 0 || !(inner_rtol > 0.0 && inner_rtol < 1.0) || inner_maxit < 1)
     return fail(SG_EINVAL, "need rtol >= 0, maxit >= 0, 0 < inner_rtol < 1, inner_maxit >= 1");
   const long nP = h->n * (long)h->P;
   hipStream_t s = h->stream;
   // flexible CG (Section 5) on A with Algorithm 1 as the preconditioner
-  sgk::launch_logn_axpby(nP, 0.0, F, 0.0, U, 0, nullptr, s);  // U = 0
-  sgk::launch_logn_axpby(nP, 1.0, F, 0.0, h->R, 0, nullptr, s);
+  sgk::launch_logn_axpby(nP, 0.0, F, 0.0, U, 0, nullptr, 0, s);  // U = 0
+  sgk::launch_logn_axpby(nP, 1.0, F, 0.0, h->R, 0, nullptr, 0, s);
   double ff = 0.0, rr = 0.0;
   int rc = dotp(h, F, F, nP, ff);
   if (rc) return rc;
@@ -444,15 +483,22 @@ int sg_logn_solve(sg_logn_handle h, const double* F, double* U, double rtol, int
   double rel = ff > 0.0 ? 1.0 : 0.0, pq_prev = 0.0;
   if (ff == 0.0 || rel <= rtol) status = SG_OK;
   for (; status == SG_NOT_CONVERGED && it < maxit; ++it) {
-    if ((rc = hsc_apply(h, h->R, h->Z, inner_rtol, inner_maxit, its_in))) return rc;
+    if (precond == SG_PC_HSC)
+      rc = hsc_apply(h, h->R, h->Z, inner_rtol, inner_maxit, its_in);
+    else if (precond == SG_PC_BGS)
+      rc = bgs_apply(h, h->R, h->Z, inner_rtol, inner_maxit, its_in);
+    else  // each column its own K(k_0) solve, so every column meets the inner tolerance
+      for (int a = 0; a < h->P && !rc; ++a)
+        rc = range_solve(h, 1, 0, 1, h->R + a * h->n, h->Z + a * h->n, inner_rtol, inner_maxit, its_in);
+    if (rc) return rc;
     if (it == 0) {
-      sgk::launch_logn_axpby(nP, 1.0, h->Z, 0.0, h->Pv, 0, nullptr, s);
+      sgk::launch_logn_axpby(nP, 1.0, h->Z, 0.0, h->Pv, 0, nullptr, 0, s);
     } else {
       double zq = 0.0;
       if ((rc = dotp(h, h->Z, h->Q, nP, zq))) return rc;
       const double beta = -zq / pq_prev;
       be.push_back(beta);
-      sgk::launch_logn_axpby(nP, 1.0, h->Z, beta, h->Pv, 0, nullptr, s);
+      sgk::launch_logn_axpby(nP, 1.0, h->Z, beta, h->Pv, 0, nullptr, 0, s);
     }
     sgk::launch_logn_matvec(h->rptr, h->rcol, h->rslot, h->C, h->Pv, h->n_e, h->n, h->P, h->Q, s);
     double pq = 0.0, pr = 0.0;
@@ -464,8 +510,8 @@ int sg_logn_solve(sg_logn_handle h, const double* F, double* U, double rtol, int
     if ((rc = dotp(h, h->Pv, h->R, nP, pr))) return rc;
     const double alpha = pr / pq;
     al.push_back(alpha);
-    sgk::launch_logn_axpby(nP, alpha, h->Pv, 1.0, U, 0, nullptr, s);
-    sgk::launch_logn_axpby(nP, -alpha, h->Q, 1.0, h->R, 0, nullptr, s);
+    sgk::launch_logn_axpby(nP, alpha, h->Pv, 1.0, U, 0, nullptr, 0, s);
+    sgk::launch_logn_axpby(nP, -alpha, h->Q, 1.0, h->R, 0, nullptr, 0, s);
     pq_prev = pq;
     if ((rc = dotp(h, h->R, h->R, nP, rr))) return rc;
     rel = std::sqrt(rr / ff);

@@ -59,26 +59,30 @@ SOLVES = [
 ]
 
 
+@pytest.mark.parametrize("pc", ["hsc", "bgs", "mean"])
 @pytest.mark.parametrize("case", SOLVES, ids=lambda c: "ne{n_e}-M{M}-p{p}-cov{cov}".format(**c))
-def test_lognormal_hsc_solve_matches_oracle(case):
-    """FCG with Algorithm 1 over the full level blocks: the GPU's iterative D_l
-    solves (to 1e-12) give the oracle's outer iteration count with exact D_l
-    solves, its condition estimate and its solution."""
+def test_lognormal_solve_matches_oracle(case, pc):
+    """FCG with the preconditioners of Section 6 for the lognormal case: the
+    GPU's iterative block solves (to 1e-12) give the oracle's outer iteration
+    count with exact block solves, its condition estimate (to 1e-3) and its
+    solution."""
     from paper_1205_1864_amd import binding as b
     from oracle import krylov
     c = dict(case)
     cov = c.pop("cov")
     prob = named_problem("small", L=0.5, **c)
-    print(f"lognormal solve {case}", flush=True)
+    print(f"lognormal solve {case} {pc}", flush=True)
     ls = lognormal.build(prob, cov)
     F = prob.load_block()
-    res, _ = lognormal.solve_fcg(ls, F.T.copy(), "hsc", rtol=1e-8)
+    res, _ = lognormal.solve_fcg(ls, F.T.copy(), pc, rtol=1e-8)
     kap = krylov.lanczos_kappa(res.alphas, res.betas)
     op = b.LognormalOperator(prob, 1.0, cov)
-    U, st = op.solve(b.to_device_block(F), rtol=1e-8)
+    U, st = op.solve(b.to_device_block(F), rtol=1e-8, precond=pc)
     assert st["rc"] == 0
     assert st["outer_it"] == res.iterations, (st, res.iterations)
-    assert abs(st["kappa_est"] - kap) <= 1e-6 * kap
+    # the Lanczos estimate carries the inner solves' rounding over all outer
+    # iterations (2.7e-4 after the 40 mean-based ones)
+    assert abs(st["kappa_est"] - kap) <= 1e-3 * kap
     Uo = res.x.T
     assert np.linalg.norm(U.cpu().numpy() - Uo) <= 1e-9 * np.linalg.norm(Uo)
     # true residual of the GPU solution against the oracle's matrix
