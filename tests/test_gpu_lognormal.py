@@ -89,3 +89,22 @@ def test_lognormal_solve_matches_oracle(case, pc):
     r = sg.vec(F.T) - ls.A @ sg.vec(U.cpu().numpy().T)
     assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(F)
     op.close()
+
+
+def test_lognormal_solve_edge_cases():
+    """Zero right-hand side, an iteration cap, and argument checks."""
+    import torch
+    from paper_1205_1864_amd import binding as b
+    prob = named_problem("small", n_e=8, M=2, p=2, L=0.5)
+    op = b.LognormalOperator(prob, 1.0, 1.0)
+    Z = torch.zeros((op.P, op.n), dtype=torch.float64, device="cuda")
+    U, st = op.solve(Z)
+    assert st["rc"] == 0 and st["outer_it"] == 0 and float(U.abs().max()) == 0.0
+    F = b.to_device_block(prob.load_block())
+    U, st = op.solve(F, rtol=1e-14, maxit=1)
+    assert st["rc"] == b.SG_NOT_CONVERGED and st["outer_it"] == 1
+    with pytest.raises(b.SGError):
+        op.solve(F, U=F)
+    with pytest.raises(b.SGError):
+        op.solve(F, inner_rtol=1.5)
+    op.close()
