@@ -56,6 +56,7 @@ SOLVES = [
     dict(n_e=10, M=4, p=2, cov=0.5),
     dict(n_e=10, M=1, p=4, cov=1.0),   # Table 6, N = 1
     dict(n_e=12, M=3, p=1, cov=1.5),
+    dict(n_e=10, M=4, p=4, cov=1.0),   # the setting of Tables 6-9 (N = 4, degree 4, CoV 100 %)
 ]
 
 
