@@ -210,6 +210,48 @@ __global__ void __launch_bounds__(256) logn_axpby_kernel(long len, double a, con
   }
 }
 
+// One fused level-solve CG update over a grid-stride range (the grid and
+// stride of logn_dot_kernel, so the partial sums have the same order):
+//   x += alpha p;  r -= alpha q;  z = d r (d of period dn);
+//   partials of r.r into part[0..] and of r.z into part[gridDim.x..].
+__global__ void __launch_bounds__(256) logn_cg_update_kernel(long len, double alpha, const double* __restrict__ p,
+                                                             const double* __restrict__ q, double* __restrict__ x,
+                                                             double* __restrict__ r, const double* __restrict__ d,
+                                                             long dn, double* __restrict__ z,
+                                                             double* __restrict__ part) {
+  __shared__ double sm[2][256];
+  double a1 = 0.0, a2 = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x) {
+    x[i] = alpha * p[i] + 1.0 * x[i];
+    const double ri = -alpha * q[i] + 1.0 * r[i];
+    r[i] = ri;
+    const double zi = d[i % dn] * ri;
+    z[i] = zi;
+    a1 += ri * ri;
+    a2 += ri * zi;
+  }
+  sm[0][threadIdx.x] = a1;
+  sm[1][threadIdx.x] = a2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + w];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sm[0][0];
+    part[gridDim.x + blockIdx.x] = sm[1][0];
+  }
+}
+
+void launch_logn_cg_update(long len, double alpha, const double* p, const double* q, double* x, double* r,
+                           const double* d, long dn, double* z, double* part, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(logn_cg_update_kernel, dim3(nblocks), dim3(256), 0, s, len, alpha, p, q, x, r, d,
+                     dn > 0 ? dn : len, z, part);
+}
+
 void launch_logn_apply(const int* rptr, const int* rcol, const int* rslot, const double* C, const double* X,
                        int n_e, long n, int row0, int nrows, int col0, int col1, int mode, const double* R, double* Y,
                        hipStream_t s) {

@@ -33,6 +33,8 @@ void launch_logn_dot(const double* x, const double* y, long len, double* part, i
 void launch_logn_axpby(long len, double a, const double* x, double b, double* y, int mode, const double* d,
                        long dn, hipStream_t s);
 void launch_logn_mean_apply(const double* c, const double* X, int n_e, long n, int ncols, double* Y, hipStream_t s);
+void launch_logn_cg_update(long len, double alpha, const double* p, const double* q, double* x, double* r,
+                           const double* d, long dn, double* z, double* part, int nblocks, hipStream_t s);
 }  // namespace sgk
 
 namespace sgh {
@@ -223,7 +225,7 @@ int plan(const sg_problem* pr, Plan& pl) {
   pl.o_rslot = take(tot, sizeof(int) * std::max<size_t>(1, pl.rslot.size()));
   const size_t nP = (size_t)(pr->n_e - 1) * (pr->n_e - 1) * pl.P;
   pl.o_vec = take(tot, sizeof(double) * nP * 12);
-  pl.o_part = take(tot, sizeof(double) * kLognDotBlocks);
+  pl.o_part = take(tot, sizeof(double) * 2 * kLognDotBlocks);  // two partial sets
   pl.total = tot;
   return SG_OK;
 }
@@ -235,7 +237,7 @@ int dotp(sg_logn_ctx* h, const double* x, const double* y, long len, double& out
                         h->stream));
   SG_HIP(hipStreamSynchronize(h->stream));
   double s = 0.0;
-  for (double v : h->host_part) s += v;
+  for (int i = 0; i < kLognDotBlocks; ++i) s += h->host_part[i];
   out = s;
   return SG_OK;
 }
@@ -271,13 +273,17 @@ int range_solve(sg_logn_ctx* h, int kind, int lo, int nr, const double* B, doubl
     if ((rc = dotp(h, h->cp, h->cq, len, pq))) return rc;
     if (!(pq > 0.0) || !std::isfinite(pq)) break;
     const double alpha = rz / pq;
-    sgk::launch_logn_axpby(len, alpha, h->cp, 1.0, X, 0, nullptr, 0, s);
-    sgk::launch_logn_axpby(len, -alpha, h->cq, 1.0, h->cr, 0, nullptr, 0, s);
+    // x += alpha p, r -= alpha q, z = D^-1 r and the partials of r.r and r.z in one pass
+    sgk::launch_logn_cg_update(len, alpha, h->cp, h->cq, X, h->cr, dinv, dn, h->cz, h->part, kLognDotBlocks, s);
+    SG_HIP(hipMemcpyAsync(h->host_part.data(), h->part, sizeof(double) * 2 * kLognDotBlocks, hipMemcpyDeviceToHost,
+                          s));
+    SG_HIP(hipStreamSynchronize(s));
+    rr = 0.0;
+    rzn = 0.0;
+    for (int i = 0; i < kLognDotBlocks; ++i) rr += h->host_part[i];
+    for (int i = 0; i < kLognDotBlocks; ++i) rzn += h->host_part[kLognDotBlocks + i];
     ++its;
-    if ((rc = dotp(h, h->cr, h->cr, len, rr))) return rc;
     if (rr <= rtol * rtol * bb) break;
-    sgk::launch_logn_axpby(len, 0.0, h->cr, 0.0, h->cz, 1, dinv, dn, s);
-    if ((rc = dotp(h, h->cr, h->cz, len, rzn))) return rc;
     const double beta = rzn / rz;
     rz = rzn;
     sgk::launch_logn_axpby(len, 1.0, h->cz, beta, h->cp, 0, nullptr, 0, s);
@@ -406,7 +412,7 @@ int sg_logn_setup(const sg_problem* pr, void* workspace, size_t workspace_bytes,
                          &h->cr, &h->cz, &h->cp, &h->cq, &h->Dinv, &h->XF};
     for (int i = 0; i < 12; ++i) *vecs[i] = v + i * nP;
     h->part = (double*)(w + pl.o_part);
-    h->host_part.assign(kLognDotBlocks, 0.0);
+    h->host_part.assign(2 * kLognDotBlocks, 0.0);
     h->off.assign(1, 0);
     for (int d = 0; d <= pr->p; ++d) {
       int cnt = 0;
