@@ -73,7 +73,7 @@ typedef struct sg_ctx* sg_handle;
  *   SG_FAMILY_HERMITE   standard Gaussian variables, normalised Hermite
  *                       polynomials He_a / sqrt(a!);
  *   SG_FAMILY_LEGENDRE  variables uniform on [-1, 1], normalised Legendre
- *                       polynomials sqrt(2a + 1) P_a (the examples of Section 7).
+ *                       polynomials sqrt(2a + 1) P_a (the examples of Section 6).
  * Requires n_e >= 3, M >= 0, p >= 0, P <= 2^20. */
 enum { SG_FAMILY_HERMITE = 0, SG_FAMILY_LEGENDRE = 1 };
 
@@ -189,6 +189,7 @@ int sg_apply_bgs(sg_handle h, const double* R, double* Z);
  * be NULL) receives the iteration count of each column. */
 int sg_inner_solve(sg_handle h, const double* B, double* X, int32_t ncols, int32_t* iters);
 
+
 /* Coupling products of Algorithm 1 on level l (1 <= l <= p), FP64:
  *   dir = 0 (pre-correction):  R[:, level l-1] -= (B_l Y)[:, level l-1]
  *            with Y read from the level-l columns of Y;
@@ -302,8 +303,7 @@ int sg_batch_solve(sg_batch b, const double* const* F, double* const* U, double 
 /* Release the batch and its per-problem handles (the workspace stays with the caller). */
 void sg_batch_destroy(sg_batch b);
 
-/* Thread-local description of the last failure (never NULL). */
-/* Lognormal coefficient (Section 7, second set of experiments; Tables 6-9).
+/* Lognormal coefficient (Section 6, second set of experiments; Tables 6-9).
  * The coefficient is k(x, xi) = exp(g(x, xi)) with the Gaussian field
  * g = mu_g + sum_k g_k(x) xi_k, g_k(e) = sigma_g s[k] phi[k][e], expanded in
  * the normalised Hermite chaos to total degree 2p; the solution has degree p.
@@ -357,6 +357,7 @@ int sg_logn_solve(sg_logn_handle h, int32_t precond, const double* F, double* U,
                   double* kappa);
 void sg_logn_destroy(sg_logn_handle h);
 
+/* Thread-local description of the last failure (never NULL). */
 const char* sg_last_error(void);
 
 #ifdef __cplusplus

@@ -27,7 +27,7 @@ schur    A-priori reduction to the Schur complement of the top degree
 lognormal
          Lognormal coefficient expanded in Hermite chaos to twice the
          solution's degree, with the full-level-block preconditioners
-         (Section 7, Tables 6-9). The GPU library does not implement it.
+         (Section 6, Tables 6-9).
 
 Every function cites the passage it follows. Readings of points where the
 paper is silent are stated where they are used.

@@ -45,7 +45,7 @@ def bgs_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = Non
     ``row_products(a, X, cols)`` (default: from the K_k and G_k) and
     ``solve_block(a, v)`` (default: ``solve_mean``, for A_aa = K_0) serve
     systems whose diagonal blocks are not K_0 (the lognormal coefficient of
-    Section 7).
+    Section 6).
     """
     rowp = row_products if row_products is not None else (lambda a, X, cols: _row_products(sys, a, X, cols))
 

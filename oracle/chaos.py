@@ -8,7 +8,7 @@ degree at most p in M independent variables; there are
   Hermite polynomials ``He_a(xi) / sqrt(a!)``;
 * ``"legendre"``: variables uniform on ``[-1, 1]`` and the normalised
   Legendre polynomials ``sqrt(2a + 1) P_a(xi)`` (Section 2; the examples of
-  Section 7). Reading: the support [-1, 1] is the one under which the
+  Section 6). Reading: the support [-1, 1] is the one under which the
   paper's remark that ellipticity is no longer guaranteed above a
   coefficient of variation of 55 % holds for its setup, and it reproduces
   the iteration counts and condition estimates of its Tables 1-4 (a test

@@ -96,7 +96,7 @@ def hsc_apply(sys: SGSystem, R: np.ndarray, solve_mean, counters: Counters = Non
     cols)`` (default: ``level_block``) gives the sub-block operators B_l, C_l,
     and ``solve_level(l, V)`` (default: ``solve_mean(V)``) applies D_l^-1, for
     systems whose D_l are not block diagonal (the lognormal coefficient of
-    Section 7).
+    Section 6).
     """
     blk = blocks if blocks is not None else (lambda rows, cols: level_block(sys, rows, cols))
 

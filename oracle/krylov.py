@@ -18,6 +18,7 @@
 from __future__ import annotations
 
 import math
+import time
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -158,6 +159,7 @@ class FCGResult:
     converged: bool
     relres: float
     history: list = field(default_factory=list)
+    history_time: list = field(default_factory=list)  # time.perf_counter() at each history entry
     alphas: list = field(default_factory=list)
     betas: list = field(default_factory=list)
     breakdown: bool = False
@@ -184,6 +186,7 @@ def fcg(apply_A, apply_M, F: np.ndarray, rtol: float, maxit: int, X0=None) -> FC
         return res
     relres = math.sqrt(dot(R, R)) / fn
     res.history.append(relres)
+    res.history_time.append(time.perf_counter())
     if relres <= rtol:
         res.converged = True
         res.relres = relres
@@ -211,6 +214,7 @@ def fcg(apply_A, apply_M, F: np.ndarray, rtol: float, maxit: int, X0=None) -> FC
         res.iterations = it + 1
         relres = math.sqrt(dot(R, R)) / fn
         res.history.append(relres)
+        res.history_time.append(time.perf_counter())
         if relres <= rtol:
             res.converged = True
             break

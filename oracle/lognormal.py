@@ -1,8 +1,9 @@
-"""Lognormal diffusion coefficient in the Hermite chaos (Section 7, second set
+"""Lognormal diffusion coefficient in the Hermite chaos (Section 6, second set
 of experiments; Tables 6-9).
 
 Test infrastructure: a plain CPU reference written from the definitions, not
-part of the product path; the GPU library does not implement this case.
+part of the product path; the GPU library's lognormal calls are checked
+against it.
 
 The coefficient is ``k(x, xi) = exp(g(x, xi))`` with a Gaussian field
 ``g = mu_g + sum_k g_k(x) xi_k`` (KL terms ``g_k = sigma_g sqrt(lambda_k)

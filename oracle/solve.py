@@ -50,3 +50,22 @@ def solve_fcg(sys: SGSystem, F: np.ndarray, precond: str = "hsc", inner="exact",
 def true_relres(sys: SGSystem, F: np.ndarray, U: np.ndarray) -> float:
     R = F - matvec(sys, U)
     return float(np.linalg.norm(R) / np.linalg.norm(F))
+
+
+def error_bound_constant(problem) -> float:
+    """c with ||u - u*||_2 <= c ||f - A u||_2 for the exact solution u* of A u* = f.
+
+    A = sum_e C_e (x) K^e (eq. (global-matrix) regrouped by element) with the
+    element chaos matrices C_e = theta0 I + sum_k a_k(e) G_k and the
+    unit-coefficient element stiffness K^e >= 0. If C_e >= m I for every e
+    (m = ``problem.coefficient_margin()``), then A >= m (I (x) K_Lap), so
+    ||A^-1||_2 <= 1 / (m lambda_1) with lambda_1 = (8 - 4c - 4c^2) / 3,
+    c = cos(pi / n_e), the smallest eigenvalue of the unit-coefficient Q1
+    Laplacian on the interior nodes (sine mode (1, 1)). Infinite if m <= 0.
+    """
+    m = float(problem.coefficient_margin())
+    if not m > 0.0:
+        return float("inf")
+    c = np.cos(np.pi / problem.n_e)
+    lam1 = (8.0 - 4.0 * c - 4.0 * c * c) / 3.0
+    return 1.0 / (m * lam1)

@@ -47,7 +47,14 @@ class SGQoI(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gQ):
         spec = ctx.spec
-        _, grad, st = ctx.solver.sg_adjoint_grad(ctx.U, spec.w_mean, spec.w_var, rtol=spec.rtol, maxit=spec.maxit)
+        if ctx.solver is None:
+            raise RuntimeError("SGQoI: backward ran already; the handle is released after the first backward")
+        try:
+            _, grad, st = ctx.solver.sg_adjoint_grad(ctx.U, spec.w_mean, spec.w_var, rtol=spec.rtol,
+                                                     maxit=spec.maxit)
+        finally:
+            ctx.solver.close()
+            ctx.solver = None
         spec.last_stats["adjoint"] = st
         g = torch.from_numpy(grad).to(ctx.theta_device, ctx.theta_dtype)
         return gQ * g, None

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass
 
 import numpy as np
@@ -127,6 +128,18 @@ def last_error() -> str:
     return lib.sg_last_error().decode()
 
 
+def _release(obj):
+    """Finaliser of the handle classes. Callers close handles explicitly; a
+    handle still open when the interpreter shuts down is left to the process
+    exit, so that no HIP call runs after the runtime's own teardown began."""
+    if sys.is_finalizing():
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
+
+
 @dataclass
 class Options:
     inner_precision: int = 64
@@ -207,6 +220,12 @@ class SGSolver:
             raise ValueError(f"expected a contiguous float64 ({ncols}, {self.n}) tensor on {self.device}")
         return t
 
+    def _vec(self, t: torch.Tensor) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device or \
+                not t.is_contiguous() or tuple(t.shape) != (self.n,):
+            raise ValueError(f"expected a contiguous float64 ({self.n},) tensor on {self.device}")
+        return t
+
     def empty(self, ncols=None) -> torch.Tensor:
         return torch.empty((self.P if ncols is None else ncols, self.n), dtype=torch.float64, device=self.device)
 
@@ -269,7 +288,8 @@ class SGSolver:
 
     def sg_qoi(self, U, w_mean, w_var):
         Q = ctypes.c_double()
-        _check(lib.sg_qoi(self.handle, _dptr(self._block(U)), _dptr(w_mean), _dptr(w_var), ctypes.byref(Q)))
+        _check(lib.sg_qoi(self.handle, _dptr(self._block(U)), _dptr(self._vec(w_mean)), _dptr(self._vec(w_var)),
+                          ctypes.byref(Q)))
         return Q.value
 
     def sg_adjoint_grad(self, U, w_mean, w_var, rtol=1e-8, maxit=200, Lambda=None):
@@ -277,7 +297,8 @@ class SGSolver:
         grad = (ctypes.c_double * (1 + self.M))()
         st = SgStats()
         lam_ptr = _dptr(self._block(Lambda)) if Lambda is not None else None
-        rc = _check(lib.sg_adjoint_grad(self.handle, _dptr(self._block(U)), _dptr(w_mean), _dptr(w_var),
+        rc = _check(lib.sg_adjoint_grad(self.handle, _dptr(self._block(U)), _dptr(self._vec(w_mean)),
+                                        _dptr(self._vec(w_var)),
                                         float(rtol), int(maxit), ctypes.byref(Q), grad, lam_ptr,
                                         ctypes.byref(st)), allow_positive=True)
         d = st.as_dict()
@@ -295,10 +316,7 @@ class SGSolver:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)
 
 
 class SGBatch:
@@ -368,10 +386,7 @@ class SGBatch:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)
 
 
 class LognormalOperator:
@@ -396,12 +411,15 @@ class LognormalOperator:
         _check(lib.sg_logn_sizes(self.handle, ctypes.byref(n), ctypes.byref(P), ctypes.byref(nb_)))
         self.n, self.P, self.nblocks = int(n.value), int(P.value), int(nb_.value)
 
-    def matvec(self, U: torch.Tensor, Y: torch.Tensor = None) -> torch.Tensor:
-        if U.dtype != torch.float64 or not U.is_contiguous() or tuple(U.shape) != (self.P, self.n) \
-                or U.device != self.device:
+    def _block(self, t: torch.Tensor) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() or \
+                tuple(t.shape) != (self.P, self.n) or t.device != self.device:
             raise ValueError(f"expected a contiguous float64 ({self.P}, {self.n}) tensor on {self.device}")
-        Y = torch.empty_like(U) if Y is None else Y
-        _check(lib.sg_logn_matvec(self.handle, _dptr(U), _dptr(Y)))
+        return t
+
+    def matvec(self, U: torch.Tensor, Y: torch.Tensor = None) -> torch.Tensor:
+        Y = torch.empty_like(self._block(U)) if Y is None else Y
+        _check(lib.sg_logn_matvec(self.handle, _dptr(self._block(U)), _dptr(self._block(Y))))
         return Y
 
     def solve(self, F: torch.Tensor, U: torch.Tensor = None, rtol=1e-8, maxit=500, inner_rtol=1e-12,
@@ -409,10 +427,10 @@ class LognormalOperator:
         """A U = F by flexible CG; precond "hsc" (Algorithm 1 over the full level
         blocks), "bgs" or "mean"."""
         pc = {"hsc": SG_PC_HSC, "bgs": SG_PC_BGS, "mean": SG_PC_MEAN}[precond]
-        self.matvec(F, torch.empty_like(F))  # shape and device check
-        U = torch.empty_like(F) if U is None else U
+        U = torch.empty_like(self._block(F)) if U is None else U
         it, iin, rel, kap = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-        rc = _check(lib.sg_logn_solve(self.handle, pc, _dptr(F), _dptr(U), float(rtol), int(maxit), float(inner_rtol),
+        rc = _check(lib.sg_logn_solve(self.handle, pc, _dptr(self._block(F)), _dptr(self._block(U)), float(rtol),
+                                      int(maxit), float(inner_rtol),
                                       int(inner_maxit), ctypes.byref(it), ctypes.byref(iin), ctypes.byref(rel),
                                       ctypes.byref(kap)), allow_positive=True)
         return U, {"rc": rc, "outer_it": int(it.value), "inner_it": int(iin.value), "relres": float(rel.value),
@@ -424,10 +442,7 @@ class LognormalOperator:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)
 
 
 def to_device_block(A: np.ndarray, device="cuda") -> torch.Tensor:

@@ -8,6 +8,7 @@ the device code (-packed-fp32-ops).
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -42,9 +43,36 @@ def _compile(src: str) -> str:
     return obj
 
 
+SRCHASH = LIB + ".srchash"
+
+
+def _sources():
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+
+
+def source_hash() -> str:
+    """SHA-256 over the library's sources, the public header and the compile flags."""
+    h = hashlib.sha256()
+    for path in _sources() + [os.path.join(ROOT, "include", "sg.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(COMMON + [ARCH]).encode())
+    return h.hexdigest()
+
+
+def built_from_current_sources() -> bool:
+    """True if the library exists and was built from the sources as they are now."""
+    if not os.path.exists(LIB) or not os.path.exists(SRCHASH):
+        return False
+    with open(SRCHASH) as f:
+        return f.read().strip() == source_hash()
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+    digest = source_hash()
+    srcs = [p for p in _sources() if p.endswith((".hip", ".cpp"))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
@@ -53,6 +81,8 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    with open(SRCHASH, "w") as f:
+        f.write(digest + "\n")
     if verbose:
         print(f"built {LIB}")
     return LIB

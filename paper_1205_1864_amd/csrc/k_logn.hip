@@ -1,4 +1,4 @@
-// Kernels of the lognormal-coefficient SG operator (Section 7, second set of
+// Kernels of the lognormal-coefficient SG operator (Section 6, second set of
 // experiments): the coefficient is expanded in Hermite chaos to twice the
 // solution's degree, so every chaos block couples and the operator is
 //   Y_a = sum_b K(c_ab) U_b,  c_ab(e) = sum_i E[psi_i psi_a psi_b] k_i(e),

@@ -27,11 +27,13 @@
 // from per-tile partials in a fixed order, identically in every block, so all
 // owners of a column take the same decisions.
 //
-// Two tile shapes. Banded tiles (the default) are tsx x 32 nodes with tsx
-// chosen so that the tile plus its halo is at most 64 columns wide: each lane
-// owns one column of the region and each wave one band of its rows, the
-// horizontal stencil neighbours come from the neighbouring lanes (DPP) and the
-// vertical ones from a sliding window of rows, so a node update reads LDS once.
+// Two tile shapes. Banded tiles (the default) are tsx x R nodes (R = 64, 128
+// or 256 rows by precision and launch size) with tsx chosen so that the tile
+// plus its halo is at most 64 columns wide: each lane owns one column of the
+// region and each wave one band of its rows, the horizontal stencil
+// neighbours come from the neighbouring lanes (DPP) and the vertical ones from
+// the wave's own registers (rows just outside its band through a small LDS
+// exchange).
 // Square 16 x 16 tiles serve Chebyshev degrees whose halo is too wide for that.
 //
 // The same kernel runs a ragged set of columns from several problems (grids

@@ -378,13 +378,28 @@ int choose_tile(const sg_ctx* h, int degree) {
   return degree <= sgk::kBandMaxDegree ? 32 : 16;
 }
 
+int flush_inner(sg_ctx* h);
+
+// State vectors and scratch of the inner solver: by default the handle's part
+// of the workspace; sg_inner_solve_static passes its own.
+struct PcgBufs {
+  void *R0, *R1, *P0, *P1, *Q, *Z;
+  sgk::PcgScratch sc;
+  int maxcols;
+};
+
+PcgBufs handle_bufs(const sg_ctx* h) {
+  return {h->pR0, h->pR1, h->pP0, h->pP1, h->pQ, h->pZ, h->pcgsc, h->pcg_maxcols};
+}
+
 // Batched inner PCG on `ncols` contiguous columns (inner precision T). warm:
 // start from the contents of X where the options allow it, else from zero.
 template <typename T>
 int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::vector<int>* iters_out = nullptr,
-            bool warm = false) {
+            bool warm = false, const PcgBufs* bufs = nullptr) {
   if (ncols <= 0) return SG_OK;
-  if (ncols > h->pcg_maxcols) return fail(SG_EINVAL, "too many columns for the inner solver");
+  const PcgBufs buf = bufs ? *bufs : handle_bufs(h);
+  if (ncols > buf.maxcols) return fail(SG_EINVAL, "too many columns for the inner solver");
   sgk::PcgArgs<T> a{};
   const int degree = effective_degree(h);
   const int tile = choose_tile(h, degree);
@@ -393,13 +408,13 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.ncols = ncols;
   a.B = B;
   a.X = X;
-  a.R0 = (T*)h->pR0;
-  a.R1 = (T*)h->pR1;
-  a.P0 = (T*)h->pP0;
-  a.P1 = (T*)h->pP1;
-  a.Q = (T*)h->pQ;
-  a.Z = (T*)h->pZ;
-  a.sc = h->pcgsc;
+  a.R0 = (T*)buf.R0;
+  a.R1 = (T*)buf.R1;
+  a.P0 = (T*)buf.P0;
+  a.P1 = (T*)buf.P1;
+  a.Q = (T*)buf.Q;
+  a.Z = (T*)buf.Z;
+  a.sc = buf.sc;
   a.rows = sgk::band_rows(sizeof(T) == 4 ? 32 : 64, degree);
   sgk::pcg_tiling(h->nx, degree, tile, a.rows, a.ntx, a.ntiles);
   if (tile != 16 && h->opts.tile == 0 && (long)ncols * a.ntiles < h->num_cu) {
@@ -412,35 +427,74 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;
   a.warm = warm && h->opts.warm_start && tile != 16;
   fill_pcg_consts<T>(h, a);
-  SG_HIP(hipEventRecord(h->ev0, h->stream));
-  SG_HIP(sgk::launch_pcg<T>(a, tile, h->pcg_max_blocks, h->stream));
-  SG_HIP(hipEventRecord(h->ev1, h->stream));
-  std::vector<int> it(ncols);
-  int wait_status = 0;
-  SG_HIP(hipMemcpyAsync(it.data(), h->pcgsc.iters, sizeof(int) * ncols, hipMemcpyDeviceToHost, h->stream));
-  SG_HIP(hipMemcpyAsync(&wait_status, h->pcgsc.status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  SG_HIP(hipStreamSynchronize(h->stream));
-  if (wait_status != 0) return fail(SG_EDEVICE, "inner solver: a bounded column wait expired");
-  float ms = 0.f;
-  SG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-  h->inner_ms_acc += ms;
-  h->inner_launch_acc += 1;
-  int mx = 0;
-  for (int v : it) {
-    h->inner_it_acc += v;
-    // phase A reads z, p and x and writes p and x (and q with 16 x 16 tiles); phase B
-    // reads r and p (q) and writes r and z; the start reads b and writes z and x (warm:
-    // reads b and x, writes z and r); a column that stops after at least one iteration
-    // reads x and p and writes x once more
-    const double per_it = tile == 16 ? 10.0 : 9.0;
-    h->inner_bytes_acc += (per_it * v + (v > 0 ? 6.0 : 3.0) + (a.warm ? 1.0 : 0.0)) * (double)h->n * sizeof(T);
-    mx = std::max(mx, v);
+  // room for this launch's read-back, else settle the earlier ones first
+  if ((int)h->pending.size() >= sg_ctx::kMaxPending || (int)h->pending.size() * 2 + 2 > h->nev ||
+      h->iters_used + ncols > h->iters_cap) {
+    int rc = flush_inner(h);
+    if (rc) return rc;
   }
-  if (level_for_stats >= 0 && level_for_stats < sgk::kMaxLevels)
-    h->inner_it_max[level_for_stats] = std::max(h->inner_it_max[level_for_stats], mx);
-  if (iters_out) *iters_out = it;
+  const int k = (int)h->pending.size();
+  hipEvent_t e0 = h->evpool[2 * k], e1 = h->evpool[2 * k + 1];
+  SG_HIP(hipEventRecord(e0, h->stream));
+  SG_HIP(sgk::launch_pcg<T>(a, tile, h->pcg_max_blocks, h->stream));
+  SG_HIP(hipEventRecord(e1, h->stream));
+  sg_ctx::PendingLaunch L{ncols, level_for_stats, tile, a.warm, (int)sizeof(T), h->iters_used};
+  SG_HIP(hipMemcpyAsync(h->iters_host + L.slot, buf.sc.iters, sizeof(int) * ncols, hipMemcpyDeviceToHost,
+                        h->stream));
+  SG_HIP(hipMemcpyAsync(h->status_host + k, buf.sc.status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  h->pending.push_back(L);
+  h->iters_used += ncols;
+  if (h->defer > 0 && !iters_out) return SG_OK;
+  if (iters_out) iters_out->assign(ncols, 0);
+  const long slot = L.slot;
+  int rc = flush_inner(h);
+  if (rc) return rc;
+  if (iters_out)
+    for (int c = 0; c < ncols; ++c) (*iters_out)[c] = h->iters_host[slot + c];
   return SG_OK;
 }
+
+// Settles every inner launch still pending: waits for the stream, then checks
+// each launch's status word and adds its iteration counts, algorithmic bytes
+// and event time to the handle's statistics.
+int flush_inner(sg_ctx* h) {
+  if (h->pending.empty()) return SG_OK;
+  SG_HIP(hipStreamSynchronize(h->stream));
+  int bad = 0;
+  for (size_t k = 0; k < h->pending.size(); ++k) {
+    const sg_ctx::PendingLaunch& L = h->pending[k];
+    if (h->status_host[k] != 0) bad = 1;
+    float ms = 0.f;
+    SG_HIP(hipEventElapsedTime(&ms, h->evpool[2 * k], h->evpool[2 * k + 1]));
+    h->inner_ms_acc += ms;
+    h->inner_launch_acc += 1;
+    int mx = 0;
+    for (int c = 0; c < L.ncols; ++c) {
+      const int v = h->iters_host[L.slot + c];
+      h->inner_it_acc += v;
+      // phase A reads z, p and x and writes p and x (and q with 16 x 16 tiles); phase B
+      // reads r and p (q) and writes r and z; the start reads b and writes z and x (warm:
+      // reads b and x, writes z and r); a column that stops after at least one iteration
+      // reads x and p and writes x once more
+      const double per_it = L.tile == 16 ? 10.0 : 9.0;
+      h->inner_bytes_acc += (per_it * v + (v > 0 ? 6.0 : 3.0) + (L.warm ? 1.0 : 0.0)) * (double)h->n * L.wsize;
+      mx = std::max(mx, v);
+    }
+    if (L.level >= 0 && L.level < sgk::kMaxLevels) h->inner_it_max[L.level] = std::max(h->inner_it_max[L.level], mx);
+  }
+  h->pending.clear();
+  h->iters_used = 0;
+  if (bad) return fail(SG_EDEVICE, "inner solver: a bounded column wait expired");
+  return SG_OK;
+}
+
+// Defers the read-back of inner launches for the lifetime of the guard (one
+// preconditioner action); the caller settles them with flush_inner.
+struct DeferInner {
+  sg_ctx* h;
+  explicit DeferInner(sg_ctx* hh) : h(hh) { ++h->defer; }
+  ~DeferInner() { --h->defer; }
+};
 
 template <typename T>
 sgk::ChaosLists<T> lists(const sg_ctx* h);
@@ -564,7 +618,7 @@ int bgs_core(sg_ctx* h, T* rw, T* Zb, long* nbmv, long* nbs) {
   return SG_OK;
 }
 
-int apply_bgs(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
+int apply_bgs_body(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
   const long N = h->n * (long)h->P;
   if (h->opts.inner_precision == 64) {
     double* rw = (double*)h->rw;
@@ -580,7 +634,7 @@ int apply_bgs(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
   return SG_OK;
 }
 
-int apply_hsc(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
+int apply_hsc_body(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
   const long N = h->n * (long)h->P;
   if (h->opts.inner_precision == 64) {
     double* rw = (double*)h->rw;
@@ -596,7 +650,7 @@ int apply_hsc(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
   return SG_OK;
 }
 
-int apply_mean(sg_ctx* h, const double* R, double* Z, long* nbs) {
+int apply_mean_body(sg_ctx* h, const double* R, double* Z, long* nbs) {
   const long N = h->n * (long)h->P;
   *nbs += h->P;
   if (h->opts.inner_precision == 64) return run_pcg<double>(h, R, Z, h->P, -1);
@@ -607,6 +661,37 @@ int apply_mean(sg_ctx* h, const double* R, double* Z, long* nbs) {
   if (rc) return rc;
   sgk::launch_copy_f2d(Z, zw, N, h->stream);
   return SG_OK;
+}
+
+// One preconditioner action with the inner launches' read-back settled once at its end.
+int apply_bgs(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
+  int rc;
+  {
+    DeferInner d(h);
+    rc = apply_bgs_body(h, R, Z, nbmv, nbs);
+  }
+  const int rf = flush_inner(h);
+  return rc ? rc : rf;
+}
+
+int apply_hsc(sg_ctx* h, const double* R, double* Z, long* nbmv, long* nbs) {
+  int rc;
+  {
+    DeferInner d(h);
+    rc = apply_hsc_body(h, R, Z, nbmv, nbs);
+  }
+  const int rf = flush_inner(h);
+  return rc ? rc : rf;
+}
+
+int apply_mean(sg_ctx* h, const double* R, double* Z, long* nbs) {
+  int rc;
+  {
+    DeferInner d(h);
+    rc = apply_mean_body(h, R, Z, nbs);
+  }
+  const int rf = flush_inner(h);
+  return rc ? rc : rf;
 }
 
 void matvec(sg_ctx* h, const double* U, double* Y) {
@@ -901,7 +986,13 @@ int solve_reduced(sg_ctx* h, const double* F, double* U, double rtol, int maxit,
       return run_pcg<double>(h, r, z, lo, -1);
     }
     sgk::launch_copy_d2d((double*)h->rw, r, Nr, h->stream);
-    return hsc_core<double>(h, (double*)h->rw, z, &nbmv, &nbs, p - 1);
+    int rc2;
+    {
+      DeferInner d(h);
+      rc2 = hsc_core<double>(h, (double*)h->rw, z, &nbmv, &nbs, p - 1);
+    }
+    const int rf = flush_inner(h);
+    return rc2 ? rc2 : rf;
   };
   FcgRun run;
   rc = fcg_core(h, Nr, g, U, rtol, maxit, 0, op, prec, run);
@@ -1027,6 +1118,16 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
   R.pcg_max_blocks = h->pcg_max_blocks;
   if (out) *out = R;
   return SG_OK;
+}
+
+// Frees a handle's host-side resources: events, pinned read-back buffers, the context.
+void release_ctx(sg_ctx* h) {
+  (void)hipEventDestroy(h->ev0);
+  (void)hipEventDestroy(h->ev1);
+  for (int i = 0; i < h->nev; ++i) (void)hipEventDestroy(h->evpool[i]);
+  if (h->iters_host) (void)hipHostFree(h->iters_host);
+  if (h->status_host) (void)hipHostFree(h->status_host);
+  delete h;
 }
 
 }  // namespace sgh
@@ -1292,6 +1393,20 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
     delete h;
     return fail(SG_EDEVICE, "event creation failed");
   }
+  // read-back of deferred inner launches: an action launches at most 2p + 1
+  // solves over at most 2P + 1 columns (more only force an earlier flush)
+  h->iters_cap = 2L * P + 64;
+  bool ok = hipHostMalloc((void**)&h->iters_host, sizeof(int) * h->iters_cap, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&h->status_host, sizeof(int) * sg_ctx::kMaxPending, hipHostMallocDefault) ==
+                hipSuccess;
+  for (int i = 0; ok && i < 2 * sg_ctx::kMaxPending; ++i) {
+    ok = hipEventCreate(&h->evpool[i]) == hipSuccess;
+    if (ok) h->nev = i + 1;
+  }
+  if (!ok) {
+    release_ctx(h);
+    return fail(SG_EDEVICE, "event or pinned buffer creation failed");
+  }
   *out = h;
   return SG_OK;
 }
@@ -1465,9 +1580,8 @@ int sg_autotune(sg_handle h, int32_t flags, sg_tune_report* report) {
 
 void sg_destroy(sg_handle h) {
   if (!h) return;
-  (void)hipEventDestroy(h->ev0);
-  (void)hipEventDestroy(h->ev1);
-  delete h;
+  (void)hipStreamSynchronize(h->stream);
+  release_ctx(h);
 }
 
 const char* sg_last_error(void) { return g_last_error.c_str(); }

@@ -381,4 +381,20 @@ struct sg_ctx {
   long inner_launch_acc;
   hipEvent_t ev0, ev1;
   int inner_it_max[sgk::kMaxLevels];
+  // Inner launches whose iteration counts, status word and timing are read
+  // back later (once per preconditioner action instead of once per launch):
+  // each has a pair of events from evpool and a slice of the pinned host
+  // buffer iters_host (its column counts), status_host[i] its status word.
+  struct PendingLaunch {
+    int ncols, level, tile, warm, wsize;
+    long slot;
+  };
+  static constexpr int kMaxPending = 64;
+  std::vector<PendingLaunch> pending;
+  hipEvent_t evpool[2 * kMaxPending];
+  int nev = 0;             // events created in evpool
+  int* iters_host = nullptr;   // pinned, iters_cap ints
+  int* status_host = nullptr;  // pinned, kMaxPending ints
+  long iters_cap = 0, iters_used = 0;
+  int defer = 0;           // > 0: run_pcg leaves the read-back to flush_inner
 };

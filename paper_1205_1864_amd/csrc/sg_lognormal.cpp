@@ -1,4 +1,4 @@
-// Lognormal-coefficient SG operator (Section 7, second set of experiments;
+// Lognormal-coefficient SG operator (Section 6, second set of experiments;
 // Tables 6-9): k(x, xi) = exp(g(x, xi)) with the Gaussian field
 // g = mu_g + sum_k g_k(x) xi_k, expanded in the normalised Hermite chaos to
 // total degree 2p. The global matrix A = sum_i G_i (x) K_i,
@@ -245,7 +245,7 @@ int dotp(sg_logn_ctx* h, const double* x, const double* y, long len, double& out
 // Block solve by Jacobi-preconditioned CG from X = 0 to ||r|| <= rtol ||B||
 // or maxit iterations, on the n x nr system of
 //   kind 0: the diagonal sub-block of A over chaos columns lo..lo+nr-1 (a
-//           level block D_l of Section 7, where the level blocks couple, or one
+//           level block D_l of Section 6, where the level blocks couple, or one
 //           block A_aa);
 //   kind 1: I (x) K(k_0) over nr columns (the mean-based preconditioner).
 // B and X: n x nr device blocks.
@@ -364,7 +364,7 @@ int sg_logn_setup(const sg_problem* pr, void* workspace, size_t workspace_bytes,
   if (rc) return rc;
   if (workspace_bytes < pl.total) return fail(SG_ENOMEM, "workspace too small");
   const int n_e = pr->n_e, M = pr->M, ne2 = n_e * n_e;
-  // Chaos coefficients of exp(g) (Section 7; the Gaussian field carries the KL
+  // Chaos coefficients of exp(g) (Section 6; the Gaussian field carries the KL
   // data and the lognormal mean and CoV fix its mean and variance):
   // k_i(e) = exp(mu_g + sum_k g_k(e)^2 / 2) prod_k g_k(e)^{i_k} / sqrt(i_k!).
   const double sg2 = std::log(1.0 + pr->sigma * pr->sigma);
@@ -483,6 +483,7 @@ int sg_logn_solve(sg_logn_handle h, int32_t precond, const double* F, double* U,
   double ff = 0.0, rr = 0.0;
   int rc = dotp(h, F, F, nP, ff);
   if (rc) return rc;
+  if (!std::isfinite(ff)) return fail(SG_EINVAL, "right-hand side is not finite");
   std::vector<double> al, be;
   long its_in = 0;
   int it = 0, status = SG_NOT_CONVERGED;
@@ -521,6 +522,11 @@ int sg_logn_solve(sg_logn_handle h, int32_t precond, const double* F, double* U,
     pq_prev = pq;
     if ((rc = dotp(h, h->R, h->R, nP, rr))) return rc;
     rel = std::sqrt(rr / ff);
+    if (!std::isfinite(rel)) {
+      status = SG_BREAKDOWN;
+      ++it;
+      break;
+    }
     if (rel <= rtol) {
       status = SG_OK;
       ++it;

@@ -210,7 +210,7 @@ _NAMED = {
     "scale": dict(n_e=256, M=10, p=3, sigma=0.25, L=0.3),
     "grad": dict(n_e=512, M=8, p=3, sigma=0.2, L=0.4),
     "grad_small": dict(n_e=32, M=8, p=3, sigma=0.2, L=0.4),
-    # the examples of Section 7: uniform variables with Legendre chaos on a
+    # the examples of Section 6: uniform variables with Legendre chaos on a
     # 10 x 10 mesh, mean 1, L = 0.5, CoV = sigma = 50 %, N = 4, degree 4
     "paper_legendre": dict(n_e=10, M=4, p=4, sigma=0.5, L=0.5, family="legendre"),
     # the 256^2 scale case with Legendre chaos
@@ -231,7 +231,7 @@ def batch_problems(seed: int = 0, count: int = 48, grids=(32, 64, 128, 256), max
     redrawn together until P <= max_P; then sigma ~ U[0.1, 0.3],
     L ~ U[0.2, 1.0] and a Gaussian bump (A ~ U[0.5, 2], w ~ U[0.05, 0.2],
     centre ~ U[0.2, 0.8]^2). sigma is redrawn while the coefficient margin is
-    not positive.
+    at most 0.05 (at most 100 draws, else ValueError).
     """
     rng = np.random.default_rng(seed)
     out = []
@@ -252,6 +252,8 @@ def batch_problems(seed: int = 0, count: int = 48, grids=(32, 64, 128, 256), max
                            s=np.sqrt(lam), phi=phi, f_nodal=nodal_rhs(n_e, bump), modes=modes)
             if prob.coefficient_margin() > 0.05:
                 break
+        else:
+            raise ValueError(f"batch problem {b}: no sigma draw out of 100 keeps the coefficient margin above 0.05")
         out.append(prob)
     return out
 

@@ -28,3 +28,18 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _release_gpu_handles(request):
+    """After each GPU test: release the library handles the test dropped (their
+    finalisers run now, while the runtime is up, not at interpreter exit) and
+    wait for the device."""
+    yield
+    if "gpu" not in request.keywords or not _gpu_available():
+        return
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()

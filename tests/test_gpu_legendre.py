@@ -1,4 +1,4 @@
-"""Legendre chaos (uniform variables on [-1, 1], the examples of Section 7)
+"""Legendre chaos (uniform variables on [-1, 1], the examples of Section 6)
 through the C-ABI against the CPU oracle."""
 
 import numpy as np
@@ -61,7 +61,7 @@ def test_preconditioner_tight_parity(which):
 
 @pytest.mark.parametrize("pc", ["mean", "bgs", "hsc"])
 def test_paper_example_solves(pc):
-    """The Section 7 example (10 x 10 mesh, N = 4, degree 4, CoV 50 %): with
+    """The Section 6 example (10 x 10 mesh, N = 4, degree 4, CoV 50 %): with
     (nearly) exact inner solves the GPU flexible CG takes the oracle's
     iterations, with the oracle's Lanczos condition estimate, and reaches the
     direct solution."""

@@ -1,5 +1,5 @@
 """Lognormal-coefficient SG operator (sg_logn_*) against the oracle's
-assembled block-dense matrix (Section 7, Tables 6-9 setting)."""
+assembled block-dense matrix (Section 6, Tables 6-9 setting)."""
 
 import numpy as np
 import pytest

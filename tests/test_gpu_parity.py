@@ -373,18 +373,31 @@ def test_autotune_keeps_parity(kw, prec):
 @pytest.mark.parametrize("prec", [64, 32])
 def test_solve_scale_benchmark_configuration(prec):
     """256^2, M = 10, p = 3, Hermite chaos, in the benchmark's launch configuration
-    (Chebyshev degree 16, autotuned schedules): the solve reaches 1e-8 and its true
-    residual on the oracle's operator agrees."""
+    (Chebyshev degree 16, autotuned schedules): the solve reaches 1e-8, its true
+    residual on the oracle's operator agrees, and the solution matches the
+    oracle's own solve (FCG with Algorithm 1 and exact LU inner solves, to 1e-10)
+    within the a-posteriori bound (||r_gpu|| + ||r_oracle||) ||A^-1||, with
+    ||A^-1|| bounded through the coefficient margin (oracle.solve.error_bound_constant)."""
+    from gpu_common import oracle_solution
     b = _b()
-    prob = named_problem("scale")
-    print(f"benchmark configuration solve 256^2 inner FP{prec}", flush=True)
+    print(f"benchmark configuration solve 256^2 inner FP{prec}: oracle reference", flush=True)
+    prob, s, F, Uo, ro = oracle_solution("scale")
+    print(f"benchmark configuration solve 256^2 inner FP{prec}: GPU solve", flush=True)
     solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=16, precond="hsc", inner_rtol=1e-4,
                                         inner_maxit=2000))
-    solver.sg_autotune(3)
-    F = prob.load_block()
-    U, st = solver.sg_solve(_dev(F), rtol=1e-8, maxit=100)
-    assert st["rc"] == 0 and st["true_relres"] <= 1.05e-8
-    s = sg.build_system(prob)
-    tr = solve.true_relres(s, F.T, U.cpu().numpy().T)
+    try:
+        solver.sg_autotune(3)
+        U, st = solver.sg_solve(_dev(F.T), rtol=1e-8, maxit=100)
+        assert st["rc"] == 0 and st["true_relres"] <= 1.05e-8
+        Ug = U.cpu().numpy().T
+    finally:
+        solver.close()
+    tr = solve.true_relres(s, F, Ug)
     assert tr <= 1.05e-8
     assert abs(st["true_relres"] - tr) <= 1e-3 * tr
+    fn = float(np.linalg.norm(F))
+    bound = (tr * fn + ro) * solve.error_bound_constant(prob) / float(np.linalg.norm(Uo))
+    err = float(np.linalg.norm(Ug - Uo) / np.linalg.norm(Uo))
+    print(f"FP{prec} inner: |u - u_oracle| / |u_oracle| = {err:.3e}, bound {bound:.3e}", flush=True)
+    assert bound < 1e-6
+    assert err <= bound

@@ -2,7 +2,7 @@
 
 The Hermite family is pinned in test_oracle_chaos.py and test_oracle_sg.py;
 here the same checks are made for the family of the paper's examples
-(Section 7), plus the paper's own iteration counts and condition estimates.
+(Section 6), plus the paper's own iteration counts and condition estimates.
 """
 
 import itertools

@@ -1,4 +1,4 @@
-"""Pins of the oracle's lognormal-coefficient system (Section 7, Tables 6-9).
+"""Pins of the oracle's lognormal-coefficient system (Section 6, Tables 6-9).
 
 Closed forms against library quadrature, the fast assembly against the
 Kronecker definition and against tensor quadrature of the expanded

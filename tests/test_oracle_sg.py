@@ -158,3 +158,16 @@ def test_fcg_equals_pcg_with_fixed_preconditioner():
         r2 = krylov.pcg(lambda U: sg.matvec(s, U), M, F, 1e-10, 100)
         assert abs(r1.iterations - r2.iterations) <= 1
         assert np.linalg.norm(r1.x - r2.x) <= 1e-8 * np.linalg.norm(r2.x)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(n_e=12, M=3, p=3, sigma=0.3),
+                                dict(n_e=10, M=4, p=4, family="legendre", sigma=0.5, L=0.5)])
+def test_error_bound_constant_bounds_the_inverse(kw):
+    """||A^-1||_2 <= c (the margin bound A >= m I (x) K_Lap) against the dense
+    spectrum, and c is not loose by more than a small factor."""
+    from oracle import solve
+    prob = named_problem("small", **kw)
+    s = sg.build_system(prob)
+    lmin = float(np.linalg.eigvalsh(sg.assemble(s).toarray()).min())
+    c = solve.error_bound_constant(prob)
+    assert 1.0 <= lmin * c <= 3.0
