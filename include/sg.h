@@ -189,6 +189,19 @@ int sg_apply_bgs(sg_handle h, const double* R, double* Z);
  * be NULL) receives the iteration count of each column. */
 int sg_inner_solve(sg_handle h, const double* B, double* X, int32_t ncols, int32_t* iters);
 
+/* sg_inner_solve without any device allocation, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid it): the inner solver's state vectors, the FP32
+ * copies of B and X (FP32 inner precision), the per-tile partial sums and the
+ * per-column counters live in a fixed 64 MiB device array of the library (one
+ * copy per device, held until the process ends) instead of the handle's
+ * workspace. Same arguments, results and synchronisation as sg_inner_solve.
+ * SG_ENOMEM if ncols columns need more than 64 MiB of that scratch (per column
+ * 6 n w bytes, 8 n w in FP32, plus partial sums; at n = 65025 in FP64 at most
+ * 20 columns). Every call on one device shares its array: calls that overlap
+ * on one device (other streams, other host threads) race and must be
+ * serialised by the caller. */
+int sg_inner_solve_static(sg_handle h, const double* B, double* X, int32_t ncols, int32_t* iters);
 
 /* Coupling products of Algorithm 1 on level l (1 <= l <= p), FP64:
  *   dir = 0 (pre-correction):  R[:, level l-1] -= (B_l Y)[:, level l-1]

@@ -78,6 +78,7 @@ def _load():
         "sg_apply_mean": [VP, VP, VP],
         "sg_apply_bgs": [VP, VP, VP],
         "sg_inner_solve": [VP, VP, VP, I32, P(I32)],
+        "sg_inner_solve_static": [VP, VP, VP, I32, P(I32)],
         "sg_coupling": [VP, I32, I32, VP, VP],
         "sg_solve": [VP, VP, VP, D, I32, I32, P(SgStats)],
         "sg_solve_reduced": [VP, VP, VP, D, I32, D, P(SgStats)],
@@ -261,6 +262,16 @@ class SGSolver:
         its = (ctypes.c_int32 * max(1, ncols))()
         _check(lib.sg_inner_solve(self.handle, _dptr(self._block(B, ncols)), _dptr(self._block(X, ncols)),
                                   ncols, its))
+        return X, np.array(its[:ncols])
+
+    def sg_inner_solve_static(self, B, X=None):
+        """sg_inner_solve with the solver's scratch in the library's static
+        device array (no workspace use beyond the handle's tables)."""
+        ncols = B.shape[0]
+        X = self.empty(ncols) if X is None else X
+        its = (ctypes.c_int32 * max(1, ncols))()
+        _check(lib.sg_inner_solve_static(self.handle, _dptr(self._block(B, ncols)), _dptr(self._block(X, ncols)),
+                                         ncols, its))
         return X, np.array(its[:ncols])
 
     def sg_coupling(self, level, direction, R, V):

@@ -1012,6 +1012,66 @@ int solve_reduced(sg_ctx* h, const double* F, double* U, double rtol, int maxit,
   return finish_stats(h, run, true_rel, nbmv, nbs, total, st);
 }
 
+// Bytes of scratch the inner solver needs for ncols columns outside the
+// handle's workspace: the inner-precision copies of B and X (FP32 only), the
+// six state vectors, the per-tile partials (sized for the finest tiling) and
+// the per-column counters; each piece 256-byte aligned.
+size_t inner_scratch_bytes(const sg_ctx* h, int ncols) {
+  const size_t w = h->opts.inner_precision == 32 ? 4 : 8;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t vec = al(w * (size_t)h->n * ncols);
+  const size_t ntiles = (size_t)((h->nx + 15) / 16) * ((h->nx + 15) / 16);
+  size_t total = 6 * vec;
+  if (w == 4) total += 2 * vec;
+  total += al(sizeof(double) * sgk::kPcgPartials * ncols * ntiles);
+  total += al(sizeof(unsigned) * ncols) + al(sizeof(int) * ncols) + al(sizeof(int));
+  return total;
+}
+
+// sg_inner_solve with every buffer beyond B and X inside `scratch` (device,
+// 256-byte aligned, at least inner_scratch_bytes(h, ncols) long).
+int inner_solve_in(sg_ctx* h, const double* B, double* X, int ncols, int32_t* iters, char* scratch) {
+  const size_t w = h->opts.inner_precision == 32 ? 4 : 8;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t vec = al(w * (size_t)h->n * ncols);
+  const size_t ntiles = (size_t)((h->nx + 15) / 16) * ((h->nx + 15) / 16);
+  char* p = scratch;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += al(bytes);
+    return q;
+  };
+  void* rw = w == 4 ? take(vec) : nullptr;
+  void* zw = w == 4 ? take(vec) : nullptr;
+  PcgBufs buf{};
+  buf.R0 = take(vec);
+  buf.R1 = take(vec);
+  buf.P0 = take(vec);
+  buf.P1 = take(vec);
+  buf.Q = take(vec);
+  buf.Z = take(vec);
+  buf.sc.part = (double*)take(sizeof(double) * sgk::kPcgPartials * ncols * ntiles);
+  buf.sc.arrivals = (unsigned*)take(sizeof(unsigned) * ncols);
+  buf.sc.iters = (int*)take(sizeof(int) * ncols);
+  buf.sc.status = (int*)take(sizeof(int));
+  buf.maxcols = ncols;
+  std::vector<int> it;
+  const long N = h->n * (long)ncols;
+  int rc;
+  if (w == 8) {
+    rc = run_pcg<double>(h, B, X, ncols, -1, &it, false, &buf);
+  } else {
+    sgk::launch_copy_d2f((float*)rw, B, N, h->stream);
+    rc = run_pcg<float>(h, (const float*)rw, (float*)zw, ncols, -1, &it, false, &buf);
+    if (!rc) sgk::launch_copy_f2d(X, (const float*)zw, N, h->stream);
+  }
+  if (rc) return rc;
+  SG_HIP(hipStreamSynchronize(h->stream));
+  if (iters)
+    for (int c = 0; c < ncols; ++c) iters[c] = it[c];
+  return SG_OK;
+}
+
 // Schedule autotuner (sg_autotune).
 int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
   sg_tune_report R{};
@@ -1407,6 +1467,9 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
     release_ctx(h);
     return fail(SG_EDEVICE, "event or pinned buffer creation failed");
   }
+  // this device's static scratch (used only by sg_inner_solve_static); a
+  // failure here is reported by that call, which retries the lookup
+  if (static_scratch_address(&h->static_scratch) != SG_OK) h->static_scratch = nullptr;
   *out = h;
   return SG_OK;
 }

@@ -37,4 +37,14 @@ int choose_tile(const sg_ctx* h, int degree);
 int dots(sg_ctx* h, int nd, const double* a0, const double* b0, const double* a1 = nullptr,
          const double* b1 = nullptr, const double* a2 = nullptr, const double* b2 = nullptr);
 
+// Scratch of the inner solver outside the workspace (sg_inner_solve_static):
+// bytes needed for ncols columns, and the solve with every buffer beyond B and
+// X inside `scratch` (device, 256-byte aligned, at least that long).
+size_t inner_scratch_bytes(const sg_ctx* h, int ncols);
+int inner_solve_in(sg_ctx* h, const double* B, double* X, int ncols, int32_t* iters, char* scratch);
+// Device address of this device's copy of the library's static scratch array
+// (resolved once per device, with that device current), and its size.
+int static_scratch_address(void** out);
+size_t static_scratch_bytes();
+
 }  // namespace sgh

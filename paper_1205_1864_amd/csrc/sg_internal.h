@@ -397,4 +397,5 @@ struct sg_ctx {
   int* status_host = nullptr;  // pinned, kMaxPending ints
   long iters_cap = 0, iters_used = 0;
   int defer = 0;           // > 0: run_pcg leaves the read-back to flush_inner
+  void* static_scratch = nullptr;  // this device's static scratch array (sg_inner_solve_static)
 };
