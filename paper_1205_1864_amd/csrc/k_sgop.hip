@@ -634,6 +634,229 @@ __global__ void __launch_bounds__(512) sgop_march_kernel(const SgOpArgs<T> A, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// Piece kernel. The node grid is cut into pieces of one wavefront of node
+// columns by TY node rows: lane 0 and lane W + 1 hold the halo columns of a
+// piece, lanes 1..W its W output columns. A block is one wave and marches one
+// piece upwards for one row group (the groups of the y-marching kernel), with
+// the same corner sums and element matrix as march_body, but without any
+// barrier: horizontal neighbours come from DPP lane shifts inside the wave,
+// and the halo lanes absorb what the shifts bring in at the ends. Blocks are
+// pinned to XCDs (hardware block b runs on XCD b mod 8); XCD x works through a
+// contiguous band of pieces, every row group of a piece before the next
+// piece, so the input columns of a piece come from HBM about once and are
+// then served to the other row groups from that XCD's L2.
+//
+// Values outside the grid are zero (Dirichlet nodes, and loads of off-grid
+// lanes are replaced by zero), so elements that do not exist contribute
+// nothing to an output node; their coefficient loads are clamped into the
+// array (finite values multiplied by zero).
+// ---------------------------------------------------------------------------
+template <typename T, int NK, int RG, bool LK>
+__device__ __forceinline__ void piece_body(const SgOpArgs<T>& A, const StripTables<T>& tab, const MarchJob& job,
+                                           int g, int x0, int ys, int ye, int W) {
+  const int lane = threadIdx.x & 63;
+  const int ne = A.n_e, nx = A.nx, M = tab.M;
+  const long n = A.n;
+  const long ne2 = (long)ne * ne;
+  const int x = x0 + lane;                          // node column of the lane; its element spans x .. x + 1
+  const bool xin = x >= 1 && x <= nx;               // interior node column
+  const bool xout = xin && lane >= 1 && lane <= W;  // output column of this piece
+  const int xe = x <= ne - 1 ? x : ne - 1;          // element column clamped into the array
+  const T scale = A.sgn / T(6);
+  const T* __restrict__ in = A.in;
+  const T* __restrict__ acoef = A.a;
+  const T diag = A.diag;
+  const bool has_diag = diag != T(0);
+
+  const int gbeg = ld_uniform(job.gptr, g);
+  const int cnt = ld_uniform(job.gptr, g + 1) - gbeg;
+  int rows[RG];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) rows[j] = j < cnt ? ld_uniform(job.grows, gbeg + j) : -1;
+  int ks[NK];
+#pragma unroll
+  for (int s = 0; s < NK; ++s) ks[s] = LK ? ld_uniform(job.lk, g * kMarchNS + s) : s;
+  // neighbour columns and weights of the group's rows (uniform); a missing
+  // neighbour has column -1 and is not loaded
+  int cl[RG][NK], cu[RG][NK];
+  T wl[RG][NK], wu[RG][NK];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    const int row = rows[j];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      int lo = -1, up = -1;
+      T gl = T(0), gu = T(0);
+      if (row >= 0) {
+        if constexpr (LK) {
+          lo = ld_uniform(job.lcol, (g * kMarchRGL + j) * kMarchNS + s);
+          if (lo >= 0) gl = T(ld_uniform(job.lw, (g * kMarchRGL + j) * kMarchNS + s));
+        } else {
+          if (A.use_lower) {
+            lo = ld_uniform(tab.lo, row * M + s);
+            if (lo >= 0) gl = ld_uniform(tab.glo, row * M + s);
+          }
+          if (A.use_upper) {
+            up = ld_uniform(tab.up, row * M + s);
+            if (up >= 0) gu = ld_uniform(tab.gup, row * M + s);
+          }
+        }
+      }
+      cl[j][s] = lo;
+      cu[j][s] = up;
+      wl[j][s] = gl;
+      wu[j][s] = gu;
+    }
+  }
+
+  T ac[NK], acp[NK];
+#pragma unroll
+  for (int s = 0; s < NK; ++s) ac[s] = acp[s] = T(0);
+  T Bp[RG], BRp[RG], carry[RG];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) Bp[j] = BRp[j] = carry[j] = T(0);
+
+  for (int gy = ys - 1; gy <= ye; ++gy) {
+    // ---- loads: coefficients of element row gy (clamped), node values of node row gy
+    const int ey = gy < 0 ? 0 : (gy > ne - 1 ? ne - 1 : gy);
+    const long abase = (long)ey * ne + xe;
+    T an[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) an[s] = ks[s] >= 0 ? acoef[(long)ks[s] * ne2 + abase] : T(0);
+    const bool nin = xin && gy >= 1 && gy <= nx;
+    const long nid = nin ? (long)(gy - 1) * nx + (x - 1) : 0;
+    T ud[RG], ul[RG][NK], uu[RG][NK];
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      const int row = rows[j];
+      ud[j] = T(0);
+      if (has_diag && row >= 0) ud[j] = in[(long)row * n + nid];
+#pragma unroll
+      for (int s = 0; s < NK; ++s) {
+        ul[j][s] = T(0);
+        uu[j][s] = T(0);
+        if (row >= 0) {
+          if (cl[j][s] >= 0) ul[j][s] = in[(long)cl[j][s] * n + nid];
+          if (!LK && cu[j][s] >= 0) uu[j][s] = in[(long)cu[j][s] * n + nid];
+        }
+      }
+    }
+    if (!nin) {
+#pragma unroll
+      for (int j = 0; j < RG; ++j) {
+        ud[j] = T(0);
+#pragma unroll
+        for (int s = 0; s < NK; ++s) ul[j][s] = uu[j][s] = T(0);
+      }
+    }
+    // an at the element to the left (lane 0 is a halo column: its value is unused)
+    T anp[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) anp[s] = from_prev(an[s]);
+    const int orow = gy - 1;  // node row completed at this step
+    const bool wr = xout && orow >= ys && orow < ye;
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      const int row = rows[j];
+      if (row < 0) continue;
+      // corner sums at node (x, gy): T / Rt with the element row below (ac, acp),
+      // B / Rb with the element row above (an, anp); the diagonal term first
+      T t = diag * ud[j];
+      T rt = t, b = t, rb = t;
+#pragma unroll
+      for (int s = 0; s < NK; ++s) {
+        T w;
+        if constexpr (LK) {
+          w = wl[j][s] * ul[j][s];
+        } else {
+          w = wl[j][s] * ul[j][s] + wu[j][s] * uu[j][s];
+        }
+        t += ac[s] * w;
+        rt += acp[s] * w;
+        b += an[s] * w;
+        rb += anp[s] * w;
+      }
+      // element x of element row gy - 1: corners BL, BR (node row gy - 1), TR, TL (node row gy)
+      const T BL = Bp[j], BR = BRp[j], TR = from_next(rt), TL = t;
+      const T S = (BL + BR) + (TR + TL);
+      const T oBL = T(5) * BL - S - TR;
+      const T oBR = T(5) * BR - S - TL;
+      const T oTR = T(5) * TR - S - BL;
+      const T oTL = T(5) * TL - S - BR;
+      const T pend = oBL + carry[j] + from_prev(oBR);  // node row gy - 1, complete
+      if (wr) {
+        const long idx = (long)row * n + (long)(orow - 1) * nx + (x - 1);
+        T v = scale * pend;
+        if (A.rsrc) v += A.rcoef * A.rsrc[idx];
+        A.out[idx] = v;
+      }
+      carry[j] = oTL + from_prev(oTR);  // node row gy, from element row gy - 1
+      Bp[j] = b;
+      BRp[j] = from_next(rb);
+    }
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      ac[s] = an[s];
+      acp[s] = anp[s];
+    }
+  }
+}
+
+template <typename T, int MT>
+__global__ void __launch_bounds__(64) sgop_piece_kernel(const SgOpArgs<T> A, const StripTables<T> tab,
+                                                         const MarchJob job, const PieceGeom pg) {
+  if (A.active && ld_uniform(A.active, 0) == 0) return;
+  const int xcd = blockIdx.x % 8;
+  const int slot = blockIdx.x / 8;
+  const int nslots = ((int)gridDim.x - xcd + 7) / 8;  // blocks on this XCD
+  const long npieces = (long)pg.nyseg * pg.nstrips;
+  const long p0 = npieces * xcd / 8, p1 = npieces * (xcd + 1) / 8;
+  const long ntasks = (p1 - p0) * job.ngroups;
+  for (long t = slot; t < ntasks; t += nslots) {
+    const long p = p0 + t / job.ngroups;
+    const int g = (int)(t % job.ngroups);
+    const int yseg = (int)(p / pg.nstrips), strip = (int)(p % pg.nstrips);
+    const int x0 = strip * pg.W;
+    const int ys = 1 + yseg * pg.TY;
+    const int ye = min(A.nx + 1, ys + pg.TY);
+    if (ld_uniform(job.gkind, g) == 0) {
+      if constexpr (MT > 0) piece_body<T, MT, kMarchRGU, false>(A, tab, job, g, x0, ys, ye, pg.W);
+    } else {
+      piece_body<T, kMarchNS, kMarchRGL, true>(A, tab, job, g, x0, ys, ye, pg.W);
+    }
+  }
+}
+
+template <typename T, int MT>
+void launch_piece(const SgOpArgs<T>& A, const StripTables<T>& tab, const MarchJob& job, const PieceGeom& pg,
+                  hipStream_t s) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sgop_piece_kernel<T, MT>, 64, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  int dev = 0, ncu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const long ntasks = (long)pg.nyseg * pg.nstrips * job.ngroups;
+  long grid = (long)per_cu * ncu;
+  if (pg.max_waves_per_cu > 0 && pg.max_waves_per_cu < per_cu) grid = (long)pg.max_waves_per_cu * ncu;
+  if (grid > ntasks + 7) grid = (ntasks + 7) / 8 * 8;
+  grid = (grid + 7) / 8 * 8;
+  hipLaunchKernelGGL((sgop_piece_kernel<T, MT>), dim3((unsigned)grid), dim3(64), 0, s, A, tab, job, pg);
+}
+
+template <typename T, int MT>
+bool dispatch_piece(const SgOpArgs<T>& A, const StripTables<T>& tab, const MarchJob& job, const PieceGeom& pg,
+                    hipStream_t s) {
+  if (tab.M == MT) {
+    launch_piece<T, MT>(A, tab, job, pg, s);
+    return true;
+  }
+  if constexpr (MT > 0) return dispatch_piece<T, MT - 1>(A, tab, job, pg, s);
+  return false;
+}
+
 template <typename T, int MT>
 void launch_march(const SgOpArgs<T>& A, const StripTables<T>& tab, const MarchJob& job, hipStream_t s) {
   const int nblocks = job.ngroups * job.nseg;
@@ -717,6 +940,9 @@ int march_blocks_per_cu(int M, int block) { return march_occ<kStripMaxM>(M, bloc
 template <typename T>
 void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, const MarchJob* job, hipStream_t s) {
   if (args.nrows <= 0) return;
+  if (job != nullptr && job->piece.W > 0 && tab.lo != nullptr && job->ngroups > 0 &&
+      dispatch_piece<T, kStripMaxM>(args, tab, *job, job->piece, s))
+    return;
   const bool shape_ok = args.n_e % 64 == 0 && args.n_e >= 64 && args.n_e <= 512;
   if (job != nullptr && shape_ok && tab.lo != nullptr && job->ngroups > 0 &&
       dispatch_march<T, kStripMaxM>(args, tab, *job, s))

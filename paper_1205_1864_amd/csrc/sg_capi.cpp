@@ -274,8 +274,9 @@ void build_march_job(int M, int nx, const std::vector<int>& rows, bool lower, bo
 int build_march_jobs(sg_ctx* h, int seg_per_xcd) {
   h->march_ok = false;
   h->mjobs.clear();
-  if (!sgk::march_supported(h->n_e, h->M) || h->mv_variant != 2) return SG_OK;
-  const int occ = sgk::march_blocks_per_cu(h->M, h->n_e);
+  const bool piece = h->mv_variant == 3 && h->M <= sgk::kPieceMaxM;
+  if (!piece && (!sgk::march_supported(h->n_e, h->M) || h->mv_variant != 2)) return SG_OK;
+  const int occ = piece ? 1 : sgk::march_blocks_per_cu(h->M, h->n_e);
   if (occ <= 0) return SG_OK;
   const long cap = (long)occ * h->num_cu;
   const int M = h->M, P = h->P;
@@ -304,6 +305,15 @@ int build_march_jobs(sg_ctx* h, int seg_per_xcd) {
     mj.ngroups = (int)J.kind.size();
     mj.nseg = J.nseg;
     mj.seg_rows = J.seg_rows;
+    mj.piece = sgk::PieceGeom{0, 0, 0, 0, 0};
+    if (piece) {
+      // pieces of at most 62 output columns (one wavefront with its two halo
+      // columns), as many as the grid width needs and equally wide
+      const int nst = (h->nx + 61) / 62;
+      const int W = (h->nx + nst - 1) / nst;
+      const int TY = std::max(1, std::min(h->mv_piece_rows > 0 ? h->mv_piece_rows : 16, h->nx));
+      mj.piece = sgk::PieceGeom{W, (h->nx + W - 1) / W, TY, (h->nx + TY - 1) / TY, h->mv_piece_waves};
+    }
     h->mjobs.push_back(mj);
     const int base = (int)rws.size();
     for (int v : J.ptr) ptr.push_back(base + v);
@@ -322,7 +332,7 @@ int build_march_jobs(sg_ctx* h, int seg_per_xcd) {
   SG_HIP(hipMemcpyAsync(h->mj_lw_d, lw.data(), sizeof(double) * lw.size(), hipMemcpyHostToDevice, s));
   SG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
   h->march_ok = true;
-  h->mv_seg_per_xcd = seg_per_xcd;
+  h->mv_seg_per_xcd = piece ? 0 : seg_per_xcd;
   return SG_OK;
 }
 
@@ -1072,6 +1082,13 @@ int inner_solve_in(sg_ctx* h, const double* B, double* X, int ncols, int32_t* it
   return SG_OK;
 }
 
+// Schedule parameter of the SG operator variant in use (as in sg_tune_report).
+int mv_param(const sg_ctx* h) {
+  if (h->mv_variant == 3) return (h->mv_piece_rows > 0 ? h->mv_piece_rows : 16) * 100 + h->mv_piece_waves;
+  if (h->mv_variant == 2) return h->mv_seg_per_xcd;
+  return h->mv_blocks_per_band;
+}
+
 // Schedule autotuner (sg_autotune).
 int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
   sg_tune_report R{};
@@ -1099,6 +1116,10 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     };
     std::vector<Cand> cands;
     const bool wide = h->n_e % 64 == 0 && h->n_e >= 64 && h->n_e <= 512;
+    // piece kernel: node rows per piece (param = rows * 100 + wave cap per CU)
+    if (h->M <= sgk::kPieceMaxM)
+      for (int ty : {8, 16, 32})
+        if (ty <= std::max(8, h->nx)) cands.push_back({3, ty * 100});
     if (sgk::march_supported(h->n_e, h->M))
       for (int spx : {0, 1, 2, 4}) cands.push_back({2, spx});
     if (wide) {
@@ -1108,11 +1129,15 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     }
     auto apply = [&](const Cand& c) -> int {
       h->mv_variant = c.variant;
-      h->mv_blocks_per_band = c.variant == 2 ? 0 : c.param;
+      h->mv_blocks_per_band = c.variant == 0 || c.variant == 1 ? c.param : 0;
+      if (c.variant == 3) {
+        h->mv_piece_rows = c.param / 100;
+        h->mv_piece_waves = c.param % 100;
+      }
       return build_march_jobs(h, c.variant == 2 ? c.param : 0);
     };
     double best = 1e300;
-    Cand pick{h->mv_variant, h->mv_variant == 2 ? h->mv_seg_per_xcd : h->mv_blocks_per_band};
+    Cand pick{h->mv_variant, mv_param(h)};
     for (const Cand& c : cands) {
       int rc = apply(c);
       if (rc) return rc;
@@ -1132,7 +1157,7 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     R.mv_ms = cands.empty() ? 0.0 : best;
   }
   R.mv_variant = h->mv_variant;
-  R.mv_param = h->mv_variant == 2 ? h->mv_seg_per_xcd : h->mv_blocks_per_band;
+  R.mv_param = mv_param(h);
   const int degree = effective_degree(h);
   if (flags & 2) {
     const int lev = h->p;
@@ -1237,8 +1262,9 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   cheb_interval(h->n_e, h->lmin, h->lmax);
   h->mv_blocks_per_band = 0;
   if (const char* env = std::getenv("SGPC_MV_BLOCKS_PER_BAND")) h->mv_blocks_per_band = std::atoi(env);
-  h->mv_variant = 2;
+  h->mv_variant = pr->M <= sgk::kPieceMaxM ? 3 : 2;
   if (const char* env = std::getenv("SGPC_MV_VARIANT")) h->mv_variant = std::atoi(env);
+  if (const char* env = std::getenv("SGPC_MV_PIECE_ROWS")) h->mv_piece_rows = std::atoi(env);
   h->pcg_max_blocks = 0;
   if (const char* env = std::getenv("SGPC_PCG_MAX_BLOCKS")) h->pcg_max_blocks = std::atoi(env);
   int dev = 0;

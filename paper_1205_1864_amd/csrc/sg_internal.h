@@ -123,6 +123,18 @@ struct StripTables {
 constexpr int kMarchRGU = 2;
 constexpr int kMarchRGL = 6;
 constexpr int kMarchNS = 4;
+// Spatial pieces of the piece kernel: W interior node columns per piece (one
+// wavefront holds W + 2 columns with the halo), nstrips = ceil(nx / W) pieces
+// across, TY node rows per piece, nyseg = ceil(nx / TY) pieces up. W = 0: the
+// piece kernel is not used. max_waves_per_cu caps the resident waves (0: as
+// many as fit).
+struct PieceGeom {
+  int W;
+  int nstrips;
+  int TY;
+  int nyseg;
+  int max_waves_per_cu;
+};
 struct MarchJob {
   const int* gptr;
   const int* grows;
@@ -133,10 +145,14 @@ struct MarchJob {
   int ngroups;
   int nseg;
   int seg_rows;
+  PieceGeom piece;
 };
 
 template <typename T>
 void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, const MarchJob* job, hipStream_t s);
+
+// Largest number of KL terms served by the piece kernel (dense [P][M] tables).
+constexpr int kPieceMaxM = 12;
 
 // Resident blocks per CU of the y-marching kernel for this M and block size (0 if unsupported).
 int march_blocks_per_cu(int M, int block);
@@ -341,6 +357,8 @@ struct sg_ctx {
   int pcg_max_blocks;
   bool march_ok;
   int mv_seg_per_xcd = 0;  // grid segments per XCD of the y-marching kernel (0 = automatic)
+  int mv_piece_rows = 0;   // node rows per piece of the piece kernel (0 = default 16)
+  int mv_piece_waves = 0;  // cap on resident waves per CU of the piece kernel (0 = as many as fit)
   std::vector<sgk::MarchJob> mjobs;
   std::vector<int> st_lo_h, st_up_h;  // host copies of the dense neighbour tables (row groups)
   std::vector<double> st_glo_h;
