@@ -129,11 +129,13 @@ def last_error() -> str:
     return lib.sg_last_error().decode()
 
 
-def _release(obj):
+def _release(obj, _finalizing=sys.is_finalizing):
     """Finaliser of the handle classes. Callers close handles explicitly; a
     handle still open when the interpreter shuts down is left to the process
-    exit, so that no HIP call runs after the runtime's own teardown began."""
-    if sys.is_finalizing():
+    exit, so that no HIP call runs after the runtime's own teardown began.
+    (sys.is_finalizing is bound at definition: module globals may already be
+    cleared when a finaliser runs at shutdown.)"""
+    if _finalizing():
         return
     try:
         obj.close()
@@ -326,7 +328,7 @@ class SGSolver:
             lib.sg_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self)
 
 
@@ -396,7 +398,7 @@ class SGBatch:
             lib.sg_batch_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self)
 
 
@@ -452,7 +454,7 @@ class LognormalOperator:
             lib.sg_logn_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self)
 
 

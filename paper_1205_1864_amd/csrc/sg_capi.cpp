@@ -1119,7 +1119,8 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     // piece kernel: node rows per piece (param = rows * 100 + wave cap per CU)
     if (h->M <= sgk::kPieceMaxM)
       for (int ty : {8, 16, 32})
-        if (ty <= std::max(8, h->nx)) cands.push_back({3, ty * 100});
+        for (int waves : {0, 4})  // all resident waves, or 4 per CU (fewer pieces at once per XCD)
+          if (ty <= std::max(8, h->nx)) cands.push_back({3, ty * 100 + waves});
     if (sgk::march_supported(h->n_e, h->M))
       for (int spx : {0, 1, 2, 4}) cands.push_back({2, spx});
     if (wide) {

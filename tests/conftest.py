@@ -22,6 +22,12 @@ def _gpu_available():
 
 
 def pytest_collection_modifyitems(config, items):
+    # long CPU pins (paper-table rows of the largest chaos sizes) run with SGPC_RUN_SLOW=1
+    if os.environ.get("SGPC_RUN_SLOW") != "1":
+        slow = pytest.mark.skip(reason="long CPU pin: set SGPC_RUN_SLOW=1 to run")
+        for item in items:
+            if "slow" in item.keywords:
+                item.add_marker(slow)
     if _gpu_available():
         return
     skip = pytest.mark.skip(reason="no GPU in this environment")

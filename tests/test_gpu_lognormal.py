@@ -65,8 +65,9 @@ SOLVES = [
 def test_lognormal_solve_matches_oracle(case, pc):
     """FCG with the preconditioners of Section 6 for the lognormal case: the
     GPU's iterative block solves (to 1e-12) give the oracle's outer iteration
-    count with exact block solves, its condition estimate (to 1e-3) and its
-    solution."""
+    count with exact block solves, its condition estimate (to 1e-6, or within
+    the estimate's own measured sensitivity to the inner solves' accuracy) and
+    its solution."""
     from paper_1205_1864_amd import binding as b
     from oracle import krylov
     c = dict(case)
@@ -77,13 +78,27 @@ def test_lognormal_solve_matches_oracle(case, pc):
     F = prob.load_block()
     res, _ = lognormal.solve_fcg(ls, F.T.copy(), pc, rtol=1e-8)
     kap = krylov.lanczos_kappa(res.alphas, res.betas)
+    # the estimate's own sensitivity: the oracle's solve with its preconditioner's
+    # output perturbed at the GPU inner solves' relative accuracy (1e-12)
+    pcs = lognormal.LognormalPreconditioners(ls)
+    base = {"mean": pcs.mean, "bgs": pcs.bgs, "hsc": pcs.hsc}[pc]
+    rng = np.random.default_rng(1)
+
+    def perturbed(R):
+        Z = base(R)
+        return Z + 1e-12 * np.linalg.norm(Z) / np.sqrt(Z.size) * rng.standard_normal(Z.shape)
+
+    rp = krylov.fcg(lambda U: sg.unvec(ls.A @ sg.vec(U), prob.n), perturbed, F.T.copy(), 1e-8, 500)
+    sens = abs(krylov.lanczos_kappa(rp.alphas, rp.betas) - kap) / kap
     op = b.LognormalOperator(prob, 1.0, cov)
     U, st = op.solve(b.to_device_block(F), rtol=1e-8, precond=pc)
     assert st["rc"] == 0
     assert st["outer_it"] == res.iterations, (st, res.iterations)
-    # the Lanczos estimate carries the inner solves' rounding over all outer
-    # iterations (2.7e-4 after the 40 mean-based ones)
-    assert abs(st["kappa_est"] - kap) <= 1e-3 * kap
+    # The Lanczos estimate agrees to 1e-6, or to four times its own sensitivity
+    # where that is larger: after the 40 mean-based iterations of the N = 1,
+    # degree 4 case a 1e-12 (even a 1e-16) relative perturbation of the
+    # preconditioner moves the oracle's own estimate by about 1e-4.
+    assert abs(st["kappa_est"] - kap) <= max(1e-6, 4.0 * sens) * kap, (st["kappa_est"], kap, sens)
     Uo = res.x.T
     assert np.linalg.norm(U.cpu().numpy() - Uo) <= 1e-9 * np.linalg.norm(Uo)
     # true residual of the GPU solution against the oracle's matrix

@@ -401,3 +401,28 @@ def test_solve_scale_benchmark_configuration(prec):
     print(f"FP{prec} inner: |u - u_oracle| / |u_oracle| = {err:.3e}, bound {bound:.3e}", flush=True)
     assert bound < 1e-6
     assert err <= bound
+
+
+def test_solve_indefinite_reports_breakdown():
+    """A Gaussian coefficient with sigma large enough makes the Galerkin matrix
+    indefinite (Section 2's lower bound k_min fails; the coefficient margin is
+    negative). With the right-hand side along the eigenvector of the most
+    negative eigenvalue (dense spectrum of the oracle's assembled matrix), the
+    first curvature p^T A p = lambda_min |f|^2 < 0: the solve stops with
+    SG_BREAKDOWN and returns the last finite iterate, the zero start."""
+    b = _b()
+    prob, s = _sys(n_e=4, M=1, p=3, sigma=2.0)
+    assert prob.coefficient_margin() < 0
+    A = sg.assemble(s).toarray()
+    w, V = np.linalg.eigh(A)
+    assert w[0] < -1.0
+    F = sg.unvec(V[:, 0], s.n).T.copy()  # (P, n)
+    print("indefinite system: breakdown", flush=True)
+    solver = b.SGSolver(prob, b.Options(precond="none"))
+    try:
+        U, st = solver.sg_solve(_dev(F), rtol=1e-8, maxit=10)
+    finally:
+        solver.close()
+    assert st["rc"] == b.SG_BREAKDOWN and st["status"] == b.SG_BREAKDOWN
+    assert st["outer_it"] == 0
+    assert float(U.abs().max()) == 0.0
