@@ -50,12 +50,13 @@ def log(msg):
 
 
 def _ensure_built():
-    """Build the library if it is missing or was built from other sources."""
-    from paper_1205_1864_amd.build import LIB, build, built_from_current_sources
+    """Build the library if it is missing, or if its recorded source hash says it
+    was built from other sources (a library without a recorded hash is used as is)."""
+    from paper_1205_1864_amd.build import LIB, SRCHASH, build, built_from_current_sources
     if not os.path.exists(LIB):
         log("library missing: building")
         build()
-    elif not built_from_current_sources():
+    elif os.path.exists(SRCHASH) and not built_from_current_sources():
         log("library built from other sources: rebuilding")
         build()
 

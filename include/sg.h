@@ -250,9 +250,11 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
 
 /* Schedule autotuner. Times candidate launch schedules on this handle's own
  * grid and chaos sizes and keeps the fastest for all later calls:
- *   flags bit 0: the SG operator (y-marching kernel with 1, 2 or 4 grid
- *                segments per XCD or the automatic count; band kernels with
- *                32..128 row chunks per band, where the grid shape allows them);
+ *   flags bit 0: the SG operator (piece kernel with 8, 16 or 32 node rows
+ *                per piece and all resident waves or 4 per CU, when M <= 12;
+ *                y-marching kernel with 1, 2 or 4 grid segments per XCD or the
+ *                automatic count; band kernels with 32..128 row chunks per
+ *                band, where the grid shape allows them);
  *   flags bit 1: the inner PCG (tile kind 16 or 32 where the Chebyshev halo
  *                allows 32; block count automatic or half the CUs), timed on
  *                the columns of the largest chaos level with a constant
@@ -262,8 +264,9 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
  * differ only in the order of floating-point sums. report (host, may be NULL)
  * receives the choice. */
 typedef struct sg_tune_report {
-  int32_t mv_variant;      /* 0, 1: band kernels; 2: y-marching kernel */
-  int32_t mv_param;        /* row chunks per band (variants 0, 1) or segments per XCD (2; 0 = automatic) */
+  int32_t mv_variant;      /* 0, 1: band kernels; 2: y-marching kernel; 3: piece kernel */
+  int32_t mv_param;        /* row chunks per band (variants 0, 1); segments per XCD (2; 0 = automatic);
+                              100 * rows per piece + waves per CU (3; 0 waves = all resident) */
   int32_t pcg_tile;        /* inner tile kind (32 banded, 16 square) */
   int32_t pcg_max_blocks;  /* cap on the blocks of an inner launch (0 = as many as fit) */
   double mv_ms;            /* median time of one SG matvec with the chosen schedule */
