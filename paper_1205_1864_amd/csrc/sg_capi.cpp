@@ -1268,13 +1268,6 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   if (const char* env = std::getenv("SGPC_MV_PIECE_ROWS")) h->mv_piece_rows = std::atoi(env);
   h->pcg_max_blocks = 0;
   if (const char* env = std::getenv("SGPC_PCG_MAX_BLOCKS")) h->pcg_max_blocks = std::atoi(env);
-  int dev = 0;
-  h->num_cu = 1;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-    delete h;
-    return fail(SG_EDEVICE, "no HIP device");
-  }
   const int M = h->M, P = h->P;
   const long ne2 = (long)h->n_e * h->n_e;
   // element coefficients
@@ -1378,6 +1371,14 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
       pair_g.push_back(pairg[k][i]);
     }
     pair_ptr[k + 1] = (int)pair_a.size();
+  }
+  // the host tables above need no device; the first HIP call comes here
+  int dev = 0;
+  h->num_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    delete h;
+    return fail(SG_EDEVICE, "no HIP device");
   }
   h->lo_ptr = lo_ptr;
   h->up_ptr = up_ptr;
