@@ -79,7 +79,8 @@ def time_matvec(solver, U, Y, reps, cold, flush=None):
 
 
 def bench_batch(degree, count=48, seed=0):
-    """The uneven batch solved together (graph replay) and one problem after another."""
+    """The uneven batch solved together (graph replay; default, then autotuned
+    schedules) and one problem after another (default schedules)."""
     import torch
     from paper_1205_1864_amd.binding import Options, SGBatch, SGSolver, to_device_block
     from sg_inputs import batch_problems
@@ -89,12 +90,20 @@ def bench_batch(degree, count=48, seed=0):
     batch = SGBatch(probs, opts)
     F = [to_device_block(p.load_block()) for p in probs]
     U = batch.empty()
-    batch.sg_batch_solve(F, U, rtol=1e-8, maxit=100)  # warm-up; captures the graph
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, st, info = batch.sg_batch_solve(F, U, rtol=1e-8, maxit=100)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+
+    def timed():
+        batch.sg_batch_solve(F, U, rtol=1e-8, maxit=100)  # warm-up; captures the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, info = batch.sg_batch_solve(F, U, rtol=1e-8, maxit=100)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st, info
+
+    t_default, _, _ = timed()
+    log(f"batch, default schedules: {t_default:.3f} s ({count / t_default:.2f} solves/s)")
+    tune = batch.sg_batch_autotune(3)
+    log(f"batch autotuned: {tune}")
+    t_batch, st, info = timed()
     log(f"batch: {t_batch:.3f} s ({count / t_batch:.2f} solves/s), rc {info['rc']}")
     batch.close()
     del batch
@@ -118,7 +127,8 @@ def bench_batch(degree, count=48, seed=0):
     log(f"sequential: {t_seq:.3f} s ({count / t_seq:.2f} solves/s)")
     return {
         "batch_count": count, "batch_unknowns": int(sum(p.n * p.P for p in probs)),
-        "batch_s": t_batch, "batch_solves_per_s": count / t_batch,
+        "batch_s": t_batch, "batch_solves_per_s": count / t_batch, "batch_default_schedule_s": t_default,
+        "batch_schedule": tune,
         "batch_sequential_s": t_seq, "batch_sequential_solves_per_s": count / t_seq,
         "batch_speedup_vs_sequential": t_seq / t_batch, "batch_rc": info["rc"],
         "batch_outer_it": [s["outer_it"] for s in st], "batch_sequential_outer_it": seq_outer,
@@ -452,7 +462,7 @@ def main():
     # the counter traffic belongs to the schedules it was measured with
     pcg_traffic = PCG_TRAFFIC_BYTES if (schedule["pcg_tile"], schedule["pcg_max_blocks"]) == (32, 0) else None
     mv_traffic = MATVEC_TRAFFIC_BYTES.get((schedule["mv_variant"], schedule["mv_param"]))
-    mv_kernel = {3: "sgop_piece_kernel<double>", 2: "sgop_march_kernel<double>",
+    mv_kernel = {4: "sgop_stage_kernel", 3: "sgop_piece_kernel<double>", 2: "sgop_march_kernel<double>",
                  1: "sgop_strip_dyn_kernel<double>", 0: "sgop_strip_kernel<double>"}.get(
                      schedule["mv_variant"], f"SG operator variant {schedule['mv_variant']}")
     roofline = {

@@ -256,7 +256,8 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
  *                automatic count; band kernels with 32..128 row chunks per
  *                band, where the grid shape allows them);
  *   flags bit 1: the inner PCG (tile kind 16 or 32 where the Chebyshev halo
- *                allows 32; block count automatic or half the CUs), timed on
+ *                allows 32; block count automatic, half the CUs, or whole
+ *                columns per block), timed on
  *                the columns of the largest chaos level with a constant
  *                right-hand side.
  * Runs on the handle's stream inside its workspace (the FCG vectors and the
@@ -268,11 +269,14 @@ typedef struct sg_tune_report {
   int32_t mv_param;        /* row chunks per band (variants 0, 1); segments per XCD (2; 0 = automatic);
                               100 * rows per piece + waves per CU (3; 0 waves = all resident) */
   int32_t pcg_tile;        /* inner tile kind (32 banded, 16 square) */
-  int32_t pcg_max_blocks;  /* cap on the blocks of an inner launch (0 = as many as fit) */
+  int32_t pcg_max_blocks;  /* cap on the blocks of an inner launch (0 = as many as fit; -1 = whole
+                              columns per block for launches whose columns fill at least 3/4 of the
+                              resident blocks, no cap for smaller ones) */
   double mv_ms;            /* median time of one SG matvec with the chosen schedule */
   double pcg_ms;           /* time of the inner test solve with the chosen schedule */
   int32_t candidates;      /* schedules timed */
-  int32_t reserved;
+  int32_t pcg_rows;        /* band height of banded inner tiles (sg_batch_autotune; 16 for 16 x 16
+                              tiles); 0 from sg_autotune, whose launches pick it by their size */
 } sg_tune_report;
 
 int sg_autotune(sg_handle h, int32_t flags, sg_tune_report* report);
@@ -317,6 +321,21 @@ int sg_batch_solve(sg_batch b, const double* const* F, double* const* U, double 
                    int32_t use_graph, sg_stats* stats, double* ms_total);
 
 /* Release the batch and its per-problem handles (the workspace stays with the caller). */
+/* Schedule autotuner of a batch (the batch counterpart of sg_autotune):
+ *   flags bit 0: every member's SG operator, as sg_autotune's bit 0 on the
+ *                member's own sizes;
+ *   flags bit 1: the ragged inner launches: banded tiles with the default or
+ *                64-row bands, and 16 x 16 tiles when opts.tile is 0, each
+ *                with all or half of the compute units, timed on one inner
+ *                solve of every column set a preconditioner action uses, with
+ *                a constant right-hand side in every problem.
+ * Overwrites the members' vectors, drops a captured graph and synchronises
+ * the stream; the candidates differ only in the order of floating-point sums.
+ * report (host, may be NULL) receives the choice: the inner schedule, and
+ * the SG-operator schedule of the largest member with mv_ms summed over the
+ * members. */
+int sg_batch_autotune(sg_batch b, int32_t flags, sg_tune_report* report);
+
 void sg_batch_destroy(sg_batch b);
 
 /* Lognormal coefficient (Section 6, second set of experiments; Tables 6-9).

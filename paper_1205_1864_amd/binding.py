@@ -57,10 +57,10 @@ class SgStats(ctypes.Structure):
 class SgTuneReport(ctypes.Structure):
     _fields_ = [("mv_variant", ctypes.c_int32), ("mv_param", ctypes.c_int32), ("pcg_tile", ctypes.c_int32),
                 ("pcg_max_blocks", ctypes.c_int32), ("mv_ms", ctypes.c_double), ("pcg_ms", ctypes.c_double),
-                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("candidates", ctypes.c_int32), ("pcg_rows", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def _load():
@@ -89,6 +89,7 @@ def _load():
         "sg_batch_setup": [I32, P(SgProblem), P(SgOpts), VP, ctypes.c_size_t, VP, P(VP)],
         "sg_batch_sizes": [VP, I32, P(I64), P(I32)],
         "sg_batch_solve": [VP, P(VP), P(VP), D, I32, I32, P(SgStats), P(D)],
+        "sg_batch_autotune": [VP, I32, P(SgTuneReport)],
         "sg_logn_workspace_bytes": [P(SgProblem), P(ctypes.c_size_t)],
         "sg_logn_setup": [P(SgProblem), VP, ctypes.c_size_t, VP, P(VP)],
         "sg_logn_sizes": [VP, P(I64), P(I32), P(I32)],
@@ -335,7 +336,7 @@ class SGSolver:
 class SGBatch:
     """Many independent SG problems solved together (a batch handle plus its workspace).
 
-    All problems share the options; ``precond`` must be "hsc" or "mean".
+    All problems share the options; ``precond`` must be "hsc", "bgs" or "mean".
     """
 
     def __init__(self, problems, opts: Options = None, device="cuda", stream=None):
@@ -392,6 +393,11 @@ class SGBatch:
         caller.wait_stream(self.stream)
         stats = [s.as_dict() for s in st]
         return U, stats, {"rc": rc, "ms": ms.value}
+
+    def sg_batch_autotune(self, flags=3):
+        rep = SgTuneReport()
+        _check(lib.sg_batch_autotune(self.handle, int(flags), ctypes.byref(rep)))
+        return rep.as_dict()
 
     def close(self):
         if getattr(self, "handle", None):

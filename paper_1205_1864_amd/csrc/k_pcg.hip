@@ -62,12 +62,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Split-phase barrier of one column: every block that owns tiles of the column
 // adds its tile count to a monotonic arrival counter after finishing its tiles;
-// phase k of the column is complete once the counter reaches k * ntiles.
+// phase k of the column is complete once the counter reaches k * ntiles. The
+// arrival releases the block's writes (device scope) and the wait acquires
+// them: one L2 write-back per arrival, one invalidation per wait.
+// A column whose tiles all belong to one block needs neither: its phases are
+// ordered by the block's own barriers (see pcg_kernel).
 __device__ void column_arrive(unsigned* arr, unsigned count) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    atomicAdd(arr, count);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(arr, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -84,7 +88,7 @@ __device__ bool column_wait(const unsigned* arr, unsigned target, int* status, i
         break;
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *sflag = ok;
   }
   __syncthreads();
@@ -919,7 +923,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       return (int)(w / A.ntiles);
     }
   };
-  const long per_block = (nwork + gridDim.x - 1) / gridDim.x;
+  const long per_block = A.per_block > 0 ? A.per_block : (nwork + gridDim.x - 1) / gridDim.x;
   const long w_begin = (long)blockIdx.x * per_block;
   const long w_end = w_begin + per_block < nwork ? w_begin + per_block : nwork;
   if (w_begin >= w_end) return;
@@ -932,6 +936,9 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
     t1 = (int)(hi - v.tbase);
   };
   auto owner = [&](const ColView<T>& v) { return v.tbase >= w_begin; };  // this block holds tile 0
+  // this block holds every tile of the column: its phases need only the block's
+  // barriers (workgroup-scope ordering of the block's own global writes)
+  auto whole = [&](const ColView<T>& v, int t0, int t1) { return t0 == 0 && t1 == v.ntiles; };
   // the column starts from the contents of its x
   auto warm_of = [&](const ColView<T>& v) { return A.warm && Tile::warm_fits(v, degree); };
   // Fixed-order sums of up to five per-tile partial arrays of a column, one wave each.
@@ -979,7 +986,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         P(PART_RR1)[v.tbase + t] = rr;
       }
     }
-    column_arrive(arr + c, (unsigned)(t1 - t0));
+    if (whole(v, t0, t1)) __syncthreads();
+    else column_arrive(arr + c, (unsigned)(t1 - t0));
   }
 
   bool aborted = false;
@@ -994,7 +1002,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       int t0, t1;
       tiles_of(v, t0, t1);
       if (t1 <= t0) continue;
-      if (!column_wait(arr + c, (unsigned)((1 + 2 * it) * v.ntiles), A.sc.status, &sflag)) {
+      if (whole(v, t0, t1)) __syncthreads();
+      else if (!column_wait(arr + c, (unsigned)((1 + 2 * it) * v.ntiles), A.sc.status, &sflag)) {
         aborted = true;
         break;
       }
@@ -1025,7 +1034,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       }
       any_active = true;
       Tile::run_a(v, t0 + grp, t1, G, I, W0, gb, sred, P(par ? PART_PQ1 : PART_PQ0) + v.tbase);
-      column_arrive(arr + c, (unsigned)(t1 - t0));
+      if (whole(v, t0, t1)) __syncthreads();
+      else column_arrive(arr + c, (unsigned)(t1 - t0));
     }
     if (!any_active || aborted) break;
     // ---- phase B (column phase 3 + 2 it): r -= alpha q, z = M r, partials r.r, r.z
@@ -1035,7 +1045,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       int t0, t1;
       tiles_of(v, t0, t1);
       if (t1 <= t0) continue;
-      if (!column_wait(arr + c, (unsigned)((2 + 2 * it) * v.ntiles), A.sc.status, &sflag)) {
+      if (whole(v, t0, t1)) __syncthreads();
+      else if (!column_wait(arr + c, (unsigned)((2 + 2 * it) * v.ntiles), A.sc.status, &sflag)) {
         aborted = true;
         break;
       }
@@ -1059,7 +1070,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       I.rn = par ? v.r0 : v.r1;
       Tile::run_b(v, degree, t0 + grp, t1, G, I, W0, W1, gb, sred, P(par ? PART_RZ1 : PART_RZ0) + v.tbase,
                   P(par ? PART_RR1 : PART_RR0) + v.tbase);
-      column_arrive(arr + c, (unsigned)(t1 - t0));
+      if (whole(v, t0, t1)) __syncthreads();
+      else column_arrive(arr + c, (unsigned)(t1 - t0));
     }
   }
   // ---- iteration counts of columns that ran out of iterations
@@ -1095,13 +1107,37 @@ hipError_t launch_cfg(const PcgArgs<T>& args, const PcgCols<T>& cols, int max_bl
   // grid must fit on the device at once with the LDS it needs (tile buffers
   // plus one done flag per column a block can touch).
   const long min_tiles = RAGGED ? 1 : args.ntiles;
-  long grid = (nwork + 2L * G - 1) / (2L * G);
+  long per_block = 0;  // 0: the work list split evenly over the grid
+  size_t sm = 0;
+  if (!RAGGED && max_blocks < 0) {
+    // Whole columns per block: each block owns k consecutive columns, k the
+    // smallest count with which the grid fits on the device at once, so no
+    // column phase needs the device-scope arrival counters. Taken when the
+    // columns keep at least three quarters of the k * (resident blocks) column
+    // places busy; other launches take the automatic grid.
+    max_blocks = 0;
+    for (long k = 1; k <= 8; ++k) {
+      sm = tiles_bytes + sizeof(int) * (size_t)(k + 2);
+      if (sm > 160 * 1024) return hipErrorInvalidValue;
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+      if (e != hipSuccess) return e;
+      int per_cu = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, Tile::kThreads * G, sm);
+      if (e != hipSuccess) return e;
+      const long cap = (long)per_cu * ncu;
+      if (cap < 1) break;
+      if ((args.ncols + k - 1) / k <= cap) {
+        if (4L * args.ncols >= 3L * k * cap) per_block = k * args.ntiles;
+        break;
+      }
+    }
+  }
+  long grid = per_block > 0 ? (nwork + per_block - 1) / per_block : (nwork + 2L * G - 1) / (2L * G);
   if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid < 1) grid = 1;
-  size_t sm = 0;
-  for (int pass = 0; pass < 8; ++pass) {
-    const long per_block = (nwork + grid - 1) / grid;
-    const long max_cols = per_block / min_tiles + 2;  // a run of per_block items spans at most this many columns
+  for (int pass = 0; pass < 8 && per_block == 0; ++pass) {
+    const long pb = (nwork + grid - 1) / grid;
+    const long max_cols = pb / min_tiles + 2;  // a run of pb items spans at most this many columns
     sm = tiles_bytes + sizeof(int) * (size_t)max_cols;
     if (sm > 160 * 1024) return hipErrorInvalidValue;
     // the cooperative launch checks co-residency against this attribute, so keep it exact
@@ -1117,6 +1153,7 @@ hipError_t launch_cfg(const PcgArgs<T>& args, const PcgCols<T>& cols, int max_bl
     if (pass == 7) return hipErrorInvalidValue;
   }
   PcgArgs<T> a = args;
+  a.per_block = per_block;
   PcgCols<T> c = cols;
   int lg = lds_group;
   hipLaunchKernelGGL(pcg_reset_kernel, dim3(1), dim3(256), 0, s, a.sc.arrivals, a.ncols, a.sc.status);
@@ -1168,12 +1205,12 @@ hipError_t launch_pcg(const PcgArgs<T>& args, int tile, int max_blocks, hipStrea
 }
 
 template <typename T>
-hipError_t launch_pcg_ragged(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile, hipStream_t s) {
-  return dispatch_pcg<T, true>(args, cols, tile, 0, s);
+hipError_t launch_pcg_ragged(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile, int max_blocks, hipStream_t s) {
+  return dispatch_pcg<T, true>(args, cols, tile, max_blocks, s);
 }
 
-template hipError_t launch_pcg_ragged<double>(const PcgArgs<double>&, const PcgCols<double>&, int, hipStream_t);
-template hipError_t launch_pcg_ragged<float>(const PcgArgs<float>&, const PcgCols<float>&, int, hipStream_t);
+template hipError_t launch_pcg_ragged<double>(const PcgArgs<double>&, const PcgCols<double>&, int, int, hipStream_t);
+template hipError_t launch_pcg_ragged<float>(const PcgArgs<float>&, const PcgCols<float>&, int, int, hipStream_t);
 template hipError_t launch_pcg<double>(const PcgArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_pcg<float>(const PcgArgs<float>&, int, int, hipStream_t);
 

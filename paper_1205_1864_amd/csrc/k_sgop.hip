@@ -937,6 +937,214 @@ bool march_supported(int n_e, int M) { return n_e % 64 == 0 && n_e >= 64 && n_e 
 
 int march_blocks_per_cu(int M, int block) { return march_occ<kStripMaxM>(M, block); }
 
+// ---------------------------------------------------------------------------
+// Row-staged full operator (FP64). A block (one per CU: the staged rows take
+// most of the LDS) works through pieces of kStageOut node columns by TY node
+// rows. For each element row e of a piece (between node rows e - 1 and e) it
+// holds node rows e - 1 and e of every chaos column, and the coefficients of
+// element row e, in LDS; the next row is loaded into registers while the
+// current one is used. Each half wave owns a list of output columns a; for
+// every term (b, k, g) of a (b = a: k = 0 and g = 1 with coefficient theta0;
+// b = a -+ e_k: the Galerkin weight g of G_k) it forms, lane by lane,
+//   R0 += g c_k(right element) U_b(e - 1),  R1 += g c_k(right element) U_b(e),
+//   L0 += g c_k(left element) U_b(e - 1),   L1 += g c_k(left element) U_b(e),
+// the corner values of sum_terms c g U_b on the element right of the node
+// (BL = R0, TL = R1; BR and TR are the next lane's L0, L1). The element matrix
+// of the Q1 Laplacian (times 6: 4 on the diagonal, -1 along the edges, -2
+// across) turns them into the element's contributions to its four corners,
+// which complete node row e - 1 and start node row e of output a.
+// ---------------------------------------------------------------------------
+size_t stage_lds_bytes(int P, int M, int nterms, int nslots) {
+  if (P < 1 || P >= 0xFFFF || M < 0 || M > 255 || nterms < 0 || nterms > 0xFFFF || nslots < 1) return 0;
+  if ((long)P * kStageLanes > (long)kStagePre * kStageWaves * 64) return 0;
+  if ((M + 1) * kStageLanes > kStageWaves * 64) return 0;
+  // node rows [P][32 lanes][2 parities], coefficients [M + 1][32], terms, slots
+  const size_t b = sizeof(double) * ((size_t)P * 2 * kStageLanes + (size_t)(M + 1) * kStageLanes) +
+                   sizeof(StageTerm) * (size_t)nterms + sizeof(StageSlot) * (size_t)nslots;
+  return b <= 160 * 1024 ? b : 0;
+}
+
+namespace {
+
+// One element row e of a piece: node rows e - 1 (parity 1 - PE) and e (parity PE)
+// and the coefficients of element row e are in LDS; the next node row (parity
+// 1 - PE) and coefficient row are loaded meanwhile and stored after the step's
+// reads. Completes output node row e - 1 (if e > y0) and starts row e.
+template <int PE>
+__device__ __forceinline__ void stage_step(const SgOpArgs<double>& A, const StageJob& J, double* Ub, double* Cb,
+                                           const StageTerm* Tl, const StageSlot* Sl, int e, int y0, int y1, int x0,
+                                           int s_begin, int s_end, double (&Yc)[kStageSlots]) {
+  const int tid = threadIdx.x, lane = tid & 63, l32 = lane & 31;
+  const int nx = A.nx, n_e = A.n_e;
+  const long n = A.n;
+  const int P = J.P, MC = J.M + 1;
+  const bool more = e < y1;
+  // the next rows into registers: thread tid stages lane tid % 32 of chaos
+  // columns tid / 32 + 32 j (32-bit offsets: the host enables this kernel only
+  // for n P < 2^31)
+  const int sb = tid >> 5, sx = x0 - 1 + (tid & 31);
+  double nv[kStagePre];
+  double nc = 0.0;
+  if (more) {
+    const int gy = e + 1;
+    const bool ok = gy < nx && sx >= 0 && sx < nx;
+    const unsigned base = (unsigned)sb * (unsigned)n + (unsigned)(gy * nx + sx);
+    const unsigned step = 32u * (unsigned)n;
+#pragma unroll
+    for (int j = 0; j < kStagePre; ++j) nv[j] = (ok && sb + 32 * j < P) ? A.in[base + (unsigned)j * step] : 0.0;
+    if (tid < MC * kStageLanes) {
+      const int k = tid >> 5, ex = x0 + (tid & 31);
+      if (ex < n_e) nc = k == 0 ? A.diag : A.a[(long)(k - 1) * n_e * n_e + (long)gy * n_e + ex];
+    }
+  }
+  const double2* Ul = reinterpret_cast<const double2*>(Ub) + l32;  // (node row parity 0, parity 1)
+  const double* Cl = Cb + l32;                                      // right element of the lane's node
+  const unsigned hb = (lane >> 5) * 16u, hk = (lane >> 5) * 8u;
+  const int gx = x0 - 1 + l32;
+  const double scale = 1.0 / 6.0, theta0 = A.diag;
+  auto accumulate = [&](double g, const double2& uv, double cr, double& R0, double& R1, double& L0, double& L1) {
+    const double u0 = PE ? uv.x : uv.y, u1 = PE ? uv.y : uv.x;  // node rows e - 1, e
+    const double gr = g * cr, gl = from_prev(gr);                 // the left element is the previous lane's right one
+    R0 = fma(gr, u0, R0);
+    R1 = fma(gr, u1, R1);
+    L0 = fma(gl, u0, L0);
+    L1 = fma(gl, u1, L1);
+  };
+  // a term's staged values: U_b at node rows e - 1 and e (one 16-byte read) and
+  // the coefficient of k on the right element
+  auto term_vals = [&](const uint4& q, double2& uv, double& cr, double& g) {
+    const unsigned b = (q.x >> hb) & 0xFFFFu, k = (q.y >> hk) & 0xFFu;
+    uv = Ul[b * kStageLanes];
+    cr = Cl[k * kStageLanes];
+    g = __hiloint2double((int)q.w, (int)q.z);
+  };
+#pragma unroll
+  for (int s = 0; s < kStageSlots; ++s) {
+    const int si = s_begin + s;
+    if (si < s_end) {
+      const uint2 sv = *reinterpret_cast<const uint2*>(Sl + si);
+      const int t0 = __builtin_amdgcn_readfirstlane((int)(sv.y & 0xFFFFu));
+      const int nt = __builtin_amdgcn_readfirstlane((int)(sv.y >> 16));
+      const unsigned oh = (sv.x >> hb) & 0xFFFFu;
+      const int out = oh == 0xFFFFu ? -1 : (int)oh;
+      // the mean term: coefficient theta0 on both elements, weight 1
+      const double2 ud = Ul[(out >= 0 ? out : (int)(sv.x & 0xFFFFu)) * kStageLanes];
+      const double d0 = theta0 * (PE ? ud.x : ud.y), d1 = theta0 * (PE ? ud.y : ud.x);
+      double R0 = d0, R1 = d1, L0 = d0, L1 = d1;
+      const uint4* tq = reinterpret_cast<const uint4*>(Tl + t0);
+      int t = 0;
+      // two terms at a time: every LDS read of both goes out before the arithmetic
+      for (; t + 1 < nt; t += 2) {
+        const uint4 qa = tq[t], qb = tq[t + 1];
+        double2 ua, ub;
+        double ca, cb, ga, gb;
+        term_vals(qa, ua, ca, ga);
+        term_vals(qb, ub, cb, gb);
+        accumulate(ga, ua, ca, R0, R1, L0, L1);
+        accumulate(gb, ub, cb, R0, R1, L0, L1);
+      }
+      if (t < nt) {
+        double2 ua;
+        double ca, ga;
+        term_vals(tq[t], ua, ca, ga);
+        accumulate(ga, ua, ca, R0, R1, L0, L1);
+      }
+      const double BL = R0, TL = R1, BR = from_next(L0), TR = from_next(L1);
+      const double S = (BL + BR) + (TR + TL);
+      const double oBL = 5.0 * BL - S - TR;
+      const double oBR = 5.0 * BR - S - TL;
+      const double oTR = 5.0 * TR - S - BL;
+      const double oTL = 5.0 * TL - S - BR;
+      const double bot = oBL + from_prev(oBR);  // node row e - 1
+      const double top = oTL + from_prev(oTR);  // node row e
+      if (e > y0 && out >= 0 && l32 >= 1 && l32 <= kStageOut && gx < nx)
+        A.out[(unsigned)out * (unsigned)n + (unsigned)((e - 1) * nx + gx)] = scale * (Yc[s] + bot);
+      Yc[s] = top;
+    }
+  }
+  __syncthreads();  // every read of node row e - 1 and of element row e is done
+  if (more) {
+    double* dst = Ub + (sb * kStageLanes + (tid & 31)) * 2 + (1 - PE);
+#pragma unroll
+    for (int j = 0; j < kStagePre; ++j)
+      if (sb + 32 * j < P) dst[j * 32 * (2 * kStageLanes)] = nv[j];
+    if (tid < MC * kStageLanes) Cb[tid] = nc;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kStageWaves * 64) sgop_stage_kernel(const SgOpArgs<double> A, const StageJob J) {
+  if (A.active && ld_uniform(A.active, 0) == 0) return;
+  extern __shared__ double stage_lds[];
+  const int P = J.P, MC = J.M + 1;
+  double* Ub = stage_lds;                              // [P][32][2]: node rows by parity
+  double* Cb = Ub + P * 2 * kStageLanes;               // [M + 1][32]: coefficients of the current element row
+  StageTerm* Tl = reinterpret_cast<StageTerm*>(Cb + MC * kStageLanes);
+  StageSlot* Sl = reinterpret_cast<StageSlot*>(Tl + J.nterms);
+  const int tid = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nx = A.nx, n_e = A.n_e;
+  const long n = A.n;
+  const int s_begin = ld_uniform(J.wslot, wv), s_end = ld_uniform(J.wslot, wv + 1);
+  // the term and slot tables into LDS (16 and 8 bytes per entry)
+  for (int i = tid; i < J.nterms; i += kStageWaves * 64)
+    reinterpret_cast<uint4*>(Tl)[i] = reinterpret_cast<const uint4*>(J.terms)[i];
+  for (int i = tid; i < J.nslots; i += kStageWaves * 64)
+    reinterpret_cast<uint2*>(Sl)[i] = reinterpret_cast<const uint2*>(J.slots)[i];
+  // pieces of this block's XCD (block b runs on XCD b mod 8), a contiguous band
+  const int xcd = blockIdx.x % 8, bslot = blockIdx.x / 8;
+  const int nb = ((int)gridDim.x - xcd + 7) / 8;
+  const long npieces = (long)J.nyseg * J.nseg;
+  const long p0 = npieces * xcd / 8, p1 = npieces * (xcd + 1) / 8;
+  for (long pc = p0 + bslot; pc < p1; pc += nb) {
+    const int yseg = (int)(pc / J.nseg), seg = (int)(pc % J.nseg);
+    const int x0 = seg * kStageOut;     // first output node column
+    const int y0 = yseg * J.TY;
+    const int y1 = min(nx, y0 + J.TY);  // output node rows [y0, y1)
+    // prologue: node rows y0 - 1 and y0, coefficients of element row y0
+    for (int r = 0; r < 2; ++r) {
+      const int gy = y0 - 1 + r, par = (y0 + 1 + r) & 1;
+      const int sb = tid >> 5, sx = x0 - 1 + (tid & 31);
+      const bool ok = gy >= 0 && gy < nx && sx >= 0 && sx < nx;
+      const unsigned base = (unsigned)sb * (unsigned)n + (unsigned)(gy * nx + sx);
+      double* dst = Ub + (sb * kStageLanes + (tid & 31)) * 2 + par;
+      for (int j = 0; j < kStagePre; ++j)
+        if (sb + 32 * j < P) dst[j * 32 * (2 * kStageLanes)] = ok ? A.in[base + (unsigned)j * 32u * (unsigned)n] : 0.0;
+    }
+    if (tid < MC * kStageLanes) {
+      const int k = tid >> 5, ex = x0 + (tid & 31);
+      double c = 0.0;
+      if (ex < n_e) c = k == 0 ? A.diag : A.a[(long)(k - 1) * n_e * n_e + (long)y0 * n_e + ex];
+      Cb[tid] = c;
+    }
+    __syncthreads();
+    double Yc[kStageSlots];
+#pragma unroll
+    for (int s = 0; s < kStageSlots; ++s) Yc[s] = 0.0;
+    for (int e = y0; e <= y1; ++e) {
+      if (e & 1) stage_step<1>(A, J, Ub, Cb, Tl, Sl, e, y0, y1, x0, s_begin, s_end, Yc);
+      else stage_step<0>(A, J, Ub, Cb, Tl, Sl, e, y0, y1, x0, s_begin, s_end, Yc);
+    }
+  }
+}
+
+}  // namespace
+
+void launch_stage(const SgOpArgs<double>& args, const StageJob& job, hipStream_t s) {
+  const size_t lds = stage_lds_bytes(job.P, job.M, job.nterms, job.nslots);
+  if (lds == 0) return;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(sgop_stage_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int dev = 0, ncu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const long npieces = (long)job.nyseg * job.nseg;
+  long grid = ncu;
+  if (grid > npieces) grid = npieces;
+  grid = (grid + 7) / 8 * 8;
+  hipLaunchKernelGGL(sgop_stage_kernel, dim3((unsigned)grid), dim3(kStageWaves * 64), lds, s, args, job);
+}
+
 template <typename T>
 void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, const MarchJob* job, hipStream_t s) {
   if (args.nrows <= 0) return;

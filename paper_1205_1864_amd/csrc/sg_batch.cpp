@@ -34,6 +34,8 @@ struct sg_batch_ctx {
   int inner = 64;
   int degree = 1;
   int tile = 32;
+  int rows = 0;        // band height of banded inner tiles
+  int max_blocks = 0;  // cap on the blocks of a ragged inner launch (0 = as many as fit)
   sg_opts opts{};
   hipStream_t stream = nullptr;
   std::vector<sg_ctx*> h;
@@ -42,6 +44,10 @@ struct sg_batch_ctx {
   std::vector<sgk::PcgCols<double>> cols64;
   std::vector<sgk::PcgCols<float>> cols32;
   std::vector<int> set_ncols;
+  std::vector<long> set_nwork_cap;  // planned work items per set (largest over the tilings)
+  std::vector<size_t> set_off;      // byte offset of each set in the set region
+  char* sets_base = nullptr;
+  const void* sets_consts = nullptr;  // per-problem inner constants (device)
   sgk::PcgScratch sc{};
   int* sticky = nullptr;  // set if a bounded wait of an inner launch expired
   int* pdeg = nullptr;    // chaos degree of each problem (device)
@@ -84,6 +90,21 @@ int batch_tile(const sg_opts& op) {
   return op.cheb_degree <= sgk::kBandMaxDegree ? 32 : 16;
 }
 
+// Inner tilings (tile kind, band rows) a batch may run with: the default
+// first, then the other kinds the options allow (the autotuner's candidates).
+std::vector<std::pair<int, int>> batch_tilings(const sg_opts& op) {
+  const int def_rows = sgk::band_rows(op.inner_precision, op.cheb_degree);
+  std::vector<std::pair<int, int>> t;
+  if (batch_tile(op) == 32) {
+    t.push_back({32, def_rows});
+    t.push_back({32, sgk::kBandRowsSmall});
+    if (op.tile == 0) t.push_back({16, 0});
+  } else {
+    t.push_back({16, 0});
+  }
+  return t;
+}
+
 // Byte layout of the batch: the problems' own workspaces first, then the
 // shared region. Returns false if a problem is rejected.
 struct BatchPlan {
@@ -117,13 +138,18 @@ int make_batch_plan(int count, const sg_problem* probs, const sg_opts* op, Batch
     bp.ws_size.push_back(bytes);
     pmax = std::max(pmax, probs[b].p);
   }
-  const int tile = batch_tile(*op);
   bp.set_ncols.assign(pmax + 2, 0);
   bp.set_nwork.assign(pmax + 2, 0);
+  const std::vector<std::pair<int, int>> tilings = batch_tilings(*op);
   for (int b = 0; b < count; ++b) {
     const std::vector<int> off = level_offsets(probs[b].M, probs[b].p);
-    int ntx = 0, nt = 0;
-    sgk::pcg_tiling(probs[b].n_e - 1, op->cheb_degree, tile, sgk::band_rows(op->inner_precision, op->cheb_degree), ntx, nt);
+    // tiles per column: the most over the tilings the autotuner may choose
+    int nt = 0;
+    for (const auto& tr : tilings) {
+      int ntx = 0, ntt = 0;
+      sgk::pcg_tiling(probs[b].n_e - 1, op->cheb_degree, tr.first, tr.second, ntx, ntt);
+      nt = std::max(nt, ntt);
+    }
     for (int l = 0; l <= probs[b].p; ++l) {
       bp.set_ncols[l] += off[l + 1] - off[l];
       bp.set_nwork[l] += (long)(off[l + 1] - off[l]) * nt;
@@ -175,7 +201,7 @@ int build_set(sg_batch_ctx* B, int s, char* base, std::vector<char>& host, sgk::
     }
     const long n = h->n;
     int t = 0, nt = 0;
-    sgk::pcg_tiling(h->nx, B->degree, B->tile, sgk::band_rows(B->inner, B->degree), t, nt);
+    sgk::pcg_tiling(h->nx, B->degree, B->tile, B->rows, t, nt);
     T* rw = (T*)h->rw;
     T* zw = B->inner == 32 ? (T*)h->zw : (T*)h->z;
     for (int j = j0; j < j1; ++j) {
@@ -238,6 +264,40 @@ std::vector<sgk::PcgCols<double>>& sets<double>(sg_batch_ctx* B) { return B->col
 template <>
 std::vector<sgk::PcgCols<float>>& sets<float>(sg_batch_ctx* B) { return B->cols32; }
 
+// Builds every ragged column set for the batch's current tiling (B->tile,
+// B->rows) and uploads them into the set region; synchronises the stream.
+int upload_sets(sg_batch_ctx* B) {
+  B->cols64.clear();
+  B->cols32.clear();
+  B->set_ncols.assign(B->pmax + 2, 0);
+  const auto* consts = B->sets_consts;
+  for (int s = 0; s <= B->pmax + 1; ++s) {
+    std::vector<char> blob;
+    long nwork = 0;
+    char* base = B->sets_base + B->set_off[s];
+    int rc;
+    if (B->inner == 32) {
+      sgk::PcgCols<float> c{};
+      rc = build_set<float>(B, s, base, blob, c, nwork);
+      c.consts = (const sgk::PcgConsts<float>*)consts;
+      c.active = B->V.active;
+      B->cols32.push_back(c);
+    } else {
+      sgk::PcgCols<double> c{};
+      rc = build_set<double>(B, s, base, blob, c, nwork);
+      c.consts = (const sgk::PcgConsts<double>*)consts;
+      c.active = B->V.active;
+      B->cols64.push_back(c);
+    }
+    if (rc == SG_OK && nwork > B->set_nwork_cap[s]) rc = fail(SG_EINVAL, "inner tiling exceeds the planned work list");
+    if (rc) return rc;
+    if (!blob.empty()) SG_HIP(hipMemcpyAsync(base, blob.data(), blob.size(), hipMemcpyHostToDevice, B->stream));
+    // the host blob is freed at the end of this iteration: wait for its copy
+    SG_HIP(hipStreamSynchronize(B->stream));
+  }
+  return SG_OK;
+}
+
 // Ragged inner launch over column set s, restricted to problems of degree >= pmin;
 // warm: start from the contents of X where the options allow it.
 template <typename T>
@@ -247,7 +307,7 @@ int run_set(sg_batch_ctx* B, int s, int pmin = 0, bool warm = false) {
   sgk::PcgArgs<T> a{};
   a.ncols = ncols;
   a.degree = B->degree;
-  a.rows = sgk::band_rows(B->inner, B->degree);
+  a.rows = B->rows;
   a.maxit = B->opts.inner_maxit;
   a.rtol = B->opts.inner_rtol > 0.0 ? B->opts.inner_rtol : 0.0;
   a.warm = warm && B->opts.warm_start && B->tile != 16;
@@ -257,7 +317,7 @@ int run_set(sg_batch_ctx* B, int s, int pmin = 0, bool warm = false) {
   sgk::launch_batch_compact(cols.prob, cols.ntiles, ncols, B->V.active, B->pdeg, pmin, const_cast<int*>(cols.act),
                             const_cast<int*>(cols.nact), const_cast<long*>(cols.cbase),
                             const_cast<long*>(cols.nwork_act), B->stream);
-  SG_HIP(sgk::launch_pcg_ragged<T>(a, cols, B->tile, B->stream));
+  SG_HIP(sgk::launch_pcg_ragged<T>(a, cols, B->tile, B->max_blocks, B->stream));
   sgk::launch_batch_count_iters(B->sc.iters, cols.act, cols.nact, cols.prob, ncols, B->V.sc, B->sc.status,
                                 B->sticky, B->stream);
   return SG_OK;
@@ -383,6 +443,7 @@ int sg_batch_setup(int32_t count, const sg_problem* probs, const sg_opts* opts, 
   B->stream = (hipStream_t)stream;
   B->inner = opts->inner_precision;
   B->tile = batch_tile(*opts);
+  B->rows = sgk::band_rows(opts->inner_precision, opts->cheb_degree);
   for (int b = 0; b < count; ++b) {
     sg_handle hb = nullptr;
     rc = sg_setup(&probs[b], opts, w + bp.ws_off[b], bp.ws_size[b], stream, &hb);
@@ -463,34 +524,14 @@ int sg_batch_setup(int32_t count, const sg_problem* probs, const sg_opts* opts, 
       std::memcpy(consts.data() + sizeof(k) * b, &k, sizeof(k));
     }
   }
-  // ragged column sets
-  B->set_ncols.assign(B->pmax + 2, 0);
-  std::vector<char> sets_host;
+  // ragged column sets (built and uploaded after the shared tables)
+  B->sets_base = w + bp.o_sets;
+  B->sets_consts = w + bp.o_consts;
+  B->set_nwork_cap = bp.set_nwork;
+  B->set_off.clear();
   size_t set_off = 0;
-  std::vector<std::pair<size_t, std::vector<char>>> set_blobs;
   for (int s = 0; s <= B->pmax + 1; ++s) {
-    std::vector<char> blob;
-    long nwork = 0;
-    char* base = w + bp.o_sets + set_off;
-    if (B->inner == 32) {
-      sgk::PcgCols<float> c{};
-      rc = build_set<float>(B, s, base, blob, c, nwork);
-      c.consts = (const sgk::PcgConsts<float>*)(w + bp.o_consts);
-      c.active = V.active;
-      B->cols32.push_back(c);
-    } else {
-      sgk::PcgCols<double> c{};
-      rc = build_set<double>(B, s, base, blob, c, nwork);
-      c.consts = (const sgk::PcgConsts<double>*)(w + bp.o_consts);
-      c.active = V.active;
-      B->cols64.push_back(c);
-    }
-    if (rc == SG_OK && nwork > bp.set_nwork[s]) rc = fail(SG_EINVAL, "inner tiling exceeds the planned work list");
-    if (rc) {
-      sg_batch_destroy(B);
-      return rc;
-    }
-    set_blobs.push_back({set_off, std::move(blob)});
+    B->set_off.push_back(set_off);
     set_off += set_stride(bp.set_ncols[s]);
   }
   B->sc.part = (double*)(w + bp.o_pcg_part);
@@ -506,13 +547,15 @@ int sg_batch_setup(int32_t count, const sg_problem* probs, const sg_opts* opts, 
   if (e == hipSuccess) e = hipMemcpyAsync(tab_d, tab.data(), sizeof(void*) * tab.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(w + bp.o_consts, consts.data(), consts.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(B->pdeg, pdeg.data(), sizeof(int) * count, hipMemcpyHostToDevice, s);
-  for (auto& sb : set_blobs)
-    if (e == hipSuccess && !sb.second.empty())
-      e = hipMemcpyAsync(w + bp.o_sets + sb.first, sb.second.data(), sb.second.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     sg_batch_destroy(B);
     return fail(SG_EDEVICE, std::string("batch upload failed: ") + hipGetErrorString(e));
+  }
+  rc = upload_sets(B);
+  if (rc) {
+    sg_batch_destroy(B);
+    return rc;
   }
   *out = B;
   return SG_OK;
@@ -599,6 +642,94 @@ int sg_batch_solve(sg_batch B, const double* const* F, double* const* U, double 
   if (worst == SG_NOT_CONVERGED) sgh::fail(SG_NOT_CONVERGED, "a batch member did not converge");
   if (worst == SG_BREAKDOWN) sgh::fail(SG_BREAKDOWN, "breakdown in a batch member");
   return worst;
+}
+
+int sg_batch_autotune(sg_batch B, int32_t flags, sg_tune_report* report) {
+  if (!B) return fail(SG_EINVAL, "null batch");
+  if (flags & ~3) return fail(SG_EINVAL, "flags: bit 0 = SG operators, bit 1 = inner launches");
+  drop_graph(B);  // a new schedule needs a new capture
+  hipStream_t s = B->stream;
+  sg_tune_report R{};
+  // every problem takes part while the candidates are timed
+  std::vector<int> ones(B->nprob, 1);
+  SG_HIP(hipMemcpyAsync(B->V.active, ones.data(), sizeof(int) * B->nprob, hipMemcpyHostToDevice, s));
+  SG_HIP(hipStreamSynchronize(s));
+  if (flags & 1)
+    for (sg_ctx* h : B->h) {
+      sg_tune_report r{};
+      const int rc = sg_autotune(h, 1, &r);
+      if (rc) return rc;
+      R.candidates += r.candidates;
+      R.mv_ms += r.mv_ms;
+    }
+  if (flags & 2) {
+    // a constant right-hand side in every problem's inner input
+    for (sg_ctx* h : B->h) {
+      const long N = h->n * (long)h->P;
+      sgk::launch_fill(h->pv, 1.0, N, s);
+      if (B->inner == 32) sgk::launch_copy_d2f((float*)h->rw, h->pv, N, s);
+      else sgk::launch_copy_d2d((double*)h->rw, h->pv, N, s);
+    }
+    const int pc = B->opts.precond;
+    hipEvent_t e0 = B->h[0]->ev0, e1 = B->h[0]->ev1;
+    // one inner solve of every set a preconditioner action works on: the
+    // degree levels (HSC, block Gauss-Seidel) or all columns (mean-based)
+    auto pass = [&]() -> int {
+      const int first = pc == SG_PC_MEAN ? B->pmax + 1 : 0, last = pc == SG_PC_MEAN ? B->pmax + 1 : B->pmax;
+      for (int set = first; set <= last; ++set) {
+        const int rc = B->inner == 32 ? run_set<float>(B, set) : run_set<double>(B, set);
+        if (rc) return rc;
+      }
+      return SG_OK;
+    };
+    int bt = B->tile, br = B->rows, bb = B->max_blocks;
+    double best = 1e300;
+    const int ncu = B->h[0]->num_cu;
+    for (const auto& tr : batch_tilings(B->opts))
+      for (int mb : {0, std::max(1, ncu / 2)}) {
+        B->tile = tr.first;
+        B->rows = tr.first == 16 ? B->rows : tr.second;
+        B->max_blocks = mb;
+        int rc = upload_sets(B);
+        if (rc) return rc;
+        if ((rc = pass())) return rc;  // warm-up
+        std::vector<float> t;
+        for (int rep = 0; rep < 3; ++rep) {
+          SG_HIP(hipEventRecord(e0, s));
+          if ((rc = pass())) return rc;
+          SG_HIP(hipEventRecord(e1, s));
+          SG_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          SG_HIP(hipEventElapsedTime(&ms, e0, e1));
+          t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        ++R.candidates;
+        if (t[1] < best) {
+          best = t[1];
+          bt = B->tile;
+          br = B->rows;
+          bb = mb;
+        }
+      }
+    B->tile = bt;
+    B->rows = br;
+    B->max_blocks = bb;
+    const int rc = upload_sets(B);
+    if (rc) return rc;
+    R.pcg_ms = best;
+  }
+  // the schedule of the largest member stands for the SG operators
+  sg_ctx* big = B->h[0];
+  for (sg_ctx* h : B->h)
+    if (h->n * (long)h->P > big->n * (long)big->P) big = h;
+  R.mv_variant = big->mv_variant;
+  R.mv_param = sgh::mv_param(big);
+  R.pcg_tile = B->tile;
+  R.pcg_max_blocks = B->max_blocks;
+  R.pcg_rows = B->tile == 16 ? 16 : B->rows;
+  if (report) *report = R;
+  return SG_OK;
 }
 
 void sg_batch_destroy(sg_batch B) {

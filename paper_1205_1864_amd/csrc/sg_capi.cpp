@@ -86,6 +86,7 @@ struct Plan {
   size_t o_en_ptr, o_en_k, o_en_lo, o_en_up, o_en_glo64, o_en_gup64, o_en_glo32, o_en_gup32;
   size_t o_pair_ptr, o_pair_a, o_pair_b, o_pair_g;
   size_t o_mj_ptr, o_mj_rows, o_mj_kind, o_mj_lk, o_mj_lcol, o_mj_lw;
+  size_t o_stg_terms, o_stg_slots, o_stg_wslot;
   size_t o_vec[7];
   size_t o_rw, o_zw;
   size_t o_pcg[6];
@@ -178,6 +179,11 @@ void make_plan(const sg_problem* pr, const sg_opts* op, Plan& pl) {
   pl.o_mj_lk = L.take(sizeof(int) * mj_rows * sgk::kMarchNS);
   pl.o_mj_lcol = L.take(sizeof(int) * mj_rows * sgk::kMarchRGL * sgk::kMarchNS);
   pl.o_mj_lw = L.take(sizeof(double) * mj_rows * sgk::kMarchRGL * sgk::kMarchNS);
+  // row-staged operator: output pairs and their (padded) term lists
+  const long stg_slots = std::max(1, pl.P);
+  pl.o_stg_terms = L.take(sizeof(sgk::StageTerm) * (pl.P + 1L) * (2L * M + 1));
+  pl.o_stg_slots = L.take(sizeof(sgk::StageSlot) * stg_slots);
+  pl.o_stg_wslot = L.take(sizeof(int) * (sgk::kStageWaves + 1));
   for (int i = 0; i < 7; ++i) pl.o_vec[i] = L.take(sizeof(double) * nP);
   pl.o_rw = L.take(isz * nP);
   pl.o_zw = L.take(op->inner_precision == 32 ? isz * nP : 0);
@@ -271,6 +277,128 @@ void build_march_job(int M, int nx, const std::vector<int>& rows, bool lower, bo
 // Row groups of the y-marching SG operator for every use: job 0 is the matvec,
 // job 1 + 2 (l - 1) + dir the coupling product of level l in direction dir.
 // seg_per_xcd = 0 chooses the number of grid segments per XCD automatically.
+// Tables of the row-staged full operator. The slot of an output applies its
+// mean term (its own column, coefficient theta0); the term list holds the
+// Galerkin neighbours (b, k, g), b = a -+ e_k with the weight g of G_k (which
+// is symmetric), in ascending order of g. Two outputs share a slot (one per
+// half wave) when their weight sequences are equal, so a term's weight is one
+// value for both halves; an output left without a partner takes a slot alone.
+// The slots go, largest first, to the least loaded wave. Uploads into the
+// workspace and waits.
+int build_stage_tables(sg_ctx* h, sgk::StageTerm* terms_d, sgk::StageSlot* slots_d, int* wslot_d) {
+  h->stage_ok = false;
+  const int P = h->P, M = h->M;
+  // the kernel addresses the n x P blocks with 32-bit offsets; the tables use 16-bit indices
+  if (P >= 0xFFFF || M > 255 || h->n * (long)P >= (1L << 31)) return SG_OK;
+  struct Term {
+    int b, k;
+    double g;
+  };
+  std::vector<std::vector<Term>> tl(P);
+  for (int a = 0; a < P; ++a) {
+    for (int k = 0; k < M; ++k) {
+      const int lo = h->st_lo_h[(size_t)a * M + k], up = h->st_up_h[(size_t)a * M + k];
+      if (lo >= 0) tl[a].push_back({lo, k + 1, h->st_glo_h[(size_t)a * M + k]});
+      if (up >= 0) tl[a].push_back({up, k + 1, h->st_glo_h[(size_t)up * M + k]});
+    }
+    std::stable_sort(tl[a].begin(), tl[a].end(), [](const Term& x, const Term& y) { return x.g < y.g; });
+  }
+  auto same_sig = [&](int x, int y) {
+    if (tl[x].size() != tl[y].size()) return false;
+    for (size_t t = 0; t < tl[x].size(); ++t)
+      if (tl[x][t].g != tl[y][t].g) return false;
+    return true;
+  };
+  auto sig_less = [&](int x, int y) {  // longer lists first, then by weight sequence
+    if (tl[x].size() != tl[y].size()) return tl[x].size() > tl[y].size();
+    for (size_t t = 0; t < tl[x].size(); ++t)
+      if (tl[x][t].g != tl[y][t].g) return tl[x][t].g < tl[y][t].g;
+    return x < y;
+  };
+  std::vector<int> order(P);
+  for (int a = 0; a < P; ++a) order[a] = a;
+  std::sort(order.begin(), order.end(), sig_less);
+  struct Pair {
+    int out[2];
+    int nt;
+  };
+  std::vector<Pair> pairs;
+  for (int i = 0; i < P;) {
+    const bool two = i + 1 < P && same_sig(order[i], order[i + 1]);
+    pairs.push_back({{order[i], two ? order[i + 1] : -1}, (int)tl[order[i]].size()});
+    i += two ? 2 : 1;
+  }
+  std::stable_sort(pairs.begin(), pairs.end(), [](const Pair& x, const Pair& y) { return x.nt > y.nt; });
+  // each slot goes to the least loaded wave with a free slot (a slot also costs
+  // about eight terms of mean-term and element work)
+  constexpr int NW = sgk::kStageWaves;
+  std::vector<std::vector<int>> wav(NW);
+  std::vector<long> load(NW, 0);
+  for (size_t q = 0; q < pairs.size(); ++q) {
+    int best = -1;
+    for (int w2 = 0; w2 < NW; ++w2)
+      if ((int)wav[w2].size() < sgk::kStageSlots && (best < 0 || load[w2] < load[best])) best = w2;
+    if (best < 0) return SG_OK;  // more slots than the waves hold: the kernel is not used
+    wav[best].push_back((int)q);
+    load[best] += pairs[q].nt + 8;
+  }
+  std::vector<sgk::StageTerm> terms;
+  std::vector<sgk::StageSlot> slots;
+  std::vector<int> wslot(NW + 1, 0);
+  for (int w2 = 0; w2 < NW; ++w2) {
+    wslot[w2] = (int)slots.size();
+    for (int q : wav[w2]) {
+      const Pair& pr = pairs[q];
+      if (terms.size() + pr.nt > 0xFFFF) return SG_OK;  // 16-bit term indices
+      sgk::StageSlot sl{};
+      sl.out[0] = (unsigned short)pr.out[0];
+      sl.out[1] = pr.out[1] >= 0 ? (unsigned short)pr.out[1] : (unsigned short)0xFFFF;
+      sl.t0 = (unsigned short)terms.size();
+      sl.nt = (unsigned short)pr.nt;
+      slots.push_back(sl);
+      for (int t = 0; t < pr.nt; ++t) {
+        sgk::StageTerm tm{};
+        tm.g = tl[pr.out[0]][t].g;
+        for (int hf = 0; hf < 2; ++hf) {
+          const int a = pr.out[hf] >= 0 ? pr.out[hf] : pr.out[0];  // a lone output's idle half repeats it
+          tm.b[hf] = (unsigned short)tl[a][t].b;
+          tm.k[hf] = (unsigned char)tl[a][t].k;
+        }
+        terms.push_back(tm);
+      }
+    }
+  }
+  wslot[NW] = (int)slots.size();
+  if ((long)terms.size() > (P + 1L) * (2L * M + 1) || (long)slots.size() > (long)P)
+    return fail(SG_EINVAL, "internal: staged term list larger than planned");
+  if (sgk::stage_lds_bytes(P, M, (int)terms.size(), (int)slots.size()) == 0) return SG_OK;  // does not fit LDS
+  if (!terms.empty())
+    SG_HIP(hipMemcpyAsync(terms_d, terms.data(), sizeof(sgk::StageTerm) * terms.size(), hipMemcpyHostToDevice,
+                          h->stream));
+  SG_HIP(hipMemcpyAsync(slots_d, slots.data(), sizeof(sgk::StageSlot) * slots.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  SG_HIP(hipMemcpyAsync(wslot_d, wslot.data(), sizeof(int) * wslot.size(), hipMemcpyHostToDevice, h->stream));
+  SG_HIP(hipStreamSynchronize(h->stream));
+  h->stage.terms = terms_d;
+  h->stage.slots = slots_d;
+  h->stage.wslot = wslot_d;
+  h->stage.P = P;
+  h->stage.M = M;
+  h->stage.nterms = (int)terms.size();
+  h->stage.nslots = (int)slots.size();
+  h->stage_ok = true;
+  return SG_OK;
+}
+
+// Node rows per piece of the row-staged operator (0 turns it off).
+void set_stage_rows(sg_ctx* h, int rows) {
+  h->mv_stage = h->stage_ok && rows > 0 ? rows : 0;
+  if (!h->mv_stage) return;
+  h->stage.TY = rows;
+  h->stage.nseg = (h->nx + sgk::kStageOut - 1) / sgk::kStageOut;
+  h->stage.nyseg = (h->nx + rows - 1) / rows;
+}
+
 int build_march_jobs(sg_ctx* h, int seg_per_xcd) {
   h->march_ok = false;
   h->mjobs.clear();
@@ -722,6 +850,10 @@ void matvec(sg_ctx* h, const double* U, double* Y) {
   a.a = h->a64;
   a.lists = lists<double>(h);
   a.active = h->mask;
+  if (h->mv_stage > 0) {
+    sgk::launch_stage(a, h->stage, h->stream);
+    return;
+  }
   sgk::launch_sgop<double>(a, strip_tables<double>(h), h->march_ok ? &h->mjobs[0] : nullptr, h->stream);
 }
 
@@ -1110,6 +1242,7 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     return SG_OK;
   };
   if (flags & 1) {
+    set_stage_rows(h, 0);  // the candidates below run the full operator through their own kernels
     sgk::launch_fill(h->pv, 1.0, N, s);
     struct Cand {
       int variant, param;
@@ -1156,9 +1289,28 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     int rc = apply(pick);
     if (rc) return rc;
     R.mv_ms = cands.empty() ? 0.0 : best;
+    // the full operator may then take the row-staged kernel (the couplings keep the pick)
+    int best_rows = 0;
+    if (h->stage_ok)
+      for (int rows : {4, 6, 8, 10, 12, 16}) {
+        if (rows > std::max(4, h->nx)) continue;
+        set_stage_rows(h, rows);
+        matvec(h, h->pv, h->q);
+        matvec(h, h->pv, h->q);
+        double med = 0.0;
+        rc = event_ms([&] { matvec(h, h->pv, h->q); }, 5, &med);
+        if (rc) return rc;
+        ++R.candidates;
+        if (med < best) {
+          best = med;
+          best_rows = rows;
+        }
+      }
+    set_stage_rows(h, best_rows);
+    R.mv_ms = best < 1e300 ? best : 0.0;
   }
-  R.mv_variant = h->mv_variant;
-  R.mv_param = mv_param(h);
+  R.mv_variant = h->mv_stage > 0 ? 4 : h->mv_variant;
+  R.mv_param = h->mv_stage > 0 ? h->mv_stage : mv_param(h);
   const int degree = effective_degree(h);
   if (flags & 2) {
     const int lev = h->p;
@@ -1171,7 +1323,8 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
     const int band = h->opts.tile == 32 ? 32 : 0;
     std::vector<int> tiles = degree <= sgk::kBandMaxDegree ? std::vector<int>{band, 16}
                                                                                        : std::vector<int>{16};
-    std::vector<int> blocks = {0, std::max(1, h->num_cu / 2)};
+    // automatic grid, half the compute units, whole columns per block (large launches)
+    std::vector<int> blocks = {0, std::max(1, h->num_cu / 2), -1};
     double best = 1e300;
     int bt = choose_tile(h, degree), bb = h->pcg_max_blocks;
     for (int t : tiles)
@@ -1472,6 +1625,19 @@ int sg_setup(const sg_problem* pr, const sg_opts* op, void* workspace, size_t wo
   h->mj_lw_d = (double*)(w + pl.o_mj_lw);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess && build_march_jobs(h, 0) != SG_OK) e = hipErrorUnknown;
+  if (e == hipSuccess &&
+      build_stage_tables(h, (sgk::StageTerm*)(w + pl.o_stg_terms), (sgk::StageSlot*)(w + pl.o_stg_slots),
+                         (int*)(w + pl.o_stg_wslot)) != SG_OK)
+    e = hipErrorUnknown;
+  if (e == hipSuccess) {
+    // the full operator takes the row-staged kernel where it fits and its pieces
+    // of 10 node rows keep at least half of the compute units busy (one block per
+    // CU); the autotuner chooses among 4..16 rows or the other kernels
+    const long pieces10 = (long)((h->nx + sgk::kStageOut - 1) / sgk::kStageOut) * ((h->nx + 9) / 10);
+    int rows = 2 * pieces10 >= h->num_cu ? 10 : 0;
+    if (const char* env = std::getenv("SGPC_MV_STAGE")) rows = std::atoi(env);
+    set_stage_rows(h, rows);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete h;

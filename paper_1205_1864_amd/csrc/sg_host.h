@@ -32,6 +32,8 @@ template <typename T>
 void fill_pcg_consts(const sg_ctx* h, sgk::PcgArgs<T>& a);
 // Chebyshev degree actually used, and the inner tile edge for that degree.
 int effective_degree(const sg_ctx* h);
+// Schedule parameter of the SG operator variant in use (as in sg_tune_report).
+int mv_param(const sg_ctx* h);
 int choose_tile(const sg_ctx* h, int degree);
 // Up to three FP64 dot products over the handle's n x P blocks, read back into h->host_out.
 int dots(sg_ctx* h, int nd, const double* a0, const double* b0, const double* a1 = nullptr,

@@ -151,6 +151,44 @@ struct MarchJob {
 template <typename T>
 void launch_sgop(const SgOpArgs<T>& args, const StripTables<T>& tab, const MarchJob* job, hipStream_t s);
 
+// Row-staged SG operator (the full FP64 operator Y = sum_k K_k U G_k^T): a block
+// of kStageWaves waves stages node rows of all P chaos columns, for a segment of
+// 32 node columns (30 outputs plus a halo node on each side), in LDS; every half
+// wave (32 lanes) accumulates one output column's element sums from the staged
+// rows, term by term. The mean term of an output (its own column, coefficient
+// theta0) is handled by its slot; the slot's term list holds the Galerkin
+// neighbours. A slot pairs two outputs (one per half) whose neighbour weights
+// are equal in order, so a term's weight is one value for both halves; the
+// input column and the KL row differ per half. The term and slot tables are
+// copied into LDS at the start of the kernel.
+constexpr int kStageWaves = 16;
+constexpr int kStageLanes = 32;            // node columns per staged segment (lanes of a half wave)
+constexpr int kStageOut = kStageLanes - 2; // output node columns per segment
+constexpr int kStageSlots = 10;            // output pairs per wave
+constexpr int kStagePre = 9;               // staged values per thread and row: P * 32 <= 9 * 1024
+struct StageTerm {       // 16 bytes
+  unsigned short b[2];   // per half: input column
+  unsigned char k[2];    // per half: KL index (1..M)
+  unsigned short pad;
+  double g;              // Galerkin weight of the term for both halves
+};
+struct StageSlot {       // 8 bytes
+  unsigned short out[2]; // output chaos index per half (0xFFFF: none)
+  unsigned short t0, nt; // first term and term count
+};
+struct StageJob {
+  const StageTerm* terms;
+  const StageSlot* slots;
+  const int* wslot;  // [kStageWaves + 1]: slot range of each wave
+  int P, M;
+  int nterms, nslots;
+  int TY;            // output node rows per piece
+  int nseg, nyseg;   // pieces: nseg segments by nyseg row bands
+};
+// LDS bytes of the row-staged kernel, 0 if the problem does not fit it.
+size_t stage_lds_bytes(int P, int M, int nterms, int nslots);
+void launch_stage(const SgOpArgs<double>& args, const StageJob& job, hipStream_t s);
+
 // Largest number of KL terms served by the piece kernel (dense [P][M] tables).
 constexpr int kPieceMaxM = 12;
 
@@ -187,6 +225,7 @@ struct PcgArgs {
   int maxit;
   double rtol;
   int warm;    // start each column from the contents of its x (banded tiles), else from 0
+  long per_block;  // work items (tiles) per block; 0 = the work list split evenly over the grid
   T c0;        // centre weight of K_0: theta0 * 8/3
   T c1;        // neighbour weight of K_0: -theta0 / 3
   T inv_diag;  // 1 / (theta0 * 8/3)
@@ -245,7 +284,7 @@ hipError_t launch_pcg(const PcgArgs<T>& args, int tile, int max_blocks, hipStrea
 // the scratch come from `args`. A regular launch whose grid fits on the device
 // at once (so it can be captured into a graph); every wait is bounded.
 template <typename T>
-hipError_t launch_pcg_ragged(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile, hipStream_t s);
+hipError_t launch_pcg_ragged(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile, int max_blocks, hipStream_t s);
 
 template <typename T>
 size_t pcg_scratch_bytes(int ncols, int ntiles);
@@ -359,6 +398,10 @@ struct sg_ctx {
   int mv_seg_per_xcd = 0;  // grid segments per XCD of the y-marching kernel (0 = automatic)
   int mv_piece_rows = 0;   // node rows per piece of the piece kernel (0 = default 16)
   int mv_piece_waves = 0;  // cap on resident waves per CU of the piece kernel (0 = as many as fit)
+  // row-staged kernel for the full operator (sg_matvec and the outer CG products)
+  bool stage_ok = false;   // tables built and the sizes fit
+  int mv_stage = 0;        // node rows per piece when the full operator uses it, 0 = off
+  sgk::StageJob stage{};
   std::vector<sgk::MarchJob> mjobs;
   std::vector<int> st_lo_h, st_up_h;  // host copies of the dense neighbour tables (row groups)
   std::vector<double> st_glo_h;

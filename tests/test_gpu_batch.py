@@ -41,13 +41,15 @@ def _rhs(probs):
     return F
 
 
-@pytest.mark.parametrize("prec,pc,warm", [(64, "hsc", False), (32, "hsc", False), (64, "mean", False),
-                                          (64, "bgs", False), (32, "bgs", False), (64, "hsc", True),
-                                          (32, "hsc", True), (64, "bgs", True)])
-def test_batch_matches_single_solves(prec, pc, warm):
+@pytest.mark.parametrize("prec,pc,warm,tile", [(64, "hsc", False, 0), (32, "hsc", False, 0), (64, "mean", False, 0),
+                                               (64, "bgs", False, 0), (32, "bgs", False, 0), (64, "hsc", True, 0),
+                                               (32, "hsc", True, 0), (64, "bgs", True, 0), (64, "hsc", False, 16),
+                                               (32, "bgs", False, 16)])
+def test_batch_matches_single_solves(prec, pc, warm, tile):
     b = _b()
     probs = _problems()
-    opts = b.Options(inner_precision=prec, precond=pc, inner_rtol=1e-4, warm_start=warm)
+    print(f"batch vs single prec={prec} pc={pc} warm={warm} tile={tile}", flush=True)
+    opts = b.Options(inner_precision=prec, precond=pc, inner_rtol=1e-4, warm_start=warm, tile=tile)
     batch = b.SGBatch(probs, opts)
     F = _rhs(probs)
     U, stats, info = batch.sg_batch_solve(F, rtol=1e-8, maxit=100, use_graph=True)
@@ -93,6 +95,38 @@ def test_batch_against_oracle_direct_solve():
         assert tr <= 1.05e-8 and abs(st["true_relres"] - tr) <= 1e-3 * tr
         err = np.linalg.norm(u.cpu().numpy().T - Ud) / np.linalg.norm(Ud)
         assert err <= ev.max() / ev.min() * 1.05e-8
+
+
+@pytest.mark.parametrize("prec,pc", [(32, "hsc"), (64, "hsc"), (64, "mean"), (32, "bgs")])
+def test_batch_autotune_keeps_parity(prec, pc):
+    """The tuned batch schedules (every member's SG operator; tile kind, band
+    height and block cap of the ragged inner launches) solve the same systems:
+    every member reaches 1e-8 on the oracle's operator and matches the oracle's
+    direct solve within its condition number times 1.05e-8."""
+    b = _b()
+    kws = [dict(n_e=16, M=4, p=2, sigma=0.2, L=0.5), dict(n_e=12, M=3, p=3, sigma=0.25, L=0.3),
+           dict(n_e=9, M=2, p=1, sigma=0.2, L=0.6), dict(n_e=33, M=3, p=2, sigma=0.2, L=0.4)]
+    probs = [make_problem(f"t{i}", **kw) for i, kw in enumerate(kws)]
+    print(f"batch autotune prec={prec} pc={pc}", flush=True)
+    batch = b.SGBatch(probs, b.Options(inner_precision=prec, precond=pc, inner_rtol=1e-4))
+    rep = batch.sg_batch_autotune(3)
+    assert rep["candidates"] >= 2 + len(probs) and rep["pcg_ms"] > 0 and rep["mv_ms"] > 0
+    assert rep["pcg_tile"] in (16, 32) and rep["pcg_rows"] in (16, 64, 128, 256)
+    assert rep["mv_variant"] in (0, 1, 2, 3, 4)
+    F = [b.to_device_block(pr.load_block()) for pr in probs]
+    for use_graph in (True, False):
+        U, stats, info = batch.sg_batch_solve(F, rtol=1e-8, maxit=100, use_graph=use_graph)
+        assert info["rc"] == 0
+        for pr, u, st in zip(probs, U, stats):
+            s = sg.build_system(pr)
+            Fh = pr.load_block()
+            tr = solve.true_relres(s, Fh.T, u.cpu().numpy().T)
+            assert tr <= 1.05e-8 and abs(st["true_relres"] - tr) <= 1e-3 * tr
+            Ud = solve.solve_direct(s, Fh.T.copy())
+            ev = np.linalg.eigvalsh(sg.assemble(s).toarray())
+            err = np.linalg.norm(u.cpu().numpy().T - Ud) / np.linalg.norm(Ud)
+            assert err <= ev.max() / ev.min() * 1.05e-8
+    batch.close()
 
 
 def test_batch_graph_replay_equals_eager():

@@ -108,7 +108,8 @@ def test_lognormal_solve_matches_oracle(case, pc):
 
 
 def test_lognormal_solve_edge_cases():
-    """Zero right-hand side, an iteration cap, and argument checks."""
+    """Zero right-hand side, an iteration cap, argument checks, and a NaN in the
+    right-hand side."""
     import torch
     from paper_1205_1864_amd import binding as b
     prob = named_problem("small", n_e=8, M=2, p=2, L=0.5)
@@ -123,4 +124,9 @@ def test_lognormal_solve_edge_cases():
         op.solve(F, U=F)
     with pytest.raises(b.SGError):
         op.solve(F, inner_rtol=1.5)
+    # a non-finite right-hand side is rejected, not reported as converged
+    Fn = prob.load_block()
+    Fn[1, 5] = np.nan
+    with pytest.raises(b.SGError):
+        op.solve(b.to_device_block(Fn))
     op.close()

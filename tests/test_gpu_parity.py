@@ -45,10 +45,28 @@ def test_matvec_parity(kw):
     assert np.linalg.norm(Y - Yo) <= 1e-12 * np.linalg.norm(Yo)
 
 
-def test_matvec_parity_scale():
+@pytest.mark.parametrize("kw", SHAPES)
+@pytest.mark.parametrize("rows", [1, 5, 16])
+def test_matvec_parity_staged(kw, rows, monkeypatch):
+    """The row-staged operator kernel (forced, with pieces of 1, 5 and 16 node
+    rows) against the oracle on every shape."""
+    monkeypatch.setenv("SGPC_MV_STAGE", str(rows))
+    b = _b()
+    prob, s = _sys(**kw)
+    print(f"staged matvec parity n_e={prob.n_e} M={prob.M} p={prob.p} rows={rows}", flush=True)
+    solver = b.SGSolver(prob)
+    U = random_block(prob.P, prob.n, seed=11)
+    Y = solver.sg_matvec(_dev(U)).cpu().numpy()
+    Yo = sg.matvec(s, U.T).T
+    assert np.linalg.norm(Y - Yo) <= 1e-12 * np.linalg.norm(Yo)
+
+
+@pytest.mark.parametrize("rows", [0, 10])
+def test_matvec_parity_scale(rows, monkeypatch):
+    monkeypatch.setenv("SGPC_MV_STAGE", str(rows))
     b = _b()
     prob = named_problem("scale")
-    print("matvec parity 256^2 M=10 p=3", flush=True)
+    print(f"matvec parity 256^2 M=10 p=3 staged rows={rows}", flush=True)
     s = sg.build_system(prob)
     solver = b.SGSolver(prob)
     U = random_block(prob.P, prob.n, seed=0)
@@ -125,6 +143,43 @@ def test_inner_solve_tall_grid(prec, tol, degree, tile):
     assert list(its) == list(st.iterations)
     for c in range(3):
         assert np.linalg.norm(X[c] - Xo[c]) <= tol * np.linalg.norm(Xo[c])
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("degree", [16, 3])
+def test_inner_schedules_bitwise_equal(prec, degree, monkeypatch):
+    """The inner launch schedules (the automatic grid, a cap of 128 blocks, and
+    whole columns per block, whose column phases need no device-scope counters)
+    run the same arithmetic per column: bitwise equal iterates and iteration
+    counts, for the 220 top-level columns of the 256^2 benchmark grid, at fixed
+    iteration counts and to a tolerance; the first schedule's fixed-iteration
+    iterates also agree with the oracle's PCG on sampled columns."""
+    b = _b()
+    prob = named_problem("scale")
+    B = random_block(220, prob.n, seed=3)
+    Bd = _dev(B)
+    res = []
+    for mb in ("0", "128", "-1"):
+        print(f"inner schedule max_blocks={mb} prec={prec} degree={degree}", flush=True)
+        monkeypatch.setenv("SGPC_PCG_MAX_BLOCKS", mb)
+        solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=degree, inner_maxit=12, inner_rtol=0.0))
+        X12, its12 = solver.sg_inner_solve(Bd)
+        solver.set_opts(b.Options(inner_precision=prec, cheb_degree=degree, inner_maxit=2000, inner_rtol=1e-4))
+        Xt, itst = solver.sg_inner_solve(Bd)
+        res.append((X12.cpu(), list(its12), Xt.cpu(), list(itst)))
+        solver.close()
+    for X12, its12, Xt, itst in res[1:]:
+        assert bool((X12 == res[0][0]).all()) and its12 == res[0][1]
+        assert bool((Xt == res[0][2]).all()) and itst == res[0][3]
+    assert all(i == 12 for i in res[0][1])
+    K0 = sg.build_system(prob).K[0]
+    prec_o = krylov.make_chebyshev(K0, prob.n_e, prob.theta0, degree)
+    cols = [0, 97, 219]
+    st = krylov.InnerStats()
+    Xo = krylov.pcg_columns(K0, B[cols].T, prec_o, 0.0, 12, st).T
+    tol = 1e-11 if prec == 64 else 2e-5
+    for j, c in enumerate(cols):
+        assert np.linalg.norm(res[0][0][c].numpy() - Xo[j]) <= tol * np.linalg.norm(Xo[j])
 
 
 @pytest.mark.parametrize("prec", [64, 32])
@@ -360,7 +415,7 @@ def test_autotune_keeps_parity(kw, prec):
     solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=8, inner_rtol=1e-4))
     rep = solver.sg_autotune(3)
     assert rep["candidates"] >= 2 and rep["pcg_tile"] in (16, 32) and rep["pcg_ms"] > 0
-    assert rep["mv_variant"] in (0, 1, 2, 3)
+    assert rep["mv_variant"] in (0, 1, 2, 3, 4)
     U = random_block(prob.P, prob.n, seed=4)
     Y = solver.sg_matvec(_dev(U)).cpu().numpy()
     Yo = sg.matvec(s, U.T.copy()).T
