@@ -41,8 +41,10 @@ CHEB_DEGREE = 16  # updates of the Chebyshev preconditioner of the inner PCG (fa
 # runs of this benchmark, scaled by the same counters of a 512 MiB elementwise
 # kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Set to None when the
 # kernel changes.
-PCG_TRAFFIC_BYTES = 15.41e9     # pcg_kernel<double, BandTile<double, 128 | 64, 15, 16>, 1>, average over a solve's launches
-MATVEC_TRAFFIC_BYTES = {(2, 2): 570.4e6, (2, 1): 543.0e6}  # sgop_march_kernel<double, 10>, one SG matvec, by schedule
+PCG_TRAFFIC_BYTES = 15.00e9     # pcg_kernel<double, BandTile<double, 128 | 64, 15, 16>, 1>, average over a solve's launches
+# one SG matvec, by schedule (mv_variant, mv_param): the row-staged kernel with 10-row pieces,
+# and the y-marching kernel it replaced
+MATVEC_TRAFFIC_BYTES = {(4, 10): 354.2e6, (2, 2): 570.4e6, (2, 1): 543.0e6}
 
 
 def log(msg):
