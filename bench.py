@@ -299,11 +299,16 @@ def main():
                                                    inner_maxit=2000, warm_start=True)),
                          # the same solves with a degree-8 Chebyshev preconditioner
                          ("hsc_fp64_d8", Options(inner_precision=64, cheb_degree=8, precond="hsc", inner_maxit=2000)),
-                         ("hsc_fp32_d8", Options(inner_precision=32, cheb_degree=8, precond="hsc", inner_maxit=2000))]:
+                         ("hsc_fp32_d8", Options(inner_precision=32, cheb_degree=8, precond="hsc", inner_maxit=2000)),
+                         # the preconditioner action captured once and replayed from a HIP graph
+                         ("hsc_fp64_graph", Options(inner_precision=64, cheb_degree=CHEB_DEGREE, precond="hsc",
+                                                    inner_maxit=2000, use_graph=True)),
+                         ("hsc_fp32_graph", Options(inner_precision=32, cheb_degree=CHEB_DEGREE, precond="hsc",
+                                                    inner_maxit=2000, use_graph=True))]:
             sv = SGSolver(prob, o)
             sv.sg_autotune(3)
             Uv = sv.empty()
-            sv.sg_solve(F, Uv, rtol=1e-8, maxit=200)
+            sv.sg_solve(F, Uv, rtol=1e-8, maxit=200)  # warm-up (and the capture of a graph)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             _, sv_st = sv.sg_solve(F, Uv, rtol=1e-8, maxit=200)
@@ -316,8 +321,9 @@ def main():
             extra[f"true_relres_{label}"] = sv_st["true_relres"]
             extra[f"rel_diff_vs_fp64_hsc_{label}"] = float(torch.linalg.norm(Uv - U64) / torch.linalg.norm(U64))
             vs_oracle(label, Uv, sv_st["true_relres"], extra)
-            # algorithmic inner-PCG bandwidth of this variant (library byte count over its HIP-event time)
-            if sv_st["ms_inner"] > 0:
+            # algorithmic inner-PCG bandwidth of this variant (library byte count over its HIP-event
+            # time; a replayed graph is timed per action, so it has no per-launch figure)
+            if sv_st["ms_inner"] > 0 and not o.use_graph:
                 gbs = sv_st["inner_bytes"] / (sv_st["ms_inner"] * 1e-3) / 1e9
                 extra[f"pcg_GBs_{label}"] = gbs
                 extra[f"pcg_frac_{label}"] = gbs / HBM_PEAK_GBS

@@ -111,7 +111,17 @@ typedef struct sg_problem {
  *                     The stopping test stays relative to the right-hand side.
  *   inner_rtol        relative residual at which an inner solve stops
  *                     (recursive residual, Euclidean norm); <= 0 runs
- *                     exactly inner_maxit iterations. */
+ *                     exactly inner_maxit iterations.
+ *   use_graph         0 or 1: sg_solve captures one preconditioner action
+ *                     (all its inner launches, couplings and read-backs) into
+ *                     a HIP graph on the handle's stream the first time it is
+ *                     applied and replays the graph in every later outer
+ *                     iteration and solve (until the options or the schedule
+ *                     change). Needs a stream other than the default one. The
+ *                     inner launches of a captured action are ordinary (not
+ *                     cooperative) launches of at most the resident grid.
+ *                     Results are the same bit for bit.
+ *   reserved          must be 0. */
 typedef struct sg_opts {
   int32_t inner_precision;
   int32_t cheb_degree;
@@ -120,6 +130,8 @@ typedef struct sg_opts {
   int32_t tile;
   int32_t warm_start;
   double inner_rtol;
+  int32_t use_graph;
+  int32_t reserved;
 } sg_opts;
 
 /* Statistics of a solve. Counters are totals over the call. */
@@ -136,7 +148,8 @@ typedef struct sg_stats {
   double ms;                  /* wall time of the call in milliseconds */
   double ms_precond;          /* time in preconditioner actions */
   double ms_matvec;           /* time in SG matvecs */
-  double ms_inner;            /* device time of the inner PCG launches (HIP events on the stream) */
+  double ms_inner;            /* device time of the inner PCG launches (HIP events on the stream; with
+                                 use_graph, of the replayed preconditioner actions as a whole) */
   double inner_bytes;         /* algorithmic bytes of those launches: per column (9 its + 6) n w
                                  with banded tiles, (10 its + 6) n w with 16 x 16 tiles (3 n w
                                  when it stops at once; n w more from a warm start) */

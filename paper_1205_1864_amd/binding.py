@@ -35,7 +35,8 @@ class SgProblem(ctypes.Structure):
 class SgOpts(ctypes.Structure):
     _fields_ = [("inner_precision", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
                 ("inner_maxit", ctypes.c_int32), ("precond", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+                ("warm_start", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SgStats(ctypes.Structure):
@@ -153,10 +154,11 @@ class Options:
     tile: int = 0
     inner_rtol: float = 1e-4
     warm_start: bool = False
+    use_graph: bool = False
 
     def to_c(self) -> SgOpts:
         return SgOpts(self.inner_precision, self.cheb_degree, self.inner_maxit, _PC[self.precond],
-                      self.tile, int(bool(self.warm_start)), float(self.inner_rtol))
+                      self.tile, int(bool(self.warm_start)), float(self.inner_rtol), int(bool(self.use_graph)), 0)
 
 
 def _dptr(t: torch.Tensor) -> int:
@@ -197,7 +199,12 @@ class SGSolver:
         nb = ctypes.c_size_t(0)
         _check(lib.sg_workspace_bytes(ctypes.byref(cp), ctypes.byref(co), ctypes.byref(nb)))
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if stream is None:
+            # a captured graph needs a stream of its own
+            stream = torch.cuda.Stream(device=self.device) if self.opts.use_graph else \
+                torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         h = ctypes.c_void_p()
         _check(lib.sg_setup(ctypes.byref(cp), ctypes.byref(co), ctypes.c_void_p(self.workspace.data_ptr()),
                             ctypes.c_size_t(int(nb.value)), ctypes.c_void_p(self.stream.cuda_stream),
@@ -285,8 +292,11 @@ class SGSolver:
     def sg_solve(self, F, U=None, rtol=1e-8, maxit=200, use_x0=False):
         U = self.empty() if U is None else U
         st = SgStats()
+        caller = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(caller)  # F and U come from the caller's stream
         rc = _check(lib.sg_solve(self.handle, _dptr(self._block(F)), _dptr(self._block(U)), float(rtol),
                                  int(maxit), int(bool(use_x0)), ctypes.byref(st)), allow_positive=True)
+        caller.wait_stream(self.stream)
         d = st.as_dict()
         d["rc"] = rc
         return U, d

@@ -1157,7 +1157,7 @@ hipError_t launch_cfg(const PcgArgs<T>& args, const PcgCols<T>& cols, int max_bl
   PcgCols<T> c = cols;
   int lg = lds_group;
   hipLaunchKernelGGL(pcg_reset_kernel, dim3(1), dim3(256), 0, s, a.sc.arrivals, a.ncols, a.sc.status);
-  if (!RAGGED) {
+  if (!RAGGED && !args.no_coop) {
     void* kargs[] = {&a, &c, &lg};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3((unsigned)grid),
                                       dim3(Tile::kThreads * G), kargs, (unsigned)sm, s);

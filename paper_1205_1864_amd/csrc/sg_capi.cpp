@@ -116,6 +116,8 @@ int validate(const sg_problem* pr, const sg_opts* op) {
   if (op->tile != 0 && op->tile != 16 && op->tile != 32) return fail(SG_EINVAL, "tile must be 0, 16 or 32");
   if (op->warm_start != 0 && op->warm_start != 1) return fail(SG_EINVAL, "warm_start must be 0 or 1");
   if (!(op->inner_rtol < 1.0) || std::isnan(op->inner_rtol)) return fail(SG_EINVAL, "inner_rtol must be < 1");
+  if (op->use_graph != 0 && op->use_graph != 1) return fail(SG_EINVAL, "use_graph must be 0 or 1");
+  if (op->reserved != 0) return fail(SG_EINVAL, "reserved must be 0");
   return SG_OK;
 }
 
@@ -565,24 +567,29 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;
   a.warm = warm && h->opts.warm_start && tile != 16;
   fill_pcg_consts<T>(h, a);
-  // room for this launch's read-back, else settle the earlier ones first
+  a.no_coop = h->capturing ? 1 : 0;
+  // room for this launch's read-back, else settle the earlier ones first (not
+  // possible inside a graph capture: the action is then too large to capture)
   if ((int)h->pending.size() >= sg_ctx::kMaxPending || (int)h->pending.size() * 2 + 2 > h->nev ||
       h->iters_used + ncols > h->iters_cap) {
+    if (h->capturing) return fail(SG_EINVAL, "preconditioner action too large for graph capture");
     int rc = flush_inner(h);
     if (rc) return rc;
   }
   const int k = (int)h->pending.size();
   hipEvent_t e0 = h->evpool[2 * k], e1 = h->evpool[2 * k + 1];
-  SG_HIP(hipEventRecord(e0, h->stream));
+  // events recorded by graph nodes cannot be timed: a captured action is timed as a whole
+  const bool timed = !h->capturing;
+  if (timed) SG_HIP(hipEventRecord(e0, h->stream));
   SG_HIP(sgk::launch_pcg<T>(a, tile, h->pcg_max_blocks, h->stream));
-  SG_HIP(hipEventRecord(e1, h->stream));
-  sg_ctx::PendingLaunch L{ncols, level_for_stats, tile, a.warm, (int)sizeof(T), h->iters_used};
+  if (timed) SG_HIP(hipEventRecord(e1, h->stream));
+  sg_ctx::PendingLaunch L{ncols, level_for_stats, tile, a.warm, (int)sizeof(T), h->iters_used, timed};
   SG_HIP(hipMemcpyAsync(h->iters_host + L.slot, buf.sc.iters, sizeof(int) * ncols, hipMemcpyDeviceToHost,
                         h->stream));
   SG_HIP(hipMemcpyAsync(h->status_host + k, buf.sc.status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   h->pending.push_back(L);
   h->iters_used += ncols;
-  if (h->defer > 0 && !iters_out) return SG_OK;
+  if ((h->defer > 0 || h->capturing) && !iters_out) return SG_OK;
   if (iters_out) iters_out->assign(ncols, 0);
   const long slot = L.slot;
   int rc = flush_inner(h);
@@ -602,9 +609,11 @@ int flush_inner(sg_ctx* h) {
   for (size_t k = 0; k < h->pending.size(); ++k) {
     const sg_ctx::PendingLaunch& L = h->pending[k];
     if (h->status_host[k] != 0) bad = 1;
-    float ms = 0.f;
-    SG_HIP(hipEventElapsedTime(&ms, h->evpool[2 * k], h->evpool[2 * k + 1]));
-    h->inner_ms_acc += ms;
+    if (L.timed) {
+      float ms = 0.f;
+      SG_HIP(hipEventElapsedTime(&ms, h->evpool[2 * k], h->evpool[2 * k + 1]));
+      h->inner_ms_acc += ms;
+    }
     h->inner_launch_acc += 1;
     int mx = 0;
     for (int c = 0; c < L.ncols; ++c) {
@@ -830,6 +839,75 @@ int apply_mean(sg_ctx* h, const double* R, double* Z, long* nbs) {
   }
   const int rf = flush_inner(h);
   return rc ? rc : rf;
+}
+
+// Drops the captured preconditioner action (options or schedules changed).
+void drop_pc_graph(sg_ctx* h) {
+  if (h->pc_exec) (void)hipGraphExecDestroy(h->pc_exec);
+  if (h->pc_graph) (void)hipGraphDestroy(h->pc_graph);
+  h->pc_exec = nullptr;
+  h->pc_graph = nullptr;
+  h->pc_kind = -1;
+  h->pc_pending.clear();
+}
+
+// One preconditioner action of kind pc replayed from a HIP graph: captured on
+// the first call (or when the kind or the buffers change), then launched; the
+// read-back records of the captured inner launches are settled after every
+// replay exactly as after an eager action.
+int apply_graph(sg_ctx* h, int pc, const double* R, double* Z, long* nbmv, long* nbs) {
+  if (!h->stream) return fail(SG_EINVAL, "use_graph needs a stream other than the default stream");
+  if (!h->pc_exec || h->pc_kind != pc || h->pc_R != R || h->pc_Z != Z) {
+    drop_pc_graph(h);
+    int rc = flush_inner(h);
+    if (rc) return rc;
+    long bm = 0, bs = 0;
+    SG_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+    h->capturing = true;
+    if (pc == SG_PC_HSC) rc = apply_hsc_body(h, R, Z, &bm, &bs);
+    else if (pc == SG_PC_BGS) rc = apply_bgs_body(h, R, Z, &bm, &bs);
+    else rc = apply_mean_body(h, R, Z, &bs);
+    h->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    std::vector<sg_ctx::PendingLaunch> recs = h->pending;
+    const long used = h->iters_used;
+    h->pending.clear();  // nothing of the capture has run
+    h->iters_used = 0;
+    if (rc || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      if (rc) return rc;
+      return fail(SG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(SG_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ei));
+    }
+    h->pc_graph = g;
+    h->pc_exec = x;
+    h->pc_kind = pc;
+    h->pc_R = R;
+    h->pc_Z = Z;
+    h->pc_pending = recs;
+    h->pc_iters_used = used;
+    h->pc_nbmv = bm;
+    h->pc_nbs = bs;
+  }
+  SG_HIP(hipEventRecord(h->ev0, h->stream));
+  SG_HIP(hipGraphLaunch(h->pc_exec, h->stream));
+  SG_HIP(hipEventRecord(h->ev1, h->stream));
+  h->pending = h->pc_pending;
+  h->iters_used = h->pc_iters_used;
+  if (nbmv) *nbmv += h->pc_nbmv;
+  if (nbs) *nbs += h->pc_nbs;
+  const int rc = flush_inner(h);  // synchronises the stream
+  if (rc) return rc;
+  float ms = 0.f;
+  SG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->inner_ms_acc += ms;  // the whole replayed action (its inner launches are not timed one by one)
+  return SG_OK;
 }
 
 void matvec(sg_ctx* h, const double* U, double* Y) {
@@ -1066,6 +1144,7 @@ int fcg(sg_ctx* h, const double* F, double* U, double rtol, int maxit, int use_x
     return SG_OK;
   };
   auto prec = [&](const double* r, double* z) {
+    if (h->opts.use_graph && pc != SG_PC_NONE) return apply_graph(h, pc, r, z, &nbmv, &nbs);
     if (pc == SG_PC_HSC) return apply_hsc(h, r, z, &nbmv, &nbs);
     if (pc == SG_PC_BGS) return apply_bgs(h, r, z, &nbmv, &nbs);
     if (pc == SG_PC_MEAN) return apply_mean(h, r, z, &nbs);
@@ -1223,6 +1302,7 @@ int mv_param(const sg_ctx* h) {
 
 // Schedule autotuner (sg_autotune).
 int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
+  drop_pc_graph(h);  // a captured action holds the old schedules
   sg_tune_report R{};
   const long N = h->n * (long)h->P;
   hipStream_t s = h->stream;
@@ -1361,6 +1441,7 @@ int autotune(sg_ctx* h, int flags, sg_tune_report* out) {
 
 // Frees a handle's host-side resources: events, pinned read-back buffers, the context.
 void release_ctx(sg_ctx* h) {
+  drop_pc_graph(h);
   (void)hipEventDestroy(h->ev0);
   (void)hipEventDestroy(h->ev1);
   for (int i = 0; i < h->nev; ++i) (void)hipEventDestroy(h->evpool[i]);
@@ -1691,6 +1772,7 @@ int sg_set_opts(sg_handle h, const sg_opts* opts) {
   if (opts->inner_precision != h->opts.inner_precision)
     return fail(SG_EINVAL, "inner precision is fixed at setup");
   h->opts = *opts;
+  drop_pc_graph(h);  // a captured action holds the old options
   return SG_OK;
 }
 

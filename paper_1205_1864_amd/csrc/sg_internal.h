@@ -226,6 +226,7 @@ struct PcgArgs {
   double rtol;
   int warm;    // start each column from the contents of its x (banded tiles), else from 0
   long per_block;  // work items (tiles) per block; 0 = the work list split evenly over the grid
+  int no_coop;     // 1: an ordinary launch (graph capture) instead of a cooperative one
   T c0;        // centre weight of K_0: theta0 * 8/3
   T c1;        // neighbour weight of K_0: -theta0 / 3
   T inv_diag;  // 1 / (theta0 * 8/3)
@@ -449,6 +450,7 @@ struct sg_ctx {
   struct PendingLaunch {
     int ncols, level, tile, warm, wsize;
     long slot;
+    bool timed;  // its events were recorded (not inside a graph capture)
   };
   static constexpr int kMaxPending = 64;
   std::vector<PendingLaunch> pending;
@@ -457,6 +459,16 @@ struct sg_ctx {
   int* iters_host = nullptr;   // pinned, iters_cap ints
   int* status_host = nullptr;  // pinned, kMaxPending ints
   long iters_cap = 0, iters_used = 0;
+  // one preconditioner action captured into a HIP graph (opts.use_graph)
+  bool capturing = false;   // inner launches are ordinary launches and never settle the read-back
+  hipGraph_t pc_graph = nullptr;
+  hipGraphExec_t pc_exec = nullptr;
+  int pc_kind = -1;                      // preconditioner of the captured action
+  const double* pc_R = nullptr;          // its input and output blocks
+  double* pc_Z = nullptr;
+  std::vector<PendingLaunch> pc_pending; // the read-back records of one replay
+  long pc_iters_used = 0;
+  long pc_nbmv = 0, pc_nbs = 0;          // block products and solves of one action
   int defer = 0;           // > 0: run_pcg leaves the read-back to flush_inner
   void* static_scratch = nullptr;  // this device's static scratch array (sg_inner_solve_static)
 };

@@ -114,6 +114,8 @@ int main() {
         {"precond 9", [](sg_problem&, sg_opts& o) { o.precond = 9; }},
         {"tile 8", [](sg_problem&, sg_opts& o) { o.tile = 8; }},
         {"inner_rtol NaN", [](sg_problem&, sg_opts& o) { o.inner_rtol = NAN; }},
+        {"use_graph 2", [](sg_problem&, sg_opts& o) { o.use_graph = 2; }},
+        {"reserved 1", [](sg_problem&, sg_opts& o) { o.reserved = 1; }},
     };
     for (const Bad& b : bad) {
       sg_problem p = pr.p;

@@ -182,6 +182,43 @@ def test_inner_schedules_bitwise_equal(prec, degree, monkeypatch):
         assert np.linalg.norm(res[0][0][c].numpy() - Xo[j]) <= tol * np.linalg.norm(Xo[j])
 
 
+@pytest.mark.parametrize("pc,prec,warm", [("hsc", 64, False), ("hsc", 32, True), ("bgs", 64, True),
+                                         ("mean", 32, False)])
+def test_solve_graph_replay_equals_eager(pc, prec, warm):
+    """use_graph: the preconditioner action captured once and replayed in every
+    outer iteration (eager FCG work and host synchronisation between replays)
+    gives the eager solve bit for bit, with the same counters, in two solves in
+    a row (the second replays the first one's graph) and after the options
+    change (the graph is captured again)."""
+    import torch
+    b = _b()
+    prob, s = _sys(n_e=40, M=4, p=3)
+    print(f"graph replay pc={pc} prec={prec} warm={warm}", flush=True)
+    F = _dev(prob.load_block())
+    base = dict(inner_precision=prec, precond=pc, cheb_degree=8, inner_rtol=1e-4, warm_start=warm)
+    eager = b.SGSolver(prob, b.Options(**base))
+    graph = b.SGSolver(prob, b.Options(**base, use_graph=True))
+    assert graph.stream.cuda_stream != 0
+    keys = ("outer_it", "inner_it_total", "n_blockmv", "n_blocksolve", "inner_launches")
+    for degree in (8, 5):
+        if degree != 8:
+            eager.set_opts(b.Options(**dict(base, cheb_degree=degree)))
+            graph.set_opts(b.Options(**dict(base, cheb_degree=degree), use_graph=True))
+        Ue, se = eager.sg_solve(F, rtol=1e-8, maxit=100)
+        for rep in range(2):
+            Ug, sg_ = graph.sg_solve(F, rtol=1e-8, maxit=100)
+            torch.cuda.synchronize()
+            assert se["rc"] == 0 and sg_["rc"] == 0
+            assert bool((Ug == Ue).all()), (degree, rep, float((Ug - Ue).abs().max()))
+            assert all(sg_[k] == se[k] for k in keys), ({k: (sg_[k], se[k]) for k in keys})
+            assert sg_["inner_it_max"] == se["inner_it_max"]
+            # with a graph, ms_inner times the replayed actions as a whole
+            assert sg_["ms_inner"] >= 0.5 * se["ms_inner"] and sg_["ms_inner"] <= 2.0 * sg_["ms_precond"] + 1.0
+    assert solve.true_relres(s, prob.load_block().T, Ug.cpu().numpy().T) <= 1.05e-8
+    eager.close()
+    graph.close()
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_inner_solve_to_tolerance(prec):
     b = _b()
