@@ -160,7 +160,8 @@ def test_paper_tables_6_to_9(row):
     Dirichlet nodes are eliminated (the paper counts 11 x 11 nodes on the
     10 x 10 mesh), so the comparison has tolerances, fixed from the rows:
     M_HS within 2 iterations and 20 % in the condition estimate (up to CoV
-    125 %); M_bGS within 3 iterations; the mean-based condition estimate
+    125 %; at CoV 150 % within 5 and 25 %, the largest gap of the tables);
+    M_bGS within 3 iterations in every row; the mean-based condition estimate
     within 12 % on the 10 x 10 mesh (its iteration counts run 5-25 % below the
     paper's). In every row, as the paper concludes, the condition estimates
     order M_HS <= M_bGS <= M_m."""
@@ -169,10 +170,14 @@ def test_paper_tables_6_to_9(row):
     (m_it, m_k), (b_it, b_k), (h_it, h_k) = ref
     assert got["hsc"][1] <= got["bgs"][1] <= got["mean"][1]
     assert got["hsc"][0] <= got["mean"][0] and got["bgs"][0] <= got["mean"][0]
+    assert abs(got["bgs"][0] - b_it) <= 3, (got, ref)
     if key == "CoV" and val > 125:
+        # the widest gap of the tables (reading 18): at CoV 150 % M_HS takes 26
+        # iterations against the printed 21, its estimate 8.36 against 6.85
+        assert abs(got["hsc"][0] - h_it) <= 5, (got, ref)
+        assert abs(got["hsc"][1] - h_k) <= 0.25 * h_k, (got, ref)
         return
     assert abs(got["hsc"][0] - h_it) <= 2, (got, ref)
     assert abs(got["hsc"][1] - h_k) <= 0.20 * h_k, (got, ref)
-    assert abs(got["bgs"][0] - b_it) <= 3, (got, ref)
     if key != "h":
         assert abs(got["mean"][1] - m_k) <= 0.12 * m_k, (got, ref)
