@@ -55,24 +55,59 @@ constexpr long kSpinLimit = 1L << 26;      // bounded waits: a stuck column abor
 enum { PART_BB = 0, PART_PQ0 = 1, PART_PQ1 = 2, PART_RR0 = 3, PART_RR1 = 4, PART_RZ0 = 5, PART_RZ1 = 6, PART_N = 7 };
 static_assert(PART_N == kPcgPartials, "partial arrays of the inner solver");
 
+// DPP move of a double within rows of 16 lanes (every source lane exists).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over the 64 lanes of a wave, the same in every lane and in a fixed
+// order: butterflies within rows of 16 lanes (neighbour in the quad, the
+// other pair of the quad, the other quad of each 8, the other 8 of each 16;
+// both partners add the same two values), then the four row sums in order.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 // Split-phase barrier of one column: every block that owns tiles of the column
 // adds its tile count to a monotonic arrival counter after finishing its tiles;
 // phase k of the column is complete once the counter reaches k * ntiles. The
 // arrival releases the block's writes (device scope) and the wait acquires
-// them: one L2 write-back per arrival, one invalidation per wait.
+// them: one L2 write-back per arrival, one invalidation per wait. Every wave
+// first waits for its own stores: the barrier does not, and thread 0's
+// release (the write-back) covers only stores that have reached the L2.
 // A column whose tiles all belong to one block needs neither: its phases are
 // ordered by the block's own barriers (see pcg_kernel).
 __device__ void column_arrive(unsigned* arr, unsigned count) {
+  __builtin_amdgcn_s_waitcnt(0);  // every counter at zero: the wave's stores are done
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // The write-back the fence issues must be complete before the arrival
+    // can be seen. The compiler's own wait after it is dropped when the wave
+    // has no other memory operation outstanding, so it is stated here.
+    __builtin_amdgcn_s_waitcnt(0);
     __hip_atomic_fetch_add(arr, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// End of a column phase whose tiles all belong to this block: the block's
+// global stores of the phase (vectors and tile partials) are complete before
+// any wave goes on to read them. A barrier alone orders only the LDS.
+__device__ __forceinline__ void column_end_whole() {
+  __builtin_amdgcn_s_waitcnt(0);  // every counter at zero: the wave's stores are done
+  __syncthreads();
 }
 
 __device__ bool column_wait(const unsigned* arr, unsigned target, int* status, int* sflag) {
@@ -93,6 +128,15 @@ __device__ bool column_wait(const unsigned* arr, unsigned target, int* status, i
   }
   __syncthreads();
   return *sflag != 0;
+}
+
+// Completes the loads of the given registers here (an empty asm that reads
+// them). Vector loads and stores share one in-order counter, so a load
+// consumed after later stores would otherwise also wait for those stores.
+template <typename T, int N>
+__device__ __forceinline__ void ready(const T (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" ::"v"(v[i]));
 }
 
 // Index of this wave within its tile group (uniform, so that values derived
@@ -205,6 +249,7 @@ struct IterVecs {
 template <typename T, int TS, int NS>
 struct SquareTile {
   static constexpr int kThreads = kSquareGroup;
+  static constexpr bool kParkedSums = false;  // tile sums through group_sum2
   // phase A stores q = K_0 p and phase B reads it
   static constexpr int NI = (TS * TS + kThreads - 1) / kThreads;  // interior nodes per thread
   // elements of T in one group's LDS buffers (two buffers; phase A needs a 1-node halo)
@@ -446,6 +491,7 @@ struct SquareTile {
 template <typename T, int TSY, int HMAX, int NW>
 struct BandTile {
   static constexpr int kThreads = 64 * NW;
+  static constexpr bool kParkedSums = true;  // tile sums: see TileSums
   // phase B recomputes q = K_0 p from p instead of reading a stored q
   static constexpr int RYMAX = TSY + 2 * HMAX;
   static constexpr int BR = (RYMAX + NW - 1) / NW;     // region rows per wave (Chebyshev)
@@ -488,6 +534,63 @@ struct BandTile {
     y0 = (t / v.ntx) * TSY;
   }
 
+  // Per-tile sums without barriers of their own. Each wave adds its lanes
+  // (wave_sum) and parks the result in LDS, alternate tiles in alternate
+  // buffers; wave 0 adds the waves' values of a tile (a fixed tree over the
+  // waves) after the next tile's barriers, when every wave has parked them,
+  // and stores the tile's partials. `finish` ends a run of tiles: one
+  // barrier, then the last tile. A buffer is parked in again two tiles later,
+  // behind the barriers of the tile in between, which wave 0 reaches only
+  // after reading it.
+  struct TileSums {
+    double (*buf)[NW][2];  // [2][NW][2] in LDS
+    double* out0;
+    double* out1;          // null: one value per tile
+    int pend;              // tile whose sums are parked and not yet stored, -1: none
+    int pbuf;              // its buffer
+
+    __device__ void settle() {
+      if (pend < 0) return;
+      if (wave_in_group<kThreads>() == 0) {
+        const int lane = threadIdx.x & 63;
+        double a = 0.0, c = 0.0;
+        if (lane < NW) {
+          a = buf[pbuf][lane][0];
+          c = buf[pbuf][lane][1];
+        }
+        static_assert(NW == 16, "one row of 16 lanes holds the wave sums");
+        a += dpp_f64<0xB1>(a);
+        a += dpp_f64<0x4E>(a);
+        a += dpp_f64<0x141>(a);
+        a += dpp_f64<0x140>(a);
+        c += dpp_f64<0xB1>(c);
+        c += dpp_f64<0x4E>(c);
+        c += dpp_f64<0x141>(c);
+        c += dpp_f64<0x140>(c);
+        if (lane == 0) {
+          out0[pend] = a;
+          if (out1) out1[pend] = c;
+        }
+      }
+      pend = -1;
+    }
+    __device__ void park(int t, int b, double a, double c) {
+      a = wave_sum(a);
+      c = wave_sum(c);
+      if ((threadIdx.x & 63) == 0) {
+        const int wv = wave_in_group<kThreads>();
+        buf[b][wv][0] = a;
+        buf[b][wv][1] = c;
+      }
+      pend = t;
+      pbuf = b;
+    }
+    __device__ void finish(GroupBarrier& gb) {
+      group_sync(gb);
+      settle();
+    }
+  };
+
   // Chebyshev preconditioner on one tile: Zi[r] receives z at row
   // wave * BR + r of the region (meaningful only on the interior of the tile;
   // callers mask it) and Rl[(wave * BR + r) * 64 + lane] r on the interior
@@ -502,11 +605,14 @@ struct BandTile {
   // `val(r)` gives r at band row r of the region for every lane (it may use
   // DPP, so it runs unmasked); its value at nodes outside the grid is dropped.
   // H is the halo of the region: degree - 1, or degree when r is valid only
-  // off the outermost ring of the region (warm start). The sweeps exchange
-  // through buffers 1, 0, 1, ... of E.
-  template <typename VF>
+  // off the outermost ring of the region (warm start). The caller's exchange
+  // for `val` used buffer `eb` of E; the sweeps continue with the other
+  // buffer and alternate. `after0()` runs once step 0 has read every value
+  // `val` depends on (phase B issues the next tile's loads there, into the
+  // registers its inputs leave free, so they stream during the sweeps).
+  template <typename VF, typename AF>
   __device__ static void cheb(const ColView<T>& A, int degree, int H, int x0, int y0, VF val, T* E, T* Rl,
-                              T (&Zi)[BR], GroupBarrier& gb) {
+                              T (&Zi)[BR], GroupBarrier& gb, int eb, AF after0) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int tsx = A.tsx, nx = A.nx;
@@ -530,10 +636,11 @@ struct BandTile {
       const bool interior = xint && ly >= H && ly < H + TSY;
       Rl[ly * 64 + lane] = interior ? rv : T(0);
     }
+    after0();
     const T w8 = A.w8;
     for (int j = 1; j < degree; ++j) {
       T up, dn;
-      exchange(W, E, j & 1, up, dn, gb);
+      exchange(W, E, (eb + j) & 1, up, dn, gb);
       const T ca = ld_uniform(A.chebA, j), cb = ld_uniform(A.chebB, j);
       T cm = up;
 #pragma unroll
@@ -603,7 +710,7 @@ struct BandTile {
       return bv[r] - k0_apply(cm, xv[r], cp, v.c0, v.c1);
     };
     T Zi[BR];
-    cheb(v, degree, H, x0, y0, val, E, Rl, Zi, gb);
+    cheb(v, degree, H, x0, y0, val, E, Rl, Zi, gb, 0, [] {});
     rz = rr = 0.0;
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
@@ -654,7 +761,7 @@ struct BandTile {
   }
 
   __device__ static double compute_a(const ColView<T>& v, int t, const IterVecs<T>& I, const InA& in, T* W0,
-                                     GroupBarrier& gb) {
+                                     GroupBarrier& gb, int eb) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
@@ -673,7 +780,7 @@ struct BandTile {
         v.x[(unsigned)(gy * nx + gx)] = in.x[r] + I.alpha_prev * in.po[r];
     }
     T up, dn;
-    exchange(pc, W0, 0, up, dn, gb);
+    exchange(pc, W0, eb, up, dn, gb);
     double pq = 0.0;
 #pragma unroll
     for (int r = 0; r < BRA; ++r) {
@@ -692,23 +799,29 @@ struct BandTile {
   }
 
   // Phase A over tiles t_begin, t_begin + step, ... < t_end of a column; the
-  // inputs of the next tile are loaded while the current one is computed.
+  // inputs of the next tile are loaded while the current one is computed
+  // (short bands, two copies in registers) or once its stores are issued, so
+  // the next tile's wait for them does not also wait for those stores.
+  // Consecutive tiles exchange through alternate buffers. `sb`: the group's
+  // [2][NW][2] sum buffers.
   __device__ static void run_a(const ColView<T>& v, int t_begin, int t_end, int step, const IterVecs<T>& I, T* W0,
-                               GroupBarrier& gb, double (*sred)[kThreads / 64][2], double* part) {
+                               GroupBarrier& gb, double (*sb)[NW][2], double* part) {
     if (t_begin >= t_end) return;
+    TileSums sums{sb, part, nullptr, -1, 0};
     InA cur;
     load_a(v, t_begin, I, cur);
-    for (int t = t_begin; t < t_end; t += step) {
+    int k = 0;
+    for (int t = t_begin; t < t_end; t += step, ++k) {
       InA nxt;
       const bool more = t + step < t_end;
       if (kPrefetch && more) load_a(v, t + step, I, nxt);
-      double pq = compute_a(v, t, I, cur, W0, gb), unused = 0.0;
-      // without the prefetch the next tile's loads still overlap the reduction
+      const double pq = compute_a(v, t, I, cur, W0, gb, k & 1);
       if (!kPrefetch && more) load_a(v, t + step, I, cur);
-      group_sum2<kThreads>(pq, unused, sred, gb);
-      if ((threadIdx.x % kThreads) == 0) part[t] = pq;
+      sums.settle();
+      sums.park(t, k & 1, pq, 0.0);
       if (kPrefetch && more) cur = nxt;
     }
+    sums.finish(gb);
   }
 
   // x += alpha p on the interior of a tile, the update a stopping column still
@@ -763,8 +876,10 @@ struct BandTile {
     }
   }
 
+  template <typename AF, typename EF>
   __device__ static void compute_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, const InB& in,
-                                   T* W0, T* W1, GroupBarrier& gb, double& rz, double& rr) {
+                                   T* W0, T* W1, GroupBarrier& gb, int eb, double& rz, double& rr, AF after0,
+                                   EF before_out) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int H = degree, nx = v.nx;
@@ -774,16 +889,17 @@ struct BandTile {
     T* E = W0;
     T* Rl = W0 + kEx;
     // r - alpha q with q = K_0 p on the region, valid off its outermost ring
-    // (exchange buffer 0; the sweeps continue with 1, 0, ...)
+    // (exchange buffer eb; the sweeps continue with the other one, alternating)
     T up, dn;
-    exchange(in.p, E, 0, up, dn, gb);
+    exchange(in.p, E, eb, up, dn, gb);
     auto val = [&](int r) {
       const T cm = r > 0 ? in.p[r - 1] : up;
       const T cp = r + 1 < BR ? in.p[r + 1] : dn;
       return in.r[r] - I.alpha * k0_apply(cm, in.p[r], cp, v.c0, v.c1);
     };
     T Zi[BR];
-    cheb(v, degree, H, x0, y0, val, E, Rl, Zi, gb);
+    cheb(v, degree, H, x0, y0, val, E, Rl, Zi, gb, eb, after0);
+    before_out();
     rz = rr = 0.0;
     const int gx = x0 - H + lane;
     const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
@@ -803,27 +919,46 @@ struct BandTile {
   }
 
   // Phase B over tiles t_begin, t_begin + step, ... < t_end of a column; the
-  // inputs of the next tile are loaded while the current one is computed.
+  // inputs of the next tile are loaded while the current one is computed:
+  // before it (short bands, two copies in registers) or, for tall bands, into
+  // the current tile's input registers once its first Chebyshev step has
+  // consumed them.
+  // A tile makes `degree` exchanges (one for q, then the sweeps), so the
+  // next tile's first exchange takes the buffer after the tile's last one.
   __device__ static void run_b(const ColView<T>& v, int degree, int t_begin, int t_end, int step,
                                const IterVecs<T>& I, T* W0, T* W1, GroupBarrier& gb,
-                               double (*sred)[kThreads / 64][2], double* part_rz, double* part_rr) {
+                               double (*sb)[NW][2], double* part_rz, double* part_rr) {
     if (t_begin >= t_end) return;
+    TileSums sums{sb, part_rz, part_rr, -1, 0};
     InB cur;
     load_b(v, degree, t_begin, I, cur);
-    for (int t = t_begin; t < t_end; t += step) {
+    if (!kPrefetch) {
+      ready(cur.r);
+      ready(cur.p);
+    }
+    int eb = 0, k = 0;
+    for (int t = t_begin; t < t_end; t += step, ++k) {
       InB nxt;
       const bool more = t + step < t_end;
       if (kPrefetch && more) load_b(v, degree, t + step, I, nxt);
       double rz, rr;
-      compute_b(v, degree, t, I, cur, W0, W1, gb, rz, rr);
-      if (!kPrefetch && more) load_b(v, degree, t + step, I, cur);
-      group_sum2<kThreads>(rz, rr, sred, gb);
-      if ((threadIdx.x % kThreads) == 0) {
-        part_rz[t] = rz;
-        part_rr[t] = rr;
-      }
+      // the next tile's loads, issued after the first Chebyshev step, are
+      // complete before this tile's results are stored (a tile start then
+      // never waits for the stores of the tile before)
+      compute_b(v, degree, t, I, cur, W0, W1, gb, eb, rz, rr, [&] {
+        if (!kPrefetch && more) load_b(v, degree, t + step, I, cur);
+      }, [&] {
+        if (!kPrefetch) {  // unconditional, so every path into the next tile has them ready
+          ready(cur.r);
+          ready(cur.p);
+        }
+      });
+      eb = (eb + degree) & 1;
+      sums.settle();
+      sums.park(t, k & 1, rz, rr);
       if (kPrefetch && more) cur = nxt;
     }
+    sums.finish(gb);
   }
 };
 
@@ -843,6 +978,10 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
   // per-column done flags of this block's columns, after the tile buffers
   int* sdone = reinterpret_cast<int*>(reinterpret_cast<T*>(smem_raw) + (long)G * lds_group);
   __shared__ double sred[G][GT / 64][2];
+  // banded tiles (one group per block) park per-wave tile sums in two buffers
+  static_assert(!Tile::kParkedSums || G == 1, "parked tile sums serve one group per block");
+  __shared__ double spart[2][GT / 64][2];
+  double (*tsums)[GT / 64][2] = Tile::kParkedSums ? spart : sred;
   __shared__ double s4[5];
   static_assert(Tile::kThreads * G >= 5 * 64, "column sums take five waves");
   __shared__ int sflag;
@@ -937,7 +1076,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
   };
   auto owner = [&](const ColView<T>& v) { return v.tbase >= w_begin; };  // this block holds tile 0
   // this block holds every tile of the column: its phases need only the block's
-  // barriers (workgroup-scope ordering of the block's own global writes)
+  // barriers, behind a wait for the block's own global stores (column_end_whole)
   auto whole = [&](const ColView<T>& v, int t0, int t1) { return t0 == 0 && t1 == v.ntiles; };
   // the column starts from the contents of its x
   auto warm_of = [&](const ColView<T>& v) { return A.warm && Tile::warm_fits(v, degree); };
@@ -986,7 +1125,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         P(PART_RR1)[v.tbase + t] = rr;
       }
     }
-    if (whole(v, t0, t1)) __syncthreads();
+    if (whole(v, t0, t1)) column_end_whole();
     else column_arrive(arr + c, (unsigned)(t1 - t0));
   }
 
@@ -1033,8 +1172,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         continue;
       }
       any_active = true;
-      Tile::run_a(v, t0 + grp, t1, G, I, W0, gb, sred, P(par ? PART_PQ1 : PART_PQ0) + v.tbase);
-      if (whole(v, t0, t1)) __syncthreads();
+      Tile::run_a(v, t0 + grp, t1, G, I, W0, gb, tsums, P(par ? PART_PQ1 : PART_PQ0) + v.tbase);
+      if (whole(v, t0, t1)) column_end_whole();
       else column_arrive(arr + c, (unsigned)(t1 - t0));
     }
     if (!any_active || aborted) break;
@@ -1068,9 +1207,9 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       I.pn = par ? v.p1 : v.p0;
       I.ro = it == 0 ? (warm_of(v) ? v.r0 : v.b) : (par ? v.r1 : v.r0);
       I.rn = par ? v.r0 : v.r1;
-      Tile::run_b(v, degree, t0 + grp, t1, G, I, W0, W1, gb, sred, P(par ? PART_RZ1 : PART_RZ0) + v.tbase,
+      Tile::run_b(v, degree, t0 + grp, t1, G, I, W0, W1, gb, tsums, P(par ? PART_RZ1 : PART_RZ0) + v.tbase,
                   P(par ? PART_RR1 : PART_RR0) + v.tbase);
-      if (whole(v, t0, t1)) __syncthreads();
+      if (whole(v, t0, t1)) column_end_whole();
       else column_arrive(arr + c, (unsigned)(t1 - t0));
     }
   }
