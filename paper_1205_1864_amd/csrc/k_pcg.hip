@@ -638,26 +638,38 @@ struct BandTile {
     }
     after0();
     const T w8 = A.w8;
+    // Nodes outside the grid stay at zero without a select per node: a row
+    // outside the grid (the same for the whole wave) is not updated at all,
+    // and a lane outside it takes zero coefficients, so its new W is
+    // 0 * 0 + 0 * S. Inside the grid the arithmetic is the same as with the
+    // coefficients themselves.
+    bool row_in[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int gy = y0 - H + yb + r;
+      row_in[r] = gy >= 0 && gy < nx;
+    }
     for (int j = 1; j < degree; ++j) {
       T up, dn;
       exchange(W, E, (eb + j) & 1, up, dn, gb);
-      const T ca = ld_uniform(A.chebA, j), cb = ld_uniform(A.chebB, j);
+      const T ca_j = ld_uniform(A.chebA, j), cb_j = ld_uniform(A.chebB, j);
+      const T ca = xin ? ca_j : T(0), cb = xin ? cb_j : T(0);
       T cm = up;
 #pragma unroll
       for (int r = 0; r < BR; ++r) {
-        const int ly = yb + r;
         const T c0 = W[r];
-        const T cp = r + 1 < BR ? W[r + 1] : dn;
-        const T vs = cm + cp;
-        const T col = vs + c0;
-        const T s8 = (from_prev(col) + from_next(col)) + vs;
-        // S - D^-1 K_0 W, with D^-1 K_0 W = W - s8 / 8
-        const T sn = S[r] - (c0 - w8 * s8);
-        S[r] = sn;
-        const int gy = y0 - H + ly;
-        const T wn = xin && gy >= 0 && gy < nx ? ca * c0 + cb * sn : T(0);
-        W[r] = wn;
-        Zi[r] += wn;
+        if (row_in[r]) {
+          const T cp = r + 1 < BR ? W[r + 1] : dn;
+          const T vs = cm + cp;
+          const T col = vs + c0;
+          const T s8 = (from_prev(col) + from_next(col)) + vs;
+          // S - D^-1 K_0 W, with D^-1 K_0 W = W - s8 / 8
+          const T sn = S[r] - (c0 - w8 * s8);
+          S[r] = sn;
+          const T wn = ca * c0 + cb * sn;
+          W[r] = wn;
+          Zi[r] += wn;
+        }
         cm = c0;
       }
     }
