@@ -39,9 +39,11 @@ HBM_PEAK_GBS = 8000.0
 CHEB_DEGREE = 16  # updates of the Chebyshev preconditioner of the inner PCG (fastest measured; 8 as an extra)
 # HBM bytes per launch measured with separate FETCH_SIZE and WRITE_SIZE counter
 # runs of this benchmark, scaled by the same counters of a 512 MiB elementwise
-# kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Set to None when the
+# kernel (profiles/hbm_traffic_solve_256sq_M10_p3.txt). Emptied when the
 # kernel changes.
-PCG_TRAFFIC_BYTES = 15.00e9     # pcg_kernel<double, BandTile<double, 128 | 64, 15, 16>, 1>, average over a solve's launches
+# pcg_kernel<double, BandTile<double, 128 | 64, 15, 16>, 1>, average over a solve's launches, by the
+# inner schedule's block cap (-1: whole columns per block where they fill the device; 0: automatic grid)
+PCG_TRAFFIC_BYTES = {-1: 14.93e9, 0: 14.91e9}
 # one SG matvec, by schedule (mv_variant, mv_param): the row-staged kernel with 10-row pieces,
 # and the y-marching kernel it replaced
 MATVEC_TRAFFIC_BYTES = {(4, 10): 354.2e6, (2, 2): 570.4e6, (2, 1): 543.0e6}
@@ -205,6 +207,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the timed solve and the matvec")
+    ap.add_argument("--pcg-blocks", type=int, default=None,
+                    help="fix the inner PCG schedule instead of autotuning it (0: automatic grid, -1: whole "
+                         "columns per block); for counter runs of one schedule")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
@@ -237,8 +242,12 @@ def main():
         into[f"rel_err_bound_{key}"] = bound
         log(f"{key}: |u - u_oracle| / |u_oracle| = {err:.2e} (bound {bound:.2e})")
     opts64 = Options(inner_precision=64, cheb_degree=CHEB_DEGREE, inner_maxit=2000, precond="hsc", inner_rtol=1e-4)
+    if args.pcg_blocks is not None:  # the handle's default inner schedule, read at set-up
+        os.environ["SGPC_PCG_MAX_BLOCKS"] = str(args.pcg_blocks)
     solver = SGSolver(prob, opts64)
-    schedule = solver.sg_autotune(3)  # not timed: picks the launch schedules for this problem
+    # not timed: picks the launch schedules for this problem (only the SG operator's when the
+    # inner schedule is fixed)
+    schedule = solver.sg_autotune(1 if args.pcg_blocks is not None else 3)
     log(f"autotune: {schedule}")
     U = solver.empty()
 
@@ -468,7 +477,7 @@ def main():
             extra["extras_error"] = repr(exc)
     achieved = bytes_inner / (ms_inner * 1e-3) / 1e9 if ms_inner > 0 else 0.0
     # the counter traffic belongs to the schedules it was measured with
-    pcg_traffic = PCG_TRAFFIC_BYTES if (schedule["pcg_tile"], schedule["pcg_max_blocks"]) == (32, 0) else None
+    pcg_traffic = PCG_TRAFFIC_BYTES.get(schedule["pcg_max_blocks"]) if schedule["pcg_tile"] == 32 else None
     mv_traffic = MATVEC_TRAFFIC_BYTES.get((schedule["mv_variant"], schedule["mv_param"]))
     mv_kernel = {4: "sgop_stage_kernel", 3: "sgop_piece_kernel<double>", 2: "sgop_march_kernel<double>",
                  1: "sgop_strip_dyn_kernel<double>", 0: "sgop_strip_kernel<double>"}.get(

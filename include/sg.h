@@ -278,9 +278,11 @@ int sg_adjoint_grad(sg_handle h, const double* U, const double* w_mean, const do
  * differ only in the order of floating-point sums. report (host, may be NULL)
  * receives the choice. */
 typedef struct sg_tune_report {
-  int32_t mv_variant;      /* 0, 1: band kernels; 2: y-marching kernel; 3: piece kernel */
+  int32_t mv_variant;      /* 0, 1: band kernels; 2: y-marching kernel; 3: piece kernel;
+                              4: row-staged kernel (node rows of all chaos columns in LDS) */
   int32_t mv_param;        /* row chunks per band (variants 0, 1); segments per XCD (2; 0 = automatic);
-                              100 * rows per piece + waves per CU (3; 0 waves = all resident) */
+                              100 * rows per piece + waves per CU (3; 0 waves = all resident);
+                              node rows per piece (4) */
   int32_t pcg_tile;        /* inner tile kind (32 banded, 16 square) */
   int32_t pcg_max_blocks;  /* cap on the blocks of an inner launch (0 = as many as fit; -1 = whole
                               columns per block for launches whose columns fill at least 3/4 of the
