@@ -220,7 +220,8 @@ __device__ __forceinline__ T k0_apply(T cm, T c, T cp, T c0, T c1) {
 // The grid, state vectors and constants of one column.
 template <typename T>
 struct ColView {
-  int nx, ntx, ntiles, tsx;  // tsx: width of a banded tile
+  int nx, ntx, ntiles, tsx;  // tsx: interior width of an inner banded tile
+  int ta;                    // interior width of a banded tile at the grid's left or right edge
   long tbase;  // first index of the column's per-tile partials (and of its work items)
   const T* b;
   T *x, *r0, *r1, *p0, *p1, *q, *z;
@@ -523,15 +524,30 @@ struct BandTile {
     dn = wv + 1 < NW ? e[((wv + 1) * 2 + 0) * 64 + lane] : T(0);
   }
   static bool fits(int degree, int nx, int ntx, int ntiles) {
-    const int H = degree - 1;
-    if (H > HMAX || ntx < 1) return false;
-    const int tsx = (nx + ntx - 1) / ntx;
-    const int h = (H > 1 ? H : 1) + 1;  // phase B: Chebyshev halo plus one node
-    return tsx + 2 * h <= 64 && ntiles == ntx * ((nx + TSY - 1) / TSY);
+    if (degree - 1 > HMAX || ntx < 1) return false;
+    return ntx == band_ntx(nx, degree) && ntiles == ntx * ((nx + TSY - 1) / TSY);
   }
-  __device__ static void origin(const ColView<T>& v, int t, int& x0, int& y0) {
-    x0 = (t % v.ntx) * v.tsx;
+  // Interior columns [ix0, ix1) and first row y0 of tile t; tx is its column
+  // of tiles. The tiles at the grid's left and right edges are ta wide, the
+  // others tsx (band_ntx); the last one takes what remains.
+  __device__ static void span(const ColView<T>& v, int t, int& tx, int& ix0, int& ix1, int& y0) {
+    tx = t % v.ntx;
     y0 = (t / v.ntx) * TSY;
+    if (v.ntx == 1) {
+      ix0 = 0;
+      ix1 = v.nx;
+      return;
+    }
+    ix0 = tx == 0 ? 0 : v.ta + (tx - 1) * v.tsx;
+    ix1 = tx == 0 ? v.ta : (tx + 1 == v.ntx ? v.nx : ix0 + v.tsx);
+  }
+  // First grid column of the 64-lane region of tile column tx with a halo of
+  // H columns: at the grid's edges the region ends at the edge, where the
+  // lane shifts bring in the zero boundary value.
+  __device__ static int region_x(const ColView<T>& v, int tx, int ix0, int H) {
+    if (tx == 0) return 0;
+    if (tx + 1 == v.ntx) return v.nx - 64;
+    return ix0 - H;
   }
 
   // Per-tile sums without barriers of their own. Each wave adds its lanes
@@ -591,7 +607,8 @@ struct BandTile {
     }
   };
 
-  // Chebyshev preconditioner on one tile: Zi[r] receives z at row
+  // Chebyshev preconditioner on one tile (interior columns [ix0, ix1), region
+  // columns from rx0): Zi[r] receives z at row
   // wave * BR + r of the region (meaningful only on the interior of the tile;
   // callers mask it) and Rl[(wave * BR + r) * 64 + lane] r on the interior
   // (zero elsewhere; read back by the same thread).
@@ -611,15 +628,15 @@ struct BandTile {
   // `val` depends on (phase B issues the next tile's loads there, into the
   // registers its inputs leave free, so they stream during the sweeps).
   template <typename VF, typename AF>
-  __device__ static void cheb(const ColView<T>& A, int degree, int H, int x0, int y0, VF val, T* E, T* Rl,
-                              T (&Zi)[BR], GroupBarrier& gb, int eb, AF after0) {
+  __device__ static void cheb(const ColView<T>& A, int degree, int H, int rx0, int ix0, int ix1, int y0, VF val,
+                              T* E, T* Rl, T (&Zi)[BR], GroupBarrier& gb, int eb, AF after0) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
-    const int tsx = A.tsx, nx = A.nx;
-    const int RX = tsx + 2 * H, RY = TSY + 2 * H;
-    const int gx = x0 - H + lane;
-    const bool xin = lane < RX && gx >= 0 && gx < nx;          // lane holds a grid column
-    const bool xint = lane >= H && lane < H + tsx && gx < nx;  // interior column of the tile
+    const int nx = A.nx;
+    const int RY = TSY + 2 * H;
+    const int gx = rx0 + lane;
+    const bool xin = gx >= 0 && gx < nx;     // lane holds a grid column
+    const bool xint = gx >= ix0 && gx < ix1;  // interior column of the tile
     const int yb = wv * BR;                                    // first region row of this wave
     T S[BR], W[BR];
     // step 0: S = D^-1 r, W = S / theta
@@ -676,10 +693,10 @@ struct BandTile {
   }
 
   // Whether a column can start from the contents of X: the region grown by
-  // one more node must fit one wavefront and the LDS buffers.
-  __device__ static bool warm_fits(const ColView<T>& v, int degree) {
+  // one more node must fit the band (the tile widths leave that node in x).
+  __device__ static bool warm_fits(const ColView<T>&, int degree) {
     const int H1 = degree;  // (degree - 1) + 1
-    return v.tsx + 2 * H1 <= 64 && TSY + 2 * H1 <= RB;
+    return TSY + 2 * H1 <= RB;
   }
 
   // Start of the iteration: z = M r with r = b (x = 0), or r = b - K_0 x from
@@ -692,13 +709,14 @@ struct BandTile {
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
     const int H = warm ? degree : degree - 1;
-    int x0, y0;
-    origin(v, t, x0, y0);
-    const int RX = v.tsx + 2 * H, RY = TSY + 2 * H;
-    const int gx = x0 - H + lane;
-    const bool xin = lane < RX && gx >= 0 && gx < nx;
+    int tx, ix0, ix1, y0;
+    span(v, t, tx, ix0, ix1, y0);
+    const int rx0 = region_x(v, tx, ix0, H);
+    const int RY = TSY + 2 * H;
+    const int gx = rx0 + lane;
+    const bool xin = gx >= 0 && gx < nx;
     const int yb = wv * BR;
-    const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
+    const bool xint = gx >= ix0 && gx < ix1;
     T bv[BR], xv[BR];
     bb = 0.0;
 #pragma unroll
@@ -722,7 +740,7 @@ struct BandTile {
       return bv[r] - k0_apply(cm, xv[r], cp, v.c0, v.c1);
     };
     T Zi[BR];
-    cheb(v, degree, H, x0, y0, val, E, Rl, Zi, gb, 0, [] {});
+    cheb(v, degree, H, rx0, ix0, ix1, y0, val, E, Rl, Zi, gb, 0, [] {});
     rz = rr = 0.0;
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
@@ -743,19 +761,21 @@ struct BandTile {
     }
   }
 
-  // Inputs of phase A on this wave's rows of the region (tile plus a 1-node halo).
+  // Inputs of phase A on this wave's rows of the region (tile plus a 1-node
+  // halo; at the grid's left edge the region starts at the edge).
   struct InA {
     T z[BRA], po[BRA], x[BRA];
   };
+  __device__ static int region_a(int ix0) { return ix0 > 0 ? ix0 - 1 : 0; }
   __device__ static void load_a(const ColView<T>& v, int t, const IterVecs<T>& I, InA& in) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
-    int x0, y0;
-    origin(v, t, x0, y0);
-    const int gx = x0 - 1 + lane;
-    const bool xin = lane < v.tsx + 2 && gx >= 0 && gx < nx;
-    const bool xint = lane >= 1 && lane <= v.tsx && gx < nx;
+    int tx, ix0, ix1, y0;
+    span(v, t, tx, ix0, ix1, y0);
+    const int gx = region_a(ix0) + lane;
+    const bool xin = gx <= ix1 && gx < nx;
+    const bool xint = gx >= ix0 && gx < ix1;
 #pragma unroll
     for (int r = 0; r < BRA; ++r) {
       const int ly = wv * BRA + r;
@@ -777,10 +797,10 @@ struct BandTile {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
-    int x0, y0;
-    origin(v, t, x0, y0);
-    const int gx = x0 - 1 + lane;
-    const bool xint = lane >= 1 && lane <= v.tsx && gx < nx;
+    int tx, ix0, ix1, y0;
+    span(v, t, tx, ix0, ix1, y0);
+    const int gx = region_a(ix0) + lane;
+    const bool xint = gx >= ix0 && gx < ix1;
     const int yb = wv * BRA;
     T pc[BRA];
 #pragma unroll
@@ -842,15 +862,15 @@ struct BandTile {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
-    int x0, y0;
-    origin(v, t, x0, y0);
-    const int gx = x0 + lane;
+    int tx, ix0, ix1, y0;
+    span(v, t, tx, ix0, ix1, y0);
+    const int gx = ix0 + lane;
     constexpr int rows = (TSY + NW - 1) / NW;
 #pragma unroll
     for (int r = 0; r < rows; ++r) {
       const int ly = wv * rows + r;
       const int gy = y0 + ly;
-      if (lane < v.tsx && gx < nx && ly < TSY && gy < nx) {
+      if (gx < ix1 && ly < TSY && gy < nx) {
         const unsigned o = (unsigned)(gy * nx + gx);
         if (zero) {
           v.x[o] = T(0);
@@ -871,10 +891,10 @@ struct BandTile {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int H = degree, nx = v.nx;
-    int x0, y0;
-    origin(v, t, x0, y0);
-    const int gx = x0 - H + lane;
-    const bool xin = lane < v.tsx + 2 * H && gx >= 0 && gx < nx;
+    int tx, ix0, ix1, y0;
+    span(v, t, tx, ix0, ix1, y0);
+    const int gx = region_x(v, tx, ix0, H) + lane;
+    const bool xin = gx >= 0 && gx < nx;
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const int ly = wv * BR + r;
@@ -895,8 +915,9 @@ struct BandTile {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int H = degree, nx = v.nx;
-    int x0, y0;
-    origin(v, t, x0, y0);
+    int tx, ix0, ix1, y0;
+    span(v, t, tx, ix0, ix1, y0);
+    const int rx0 = region_x(v, tx, ix0, H);
     const int yb = wv * BR;
     T* E = W0;
     T* Rl = W0 + kEx;
@@ -910,11 +931,11 @@ struct BandTile {
       return in.r[r] - I.alpha * k0_apply(cm, in.p[r], cp, v.c0, v.c1);
     };
     T Zi[BR];
-    cheb(v, degree, H, x0, y0, val, E, Rl, Zi, gb, eb, after0);
+    cheb(v, degree, H, rx0, ix0, ix1, y0, val, E, Rl, Zi, gb, eb, after0);
     before_out();
     rz = rr = 0.0;
-    const int gx = x0 - H + lane;
-    const bool xint = lane >= H && lane < H + v.tsx && gx < nx;
+    const int gx = rx0 + lane;
+    const bool xint = gx >= ix0 && gx < ix1;
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const int ly = wv * BR + r;
@@ -1057,7 +1078,8 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       v.chebA = A.chebA;
       v.chebB = A.chebB;
     }
-    v.tsx = (v.nx + v.ntx - 1) / v.ntx;
+    v.ta = 64 - band_halo(degree);
+    v.tsx = 64 - 2 * band_halo(degree);
     return v;
   };
   // column holding work index w

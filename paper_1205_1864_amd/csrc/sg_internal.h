@@ -38,16 +38,27 @@ constexpr int kBandRowsSmall = 64;
 inline int band_rows(int inner_precision, int) {
   return inner_precision == 32 ? kBandRowsOf<float> : kBandRowsOf<double>;
 }
+// Column widths of banded inner tiles: a tile's region is one wavefront (64
+// grid columns) wide and needs a halo of h = (degree - 1) + 1 columns (the
+// Chebyshev halo plus one node for q = K_0 p and for the residual of a warm
+// start; at least 2) on each side that is not the grid's edge. Inner tiles
+// have 64 - 2h interior columns; the first and the last tile of a band row
+// have their regions end at the grid's edge and take 64 - h; a grid at most
+// 64 columns wide is one tile.
+__host__ __device__ inline int band_halo(int degree) { return (degree - 1 > 1 ? degree - 1 : 1) + 1; }
+__host__ __device__ inline int band_ntx(int nx, int degree) {
+  const int h = band_halo(degree), a = 64 - h, w = 64 - 2 * h;
+  if (nx <= 64) return 1;
+  return 2 + (nx > 2 * a ? (nx - 2 * a + w - 1) / w : 0);
+}
+
 inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& ntiles) {
   if (tile == 16) {
     ntx = (nx + 15) / 16;
     ntiles = ntx * ntx;
     return;
   }
-  // one more node on each side for the residual of a warm start
-  const int h = (degree - 1 > 1 ? degree - 1 : 1) + 1;
-  const int wmax = 64 - 2 * h;
-  ntx = (nx + wmax - 1) / wmax;
+  ntx = band_ntx(nx, degree);
   ntiles = ntx * ((nx + rows - 1) / rows);
 }
 
