@@ -251,6 +251,7 @@ template <typename T, int TS, int NS>
 struct SquareTile {
   static constexpr int kThreads = kSquareGroup;
   static constexpr bool kParkedSums = false;  // tile sums through group_sum2
+  __device__ static int ntiles_a(const ColView<T>& v) { return v.ntiles; }  // phase A on the same tiles
   // phase A stores q = K_0 p and phase B reads it
   static constexpr int NI = (TS * TS + kThreads - 1) / kThreads;  // interior nodes per thread
   // elements of T in one group's LDS buffers (two buffers; phase A needs a 1-node halo)
@@ -761,6 +762,24 @@ struct BandTile {
     }
   }
 
+  // Phase A needs a one-node halo only, so it has tiles of its own: a
+  // wavefront of columns (62 interior ones, 63 at the grid's edges, where the
+  // region starts or ends at the edge) by the band's rows. Its p.q partials
+  // are per phase-A tile.
+  __device__ static int ntx_a(const ColView<T>& v) { return band_cols(v.nx, 1); }
+  __device__ static int ntiles_a(const ColView<T>& v) { return ntx_a(v) * ((v.nx + TSY - 1) / TSY); }
+  __device__ static void span_a(const ColView<T>& v, int t, int& ix0, int& ix1, int& y0) {
+    const int ntx = ntx_a(v), tx = t % ntx;
+    y0 = (t / ntx) * TSY;
+    if (ntx == 1) {
+      ix0 = 0;
+      ix1 = v.nx;
+      return;
+    }
+    ix0 = tx == 0 ? 0 : 63 + (tx - 1) * 62;
+    ix1 = tx == 0 ? 63 : (tx + 1 == ntx ? v.nx : ix0 + 62);
+  }
+
   // Inputs of phase A on this wave's rows of the region (tile plus a 1-node
   // halo; at the grid's left edge the region starts at the edge).
   struct InA {
@@ -771,8 +790,8 @@ struct BandTile {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
-    int tx, ix0, ix1, y0;
-    span(v, t, tx, ix0, ix1, y0);
+    int ix0, ix1, y0;
+    span_a(v, t, ix0, ix1, y0);
     const int gx = region_a(ix0) + lane;
     const bool xin = gx <= ix1 && gx < nx;
     const bool xint = gx >= ix0 && gx < ix1;
@@ -797,8 +816,8 @@ struct BandTile {
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_group<kThreads>();
     const int nx = v.nx;
-    int tx, ix0, ix1, y0;
-    span(v, t, tx, ix0, ix1, y0);
+    int ix0, ix1, y0;
+    span_a(v, t, ix0, ix1, y0);
     const int gx = region_a(ix0) + lane;
     const bool xint = gx >= ix0 && gx < ix1;
     const int yb = wv * BRA;
@@ -1115,14 +1134,16 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
   // the column starts from the contents of its x
   auto warm_of = [&](const ColView<T>& v) { return A.warm && Tile::warm_fits(v, degree); };
   // Fixed-order sums of up to five per-tile partial arrays of a column, one wave each.
+  // (bit w of pq_arrays: array w holds p.q partials, one per phase-A tile)
   auto col_sums = [&](const ColView<T>& v, const double* q0, const double* q1, const double* q2, const double* q3,
-                      const double* q4) {
+                      const double* q4, int pq_arrays) {
     __syncthreads();
     const int wv = threadIdx.x >> 6;
     const double* src = wv == 0 ? q0 : wv == 1 ? q1 : wv == 2 ? q2 : wv == 3 ? q3 : q4;
     if (wv < 5 && src) {
+      const int n = (pq_arrays >> wv) & 1 ? Tile::ntiles_a(v) : v.ntiles;
       double s = 0.0;
-      for (int t = threadIdx.x & 63; t < v.ntiles; t += 64) s += src[v.tbase + t];
+      for (int t = threadIdx.x & 63; t < n; t += 64) s += src[v.tbase + t];
       s = wave_sum(s);
       if ((threadIdx.x & 63) == 0) s4[wv] = s;
     }
@@ -1182,7 +1203,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       }
       const bool first = it == 0;
       col_sums(v, P(PART_BB), P(par ? PART_RR0 : PART_RR1), first ? nullptr : P(par ? PART_RZ0 : PART_RZ1),
-               first ? nullptr : P(par ? PART_RZ1 : PART_RZ0), first ? nullptr : P(par ? PART_PQ0 : PART_PQ1));
+               first ? nullptr : P(par ? PART_RZ1 : PART_RZ0), first ? nullptr : P(par ? PART_PQ0 : PART_PQ1), 1 << 4);
       const double bb = s4[0];
       const double rr = s4[1];
       IterVecs<T> I{};
@@ -1206,7 +1227,12 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         continue;
       }
       any_active = true;
-      Tile::run_a(v, t0 + grp, t1, G, I, W0, gb, tsums, P(par ? PART_PQ1 : PART_PQ0) + v.tbase);
+      {
+        // this block's phase-A tiles: the same share of the column as its tiles
+        const long nta = Tile::ntiles_a(v);
+        const int ta0 = (int)(t0 * nta / v.ntiles), ta1 = (int)(t1 * nta / v.ntiles);
+        Tile::run_a(v, ta0 + grp, ta1, G, I, W0, gb, tsums, P(par ? PART_PQ1 : PART_PQ0) + v.tbase);
+      }
       if (whole(v, t0, t1)) column_end_whole();
       else column_arrive(arr + c, (unsigned)(t1 - t0));
     }
@@ -1223,7 +1249,7 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
         aborted = true;
         break;
       }
-      col_sums(v, P(par ? PART_PQ1 : PART_PQ0), P(par ? PART_RZ0 : PART_RZ1), nullptr, nullptr, nullptr);
+      col_sums(v, P(par ? PART_PQ1 : PART_PQ0), P(par ? PART_RZ0 : PART_RZ1), nullptr, nullptr, nullptr, 1 << 0);
       const double pq = s4[0], gam = s4[1];
       if (!(pq > 0.0) || !isfinite(pq)) {
         // breakdown: keep the current iterate (phase A of this iteration applied the last update)

@@ -46,11 +46,13 @@ inline int band_rows(int inner_precision, int) {
 // have their regions end at the grid's edge and take 64 - h; a grid at most
 // 64 columns wide is one tile.
 __host__ __device__ inline int band_halo(int degree) { return (degree - 1 > 1 ? degree - 1 : 1) + 1; }
-__host__ __device__ inline int band_ntx(int nx, int degree) {
-  const int h = band_halo(degree), a = 64 - h, w = 64 - 2 * h;
+// Tiles across a grid row for regions of 64 columns with a halo of h columns.
+__host__ __device__ inline int band_cols(int nx, int h) {
+  const int a = 64 - h, w = 64 - 2 * h;
   if (nx <= 64) return 1;
   return 2 + (nx > 2 * a ? (nx - 2 * a + w - 1) / w : 0);
 }
+__host__ __device__ inline int band_ntx(int nx, int degree) { return band_cols(nx, band_halo(degree)); }
 
 inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& ntiles) {
   if (tile == 16) {
