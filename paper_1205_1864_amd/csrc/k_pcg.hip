@@ -667,29 +667,43 @@ struct BandTile {
       const int gy = y0 - H + yb + r;
       row_in[r] = gy >= 0 && gy < nx;
     }
+    // One row of a sweep from the old values of the rows below (cm), at (c0)
+    // and above (cp).
+    auto row = [&](int r, T cm, T c0, T cp, T ca, T cb) {
+      if (!row_in[r]) return;
+      const T vs = cm + cp;
+      const T col = vs + c0;
+      const T s8 = (from_prev(col) + from_next(col)) + vs;
+      // S - D^-1 K_0 W, with D^-1 K_0 W = W - s8 / 8
+      const T sn = S[r] - (c0 - w8 * s8);
+      S[r] = sn;
+      const T wn = ca * c0 + cb * sn;
+      W[r] = wn;
+      Zi[r] += wn;
+    };
+    static_assert(BR >= 3, "a band has inner rows");
     for (int j = 1; j < degree; ++j) {
-      T up, dn;
-      exchange(W, E, (eb + j) & 1, up, dn, gb);
+      // The band's edge rows go to the neighbouring waves and the inner rows
+      // are updated while they travel; the barrier and the reads of the
+      // neighbours' edges come before the edge rows only.
+      T* e = E + ((eb + j) & 1) * (NW * 2 * 64);
+      e[(wv * 2 + 0) * 64 + lane] = W[0];
+      e[(wv * 2 + 1) * 64 + lane] = W[BR - 1];
       const T ca_j = ld_uniform(A.chebA, j), cb_j = ld_uniform(A.chebB, j);
       const T ca = xin ? ca_j : T(0), cb = xin ? cb_j : T(0);
-      T cm = up;
+      const T w0 = W[0], w1 = W[1], wl = W[BR - 1], wl1 = W[BR - 2];
+      T cm = w0;
 #pragma unroll
-      for (int r = 0; r < BR; ++r) {
+      for (int r = 1; r + 1 < BR; ++r) {
         const T c0 = W[r];
-        if (row_in[r]) {
-          const T cp = r + 1 < BR ? W[r + 1] : dn;
-          const T vs = cm + cp;
-          const T col = vs + c0;
-          const T s8 = (from_prev(col) + from_next(col)) + vs;
-          // S - D^-1 K_0 W, with D^-1 K_0 W = W - s8 / 8
-          const T sn = S[r] - (c0 - w8 * s8);
-          S[r] = sn;
-          const T wn = ca * c0 + cb * sn;
-          W[r] = wn;
-          Zi[r] += wn;
-        }
+        row(r, cm, c0, W[r + 1], ca, cb);
         cm = c0;
       }
+      group_sync(gb);
+      const T up = wv > 0 ? e[((wv - 1) * 2 + 1) * 64 + lane] : T(0);
+      const T dn = wv + 1 < NW ? e[((wv + 1) * 2 + 0) * 64 + lane] : T(0);
+      row(0, up, w0, w1, ca, cb);
+      row(BR - 1, wl1, wl, dn, ca, cb);
     }
   }
 
