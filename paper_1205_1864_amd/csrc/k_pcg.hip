@@ -503,6 +503,10 @@ struct BandTile {
   // the next tile's inputs are loaded during the current one, except where two
   // copies of them do not fit the registers (bands taller than 64 rows)
   static constexpr bool kPrefetch = TSY <= 64;
+  // phase B takes the part of the next tile's region that overlaps the
+  // current one from the current tile's registers (load_b_next); measured
+  // faster in FP32 (one lane shuffle per value), not in FP64 (two)
+  static constexpr bool kReuseHalo = sizeof(T) == 4;
   static_assert(NW * BRA <= RB, "phase A rows exceed the bands");
   static_assert(TSY + 2 * (HMAX + 1) <= RB, "phase B needs the Chebyshev halo plus one row");
   // elements of T per group: the exchange area, then r of the region rows
@@ -941,6 +945,41 @@ struct BandTile {
     }
   }
 
+  // Inputs of tile tn when `in` holds those of tile tc: if tn's region lies
+  // s columns to the right of tc's in the same band rows, lanes l < 64 - s
+  // take tc's values from lane l + s (the same grid columns; r and p are not
+  // written in phase B) and only the last s lanes are loaded; otherwise every
+  // lane is loaded (s = 64).
+  __device__ static void load_b_next(const ColView<T>& v, int degree, int tc, int tn, const IterVecs<T>& I,
+                                     InB& in) {
+    int txc, ixc0, ixc1, yc0, txn, ixn0, ixn1, yn0;
+    span(v, tc, txc, ixc0, ixc1, yc0);
+    span(v, tn, txn, ixn0, ixn1, yn0);
+    const int H = degree;
+    const int rxn = region_x(v, txn, ixn0, H);
+    int sh = rxn - region_x(v, txc, ixc0, H);
+    if (yn0 != yc0 || sh <= 0 || sh > 64) sh = 64;
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_group<kThreads>();
+    const int nx = v.nx;
+    const int gx = rxn + lane;
+    const bool fresh = lane >= 64 - sh;
+    const bool xin = fresh && gx >= 0 && gx < nx;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const T rs = __shfl_down(in.r[r], sh & 63, 64), ps = __shfl_down(in.p[r], sh & 63, 64);
+      const int ly = wv * BR + r;
+      const int gy = yn0 - H + ly;
+      in.r[r] = fresh ? T(0) : rs;
+      in.p[r] = fresh ? T(0) : ps;
+      if (xin && ly < TSY + 2 * H && gy >= 0 && gy < nx) {
+        const unsigned o = (unsigned)(gy * nx + gx);
+        in.r[r] = I.ro[o];
+        in.p[r] = I.pn[o];
+      }
+    }
+  }
+
   template <typename AF, typename EF>
   __device__ static void compute_b(const ColView<T>& v, int degree, int t, const IterVecs<T>& I, const InB& in,
                                    T* W0, T* W1, GroupBarrier& gb, int eb, double& rz, double& rr, AF after0,
@@ -1012,7 +1051,13 @@ struct BandTile {
       // complete before this tile's results are stored (a tile start then
       // never waits for the stores of the tile before)
       compute_b(v, degree, t, I, cur, W0, W1, gb, eb, rz, rr, [&] {
-        if (!kPrefetch && more) load_b(v, degree, t + step, I, cur);
+        if (!kPrefetch && more) {
+          if (kReuseHalo) {
+            load_b_next(v, degree, t, t + step, I, cur);
+          } else {
+            load_b(v, degree, t + step, I, cur);
+          }
+        }
       }, [&] {
         if (!kPrefetch) {  // unconditional, so every path into the next tile has them ready
           ready(cur.r);
