@@ -1390,7 +1390,11 @@ hipError_t launch_cfg(const PcgArgs<T>& args, const PcgCols<T>& cols, int max_bl
       }
     }
   }
-  long grid = per_block > 0 ? (nwork + per_block - 1) / per_block : (nwork + 2L * G - 1) / (2L * G);
+  // a launch with no more tile groups than compute units gives each block one
+  // group's worth (the column chain then waits on one tile per phase);
+  // otherwise two, so that a block's next tile can load during the current one
+  const long per_auto = nwork <= (long)ncu * G ? G : 2L * G;
+  long grid = per_block > 0 ? (nwork + per_block - 1) / per_block : (nwork + per_auto - 1) / per_auto;
   if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid < 1) grid = 1;
   for (int pass = 0; pass < 8 && per_block == 0; ++pass) {
