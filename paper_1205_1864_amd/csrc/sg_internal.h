@@ -17,10 +17,10 @@ constexpr int kPcgPartials = 7;  // per-tile partial-sum arrays of the inner sol
 constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 
 // Tiles of the inner PCG on an nx x nx grid. tile == 16: square 16 x 16 tiles.
-// Otherwise banded tiles of tsx x `rows` nodes, tsx = ceil(nx / ntx), sized
-// so that the tile plus its Chebyshev halo (degree - 1 nodes, at least one)
-// plus one more node spans at most one wavefront of 64 columns. Tiles are numbered row-major:
-// tile t covers columns (t % ntx) * tsx ... and rows (t / ntx) * rows ...
+// Otherwise banded tiles of `rows` node rows whose 64-column regions hold the
+// tile plus its Chebyshev halo (degree - 1 nodes, at least one) plus one more
+// node on each side that is not the grid's edge (band_ntx below). Tiles are
+// numbered row-major: tile t is column (t % ntx) of tiles and band row t / ntx.
 // Band heights: a taller band recomputes less of the halo. Bands are 128 rows
 // high in FP64 and 256 in FP32 (one band row at 256^2), worked by one group of
 // 16 waves per block without the next-tile prefetch, so that a wave's rows fit
