@@ -990,7 +990,6 @@ struct BandTile {
     int tx, ix0, ix1, y0;
     span(v, t, tx, ix0, ix1, y0);
     const int rx0 = region_x(v, tx, ix0, H);
-    const int yb = wv * BR;
     T* E = W0;
     T* Rl = W0 + kEx;
     // r - alpha q with q = K_0 p on the region, valid off its outermost ring
