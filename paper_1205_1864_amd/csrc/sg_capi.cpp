@@ -558,9 +558,21 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.rows = sgk::band_rows(sizeof(T) == 4 ? 32 : 64, degree);
   sgk::pcg_tiling(h->nx, degree, tile, a.rows, a.ntx, a.ntiles);
   if (tile != 16 && h->opts.tile == 0 && (long)ncols * a.ntiles < h->num_cu) {
-    // automatic choice, fewer tiles than compute units: shorter bands
-    a.rows = sgk::kBandRowsSmall;
-    sgk::pcg_tiling(h->nx, degree, tile, a.rows, a.ntx, a.ntiles);
+    // Automatic choice for a launch with fewer tiles than compute units:
+    // shorter bands spread it over more of them, but a block that then works
+    // two short tiles per phase sweeps more rows than one tall one. Take the
+    // height whose busiest block sweeps the fewest region rows (band rows plus
+    // the halo above and below) per iteration.
+    int ntx_s = 0, nt_s = 0;
+    sgk::pcg_tiling(h->nx, degree, tile, sgk::kBandRowsSmall, ntx_s, nt_s);
+    const int halo = 2 * sgk::band_halo(degree);
+    const long cost_tall = sgk::pcg_busiest_block((long)ncols * a.ntiles, h->num_cu) * (a.rows + halo);
+    const long cost_short = sgk::pcg_busiest_block((long)ncols * nt_s, h->num_cu) * (sgk::kBandRowsSmall + halo);
+    if (cost_short <= cost_tall) {
+      a.rows = sgk::kBandRowsSmall;
+      a.ntx = ntx_s;
+      a.ntiles = nt_s;
+    }
   }
   a.degree = degree;
   a.maxit = h->opts.inner_maxit;

@@ -63,6 +63,15 @@ inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& nt
   ntx = band_ntx(nx, degree);
   ntiles = ntx * ((nx + rows - 1) / rows);
 }
+// Tiles of the busiest block when nwork banded tiles (one 16-wave group per
+// block) take the inner solver's automatic grid on ncu compute units: one tile
+// per block when they fit, else two per block on at most ncu blocks, the
+// tiles split evenly over the grid.
+inline long pcg_busiest_block(long nwork, long ncu) {
+  if (nwork <= ncu) return 1;
+  const long grid = (nwork + 1) / 2 < ncu ? (nwork + 1) / 2 : ncu;
+  return (nwork + grid - 1) / grid;
+}
 
 // Chaos neighbour lists of the Hermite Galerkin matrices G_k (k >= 1): for
 // each chaos row a, the entries (k, b, g) with (G_k)_{ab} = g != 0 split into
