@@ -1438,8 +1438,19 @@ hipError_t dispatch_pcg(const PcgArgs<T>& args, const PcgCols<T>& cols, int tile
   if (tile != 16) {
     // banded tiles, one group of 16 waves per block, of the band height the
     // host tiled with: the precision's default or, for small launches, 64 rows
+    // (and 128 in FP32 when a single problem's launch has few tiles)
     constexpr int TSY = kBandRowsOf<T>;
     constexpr int TS = kBandRowsSmall;
+    if constexpr (sizeof(T) == 4 && !RAGGED) {
+      constexpr int TM = kBandRowsMid;
+      if (args.rows == TM) {
+        if (H > 15) return hipErrorInvalidValue;
+        if (H <= 3) return launch_cfg<T, BandTile<T, TM, 3, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+        if (H <= 7) return launch_cfg<T, BandTile<T, TM, 7, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+        if (H <= 11) return launch_cfg<T, BandTile<T, TM, 11, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+        return launch_cfg<T, BandTile<T, TM, 15, 16>, 1, RAGGED>(args, cols, max_blocks, s);
+      }
+    }
     if (H > 15) return hipErrorInvalidValue;
     if (args.rows == TSY) {
       if (H <= 3) return launch_cfg<T, BandTile<T, TSY, 3, 16>, 1, RAGGED>(args, cols, max_blocks, s);

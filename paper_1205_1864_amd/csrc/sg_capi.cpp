@@ -562,16 +562,21 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
     // shorter bands spread it over more of them, but a block that then works
     // two short tiles per phase sweeps more rows than one tall one. Take the
     // height whose busiest block sweeps the fewest region rows (band rows plus
-    // the halo above and below) per iteration.
-    int ntx_s = 0, nt_s = 0;
-    sgk::pcg_tiling(h->nx, degree, tile, sgk::kBandRowsSmall, ntx_s, nt_s);
+    // the halo above and below) per iteration; the shorter on a tie.
     const int halo = 2 * sgk::band_halo(degree);
-    const long cost_tall = sgk::pcg_busiest_block((long)ncols * a.ntiles, h->num_cu) * (a.rows + halo);
-    const long cost_short = sgk::pcg_busiest_block((long)ncols * nt_s, h->num_cu) * (sgk::kBandRowsSmall + halo);
-    if (cost_short <= cost_tall) {
-      a.rows = sgk::kBandRowsSmall;
-      a.ntx = ntx_s;
-      a.ntiles = nt_s;
+    long best = sgk::pcg_busiest_block((long)ncols * a.ntiles, h->num_cu) * (a.rows + halo);
+    const int shorter[2] = {sizeof(T) == 4 ? sgk::kBandRowsMid : 0, sgk::kBandRowsSmall};
+    for (int rows : shorter) {
+      if (rows <= 0 || rows >= a.rows) continue;
+      int ntx_s = 0, nt_s = 0;
+      sgk::pcg_tiling(h->nx, degree, tile, rows, ntx_s, nt_s);
+      const long cost = sgk::pcg_busiest_block((long)ncols * nt_s, h->num_cu) * (rows + halo);
+      if (cost <= best) {
+        best = cost;
+        a.rows = rows;
+        a.ntx = ntx_s;
+        a.ntiles = nt_s;
+      }
     }
   }
   a.degree = degree;

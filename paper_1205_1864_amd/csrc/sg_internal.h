@@ -32,9 +32,11 @@ constexpr int kBandRowsOf = sizeof(T) == 4 ? 256 : 128;
 // one node on each side leaves 32 interior columns of 64 lanes at degree 16.
 // Higher degrees take 16 x 16 tiles.
 constexpr int kBandMaxDegree = 16;
-// Band height of launches with few tiles: shorter bands give more tiles, so a
-// launch of a few columns still spreads over the compute units.
+// Band heights of launches with few tiles: shorter bands give more tiles, so a
+// launch of a few columns still spreads over the compute units. FP32 also has
+// the FP64 default height between its own and the shortest.
 constexpr int kBandRowsSmall = 64;
+constexpr int kBandRowsMid = 128;
 inline int band_rows(int inner_precision, int) {
   return inner_precision == 32 ? kBandRowsOf<float> : kBandRowsOf<double>;
 }

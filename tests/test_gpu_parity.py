@@ -145,6 +145,29 @@ def test_inner_solve_tall_grid(prec, tol, degree, tile):
         assert np.linalg.norm(X[c] - Xo[c]) <= tol * np.linalg.norm(Xo[c])
 
 
+@pytest.mark.parametrize("prec,tol", [(64, 1e-11), (32, 2e-5)])
+def test_inner_solve_small_launch_band_height(prec, tol):
+    """The automatic band height of a small launch on the benchmark's grid: ten
+    columns of 255 x 255 unknowns at degree 16 make 140 tiles of 128 rows or
+    280 of 64 rows; on 256 compute units the launch takes 128-row bands (one
+    tile per block) in both precisions, the FP32 kernel's middle height."""
+    b = _b()
+    prob, s = _sys(n_e=256, M=3, p=2)
+    assert prob.P == 10
+    print(f"inner small launch prec={prec}", flush=True)
+    solver = b.SGSolver(prob, b.Options(inner_precision=prec, cheb_degree=16, inner_maxit=5,
+                                        inner_rtol=0.0, tile=0))
+    B = random_block(10, prob.n, seed=256)
+    X, its = solver.sg_inner_solve(_dev(B))
+    X = X.cpu().numpy()
+    prec_o = krylov.make_chebyshev(s.K[0], prob.n_e, prob.theta0, 16)
+    st = krylov.InnerStats()
+    Xo = krylov.pcg_columns(s.K[0], B.T, prec_o, 0.0, 5, st).T
+    assert list(its) == list(st.iterations)
+    for c in range(10):
+        assert np.linalg.norm(X[c] - Xo[c]) <= tol * np.linalg.norm(Xo[c])
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 @pytest.mark.parametrize("degree", [16, 3])
 def test_inner_schedules_bitwise_equal(prec, degree, monkeypatch):

@@ -23,6 +23,7 @@ BUDGET = {
         r"pcg_kernelIdNS0_8BandTileIdLi128ELi15ELi16EEELi1ELb0E": (12, 64),
         r"pcg_kernelIfNS0_8BandTileIfLi256ELi15ELi16EEELi1ELb0E": (12, 64),
         r"pcg_kernelIdNS0_8BandTileIdLi64ELi15ELi16EEELi1ELb0E": (12, 64),
+        r"pcg_kernelIfNS0_8BandTileIfLi128ELi15ELi16EEELi1ELb0E": (12, 64),
     },
     "k_sgop.hip": {
         r"sgop_stage_kernel": (4, 32),
