@@ -555,30 +555,11 @@ int run_pcg(sg_ctx* h, const T* B, T* X, int ncols, int level_for_stats, std::ve
   a.Q = (T*)buf.Q;
   a.Z = (T*)buf.Z;
   a.sc = buf.sc;
-  a.rows = sgk::band_rows(sizeof(T) == 4 ? 32 : 64, degree);
+  const int prec = sizeof(T) == 4 ? 32 : 64;
+  // automatic tiles: the band height by the rule for launches with few tiles
+  a.rows = tile != 16 && h->opts.tile == 0 ? sgk::pcg_band_rows(h->nx, degree, prec, ncols, h->num_cu)
+                                            : sgk::band_rows(prec, degree);
   sgk::pcg_tiling(h->nx, degree, tile, a.rows, a.ntx, a.ntiles);
-  if (tile != 16 && h->opts.tile == 0 && (long)ncols * a.ntiles < h->num_cu) {
-    // Automatic choice for a launch with fewer tiles than compute units:
-    // shorter bands spread it over more of them, but a block that then works
-    // two short tiles per phase sweeps more rows than one tall one. Take the
-    // height whose busiest block sweeps the fewest region rows (band rows plus
-    // the halo above and below) per iteration; the shorter on a tie.
-    const int halo = 2 * sgk::band_halo(degree);
-    long best = sgk::pcg_busiest_block((long)ncols * a.ntiles, h->num_cu) * (a.rows + halo);
-    const int shorter[2] = {sizeof(T) == 4 ? sgk::kBandRowsMid : 0, sgk::kBandRowsSmall};
-    for (int rows : shorter) {
-      if (rows <= 0 || rows >= a.rows) continue;
-      int ntx_s = 0, nt_s = 0;
-      sgk::pcg_tiling(h->nx, degree, tile, rows, ntx_s, nt_s);
-      const long cost = sgk::pcg_busiest_block((long)ncols * nt_s, h->num_cu) * (rows + halo);
-      if (cost <= best) {
-        best = cost;
-        a.rows = rows;
-        a.ntx = ntx_s;
-        a.ntiles = nt_s;
-      }
-    }
-  }
   a.degree = degree;
   a.maxit = h->opts.inner_maxit;
   a.rtol = h->opts.inner_rtol > 0.0 ? h->opts.inner_rtol : 0.0;

@@ -74,6 +74,32 @@ inline long pcg_busiest_block(long nwork, long ncu) {
   const long grid = (nwork + 1) / 2 < ncu ? (nwork + 1) / 2 : ncu;
   return (nwork + grid - 1) / grid;
 }
+// Band height of a banded inner launch of ncols columns with automatic tiles.
+// A launch with fewer tiles of the precision's default height than compute
+// units may take shorter bands, which spread it over more of them; but a block
+// that then works two short tiles per phase sweeps more rows than one tall
+// one. The height taken is the one whose busiest block sweeps the fewest
+// region rows (band rows plus the halo above and below) per iteration, the
+// shorter on a tie; FP32 has the FP64 default height as a middle one.
+inline int pcg_band_rows(int nx, int degree, int inner_precision, int ncols, int ncu) {
+  const int def = band_rows(inner_precision, degree);
+  const long ntx = band_ntx(nx, degree);
+  auto tiles = [&](int rows) { return (long)ncols * ntx * ((nx + rows - 1) / rows); };
+  if (tiles(def) >= ncu) return def;
+  const int halo = 2 * band_halo(degree);
+  int best_rows = def;
+  long best = pcg_busiest_block(tiles(def), ncu) * (def + halo);
+  const int shorter[2] = {inner_precision == 32 ? kBandRowsMid : 0, kBandRowsSmall};
+  for (int rows : shorter) {
+    if (rows <= 0 || rows >= best_rows) continue;
+    const long cost = pcg_busiest_block(tiles(rows), ncu) * (rows + halo);
+    if (cost <= best) {
+      best = cost;
+      best_rows = rows;
+    }
+  }
+  return best_rows;
+}
 
 // Chaos neighbour lists of the Hermite Galerkin matrices G_k (k >= 1): for
 // each chaos row a, the entries (k, b, g) with (G_k)_{ab} = g != 0 split into
