@@ -24,8 +24,8 @@ constexpr int kRedBlocks = 1024; // blocks of the FP64 reduction kernels
 // Band heights: a taller band recomputes less of the halo. Bands are 128 rows
 // high in FP64 and 256 in FP32 (one band row at 256^2), worked by one group of
 // 16 waves per block without the next-tile prefetch, so that a wave's rows fit
-// its registers; launches with few tiles use 64-row bands (kBandRowsSmall,
-// with the prefetch).
+// its registers; launches with few tiles may take shorter bands (64 rows,
+// with the prefetch, or in FP32 128 rows; pcg_band_rows).
 template <typename T>
 constexpr int kBandRowsOf = sizeof(T) == 4 ? 256 : 128;
 // Highest Chebyshev degree served by banded tiles: the halo (degree - 1) plus
