@@ -43,7 +43,7 @@ CHEB_DEGREE = 16  # updates of the Chebyshev preconditioner of the inner PCG (fa
 # kernel changes.
 # pcg_kernel<double, BandTile<double, 128 | 64, 15, 16>, 1>, average over a solve's launches, by the
 # inner schedule's block cap (-1: whole columns per block where they fill the device; 0: automatic grid)
-PCG_TRAFFIC_BYTES = {-1: 14.17e9, 0: 14.05e9}
+PCG_TRAFFIC_BYTES = {-1: 14.30e9}
 # one SG matvec, by schedule (mv_variant, mv_param): the row-staged kernel with 10-row pieces,
 # and the y-marching kernel it replaced
 MATVEC_TRAFFIC_BYTES = {(4, 10): 354.2e6, (2, 2): 570.4e6, (2, 1): 543.0e6}

@@ -1173,9 +1173,17 @@ __global__ void __launch_bounds__(Tile::kThreads* G) pcg_kernel(const PcgArgs<T>
       return (int)(w / A.ntiles);
     }
   };
-  const long per_block = A.per_block > 0 ? A.per_block : (nwork + gridDim.x - 1) / gridDim.x;
-  const long w_begin = (long)blockIdx.x * per_block;
-  const long w_end = w_begin + per_block < nwork ? w_begin + per_block : nwork;
+  // this block's contiguous range of the work list: per_block items (whole
+  // columns), or an even share of the list (shares differ by at most one item,
+  // so no block works a tile more than the split needs)
+  long w_begin, w_end;
+  if (A.per_block > 0) {
+    w_begin = (long)blockIdx.x * A.per_block;
+    w_end = w_begin + A.per_block < nwork ? w_begin + A.per_block : nwork;
+  } else {
+    w_begin = (long)blockIdx.x * nwork / gridDim.x;
+    w_end = ((long)blockIdx.x + 1) * nwork / gridDim.x;
+  }
   if (w_begin >= w_end) return;
   const int c_first = column_of(w_begin), c_last = column_of(w_end - 1);
   // tiles of the column that fall in this block's range [w_begin, w_end)

@@ -68,7 +68,7 @@ inline void pcg_tiling(int nx, int degree, int tile, int rows, int& ntx, int& nt
 // Tiles of the busiest block when nwork banded tiles (one 16-wave group per
 // block) take the inner solver's automatic grid on ncu compute units: one tile
 // per block when they fit, else two per block on at most ncu blocks, the
-// tiles split evenly over the grid.
+// tiles split evenly over the grid (shares differ by at most one).
 inline long pcg_busiest_block(long nwork, long ncu) {
   if (nwork <= ncu) return 1;
   const long grid = (nwork + 1) / 2 < ncu ? (nwork + 1) / 2 : ncu;

@@ -74,10 +74,11 @@ def region_holds(nx, h, tiles):
 
 def busiest(nwork, ncu):
     """Tiles of the busiest block: one tile per block if they fit the compute
-    units, else two per block on at most ncu blocks, in contiguous chunks."""
+    units, else two per block on at most ncu blocks, the work list cut into
+    even contiguous shares."""
     grid = nwork if nwork <= ncu else min((nwork + 1) // 2, ncu)
-    chunk = math.ceil(nwork / grid)
-    sizes = [max(0, min(nwork, (b + 1) * chunk) - b * chunk) for b in range(grid)]
+    sizes = [(b + 1) * nwork // grid - b * nwork // grid for b in range(grid)]
+    assert sum(sizes) == nwork
     return max(sizes)
 
 
